@@ -1,0 +1,96 @@
+"""Krylov evaluation of phi_k(dt J) b (Sec. 2.2, eqs. (vm), (vm1), (vm2),
+(evv), (final1), (final)).
+
+Arnoldi: v_1 = b/||b||, J V_m = V_{m+1} Htilde_m, H_m = V_m^T J V_m.  The
+paper does not name its Gram-Schmidt variant; the oracle uses modified
+Gram-Schmidt (as in Saad 1992, which the paper cites).  Breakdown: if
+h_{j+1,j} <= eta ||J v_j|| the iteration stops with m_eff = j.
+
+phi_k(dt J) b ~= ||b|| V_m phi_k(dt H_m) e_1.  Eq. (final) writes
+phi_1(dt H_m) with H_m^{-1}, which fails for singular H_m (the paper notes J
+is singular with periodic boundaries); reading: phi_k(dt H_m) e_1 is taken
+from the exponential of the augmented matrix
+   [[dt H_m, e_1, 0], [0, 0, I_{k-1}], [0, 0, 0]]
+(Saad 1992, Sidje 1998), whose top-right block column equals
+phi_k(dt H_m) e_1 and which agrees with eq. (final) whenever H_m is
+invertible.  The small exponential is scipy.linalg.expm (the paper's
+Chebyshev rational approximation is one of several FP64-accurate choices).
+"""
+
+import numpy as np
+from scipy.linalg import expm
+
+
+def _norm(x):
+    # sqrt(sum x^2) without conjugation, so that complex-step perturbations pass through
+    return np.sqrt(np.sum(x * x))
+
+
+def arnoldi_mgs(matvec, b, m, eta=1e-12):
+    """Returns (V (K, m_eff+1), H (m_eff+1, m_eff), beta, m_eff, breakdown)."""
+    b = np.asarray(b).reshape(-1)
+    dt = np.result_type(b, np.float64)
+    K = b.size
+    beta = _norm(b)
+    V = np.zeros((K, m + 1), dtype=dt)
+    H = np.zeros((m + 1, m), dtype=dt)
+    if np.real(beta) == 0.0:
+        return V[:, :1], H[:1, :0], beta, 0, True
+    V[:, 0] = b / beta
+    for j in range(m):
+        w = np.asarray(matvec(V[:, j])).reshape(-1)
+        if np.iscomplexobj(w) and not np.iscomplexobj(V):
+            V = V.astype(np.complex128)
+            H = H.astype(np.complex128)
+        wn = _norm(w)
+        for i in range(j + 1):
+            H[i, j] = V[:, i] @ w
+            w = w - H[i, j] * V[:, i]
+        H[j + 1, j] = _norm(w)
+        if np.real(H[j + 1, j]) <= eta * np.real(wn):
+            return V[:, :j + 2], H[:j + 2, :j + 1], beta, j + 1, True
+        V[:, j + 1] = w / H[j + 1, j]
+    return V, H, beta, m, False
+
+
+def phi_augmented(A, k):
+    """phi_k(A) e_1 from expm of the augmented matrix (k >= 1); k = 0: expm(A) e_1."""
+    n = A.shape[0]
+    if k == 0:
+        return expm(A)[:, 0]
+    M = np.zeros((n + k, n + k), dtype=A.dtype)
+    M[:n, :n] = A
+    M[0, n] = 1.0
+    for j in range(1, k):
+        M[n + j - 1, n + j] = 1.0
+    return expm(M)[:n, n + k - 1]
+
+
+def arnoldi_phi(matvec, b, dt, k, m, eta=1e-12, return_info=False):
+    """phi_k(dt J) b (no dt prefactor) by the Krylov projection of dimension m."""
+    shape = np.shape(b)
+    V, H, beta, meff, brk = arnoldi_mgs(matvec, b, m, eta)
+    if meff == 0:
+        out = np.zeros(shape, dtype=V.dtype)
+    else:
+        y = phi_augmented(dt * H[:meff, :meff], k)
+        out = (beta * (V[:, :meff] @ y)).reshape(shape)
+    if return_info:
+        return out, dict(beta=beta, m_eff=meff, breakdown=brk,
+                         h_last=H[meff, meff - 1] if meff > 0 else 0.0)
+    return out
+
+
+def dense_phi(A, b, dt, k):
+    """phi_k(dt A) b for a dense A: expm of [[dt A, b, 0], [0, 0, I_{k-1}], [0, 0, 0]]."""
+    A = np.asarray(A)
+    b = np.asarray(b).reshape(-1)
+    n = A.shape[0]
+    if k == 0:
+        return expm(dt * A) @ b
+    M = np.zeros((n + k, n + k), dtype=np.result_type(A, b))
+    M[:n, :n] = dt * A
+    M[:n, n] = b
+    for j in range(1, k):
+        M[n + j - 1, n + j] = 1.0
+    return expm(M)[:n, n + k - 1]

@@ -1,0 +1,284 @@
+"""Pins of the oracle's quadrature, basis, fluxes and DG residual against
+closed forms, identities and special cases (Sec. 4)."""
+
+from math import factorial
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import quadrature, basis, euler
+from oracle.dg import DG
+
+GAMMA = 1.4
+
+
+# ------------------------------------------------------------- quadrature
+def _exact_simplex_monomial(e):
+    # int over the unit simplex of prod x_a^{e_a} = prod e_a! / (|e| + d)!
+    return np.prod([factorial(k) for k in e]) / factorial(sum(e) + len(e))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("q", [1, 2, 3, 4])
+def test_simplex_rule_exactness(dim, q):
+    pts, w = quadrature.simplex_rule(dim, q)
+    assert abs(w.sum() - 1.0 / factorial(dim)) < 1e-15
+    deg = 2 * q - 1
+    for tot in range(deg + 1):
+        for e in basis.exponents(dim, tot):
+            if sum(e) != tot:
+                continue
+            got = np.sum(w * np.prod(pts ** e[None, :], axis=1))
+            assert abs(got - _exact_simplex_monomial(e)) < 1e-15
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_face_rule_exactness(dim, q):
+    mu, w = quadrature.face_rule(dim, q)
+    assert abs(w.sum() - 1.0) < 1e-15
+    assert np.allclose(mu.sum(axis=1), 1.0)
+    # int over the unit (d-1)-simplex normalised to measure 1: (d-1)! prod e!/(|e|+d-1)!
+    for tot in range(2 * q):
+        for e in basis.exponents(dim - 1, tot) if dim == 3 else [(tot,)]:
+            e = np.array(e)
+            if e.sum() != tot:
+                continue
+            got = np.sum(w * np.prod(mu[:, 1:] ** e[None, :], axis=1))
+            want = factorial(dim - 1) * np.prod([factorial(k) for k in e]) / factorial(tot + dim - 1)
+            assert abs(got - want) < 1e-15
+
+
+# ------------------------------------------------------------------ basis
+def _meshes():
+    return [
+        ("sq3", W.periodic_square(3, 10.0), 45.0),
+        ("sq4j", W.periodic_square(4, 10.0, 0.15, 11), 45.0),
+        ("cube3", W.periodic_cube(3, 10.0), 45.0),
+        ("chan", W.channel_bump(8, 4, height=0.1, seed=5), 0.0),
+    ]
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
+@pytest.mark.parametrize("name,m,ang", _meshes()[:3])
+def test_basis_orthonormal(name, m, ang, p):
+    g = DG(m, p, "lf")
+    c = g._build(slice(0, g.nE))
+    M = np.einsum("eq,eqi,eqj->eij", c.W, c.psi, c.psi)
+    assert np.max(np.abs(M - np.eye(g.N))) < 1e-12
+    # psi_1 = |E|^{-1/2}
+    assert np.max(np.abs(c.psi[:, :, 0] * np.sqrt(g.mesh.vol)[:, None] - 1)) < 1e-13
+    # lower triangular in chi with s_i > 0 (eq. (basis))
+    assert np.all(np.abs(np.triu(g.C, 1)) == 0)
+    assert np.all(np.diagonal(g.C, axis1=1, axis2=2) > 0)
+
+
+def test_basis_monomial_order_invariance():
+    """The projected field does not depend on the order of the monomials."""
+    m = W.periodic_square(4, 10.0, 0.15, 7)
+    g = DG(m, 2, "lf")
+    f = lambda x: W.isentropic_vortex(x, center=(5.0, 5.0), period=m.period)
+    u = g.project(f)
+    U1 = g.evaluate(u)
+    g2 = DG(m, 2, "lf")
+    g2.exps = g2.exps[[0, 2, 1, 5, 4, 3]]
+    from oracle.mesh import affine_map
+    for s in g2._chunks():
+        x = affine_map(g2.mesh, g2.ref_pts, s)
+        Wt = g2._weights(s)
+        chi = basis.monomials(x, g2.mesh.centroid[s], g2.mesh.half_ext[s], g2.exps)
+        g2.C[s] = basis.mgs_coefficients(np.einsum("eq,eqa,eqb->eab", Wt, chi, chi))
+    g2._cache = None
+    U2 = g2.evaluate(g2.project(f))
+    assert np.max(np.abs(U1 - U2)) < 1e-12
+
+
+def test_mgs_equals_cholesky():
+    """MGS of Alg. 1 (reading: against orthonormal psi_j) = inverse Cholesky factor."""
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((3, 6, 6))
+    G = A @ np.transpose(A, (0, 2, 1)) + 6 * np.eye(6)
+    C = basis.mgs_coefficients(G)
+    L = np.linalg.cholesky(G)
+    assert np.allclose(C, np.linalg.inv(L), atol=1e-13)
+
+
+# ------------------------------------------------------------------ fluxes
+def _states(n, dim, seed=0):
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.5, 2.0, n)
+    vel = rng.uniform(-1.0, 1.0, (n, dim))
+    p = rng.uniform(0.5, 2.0, n)
+    U = W.prim_to_cons(np.concatenate([rho[:, None], vel, p[:, None]], axis=1))
+    nrm = rng.standard_normal((n, dim))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    return U, nrm
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("flux", [euler.lax_friedrichs, euler.roe])
+def test_flux_consistency_and_antisymmetry(dim, flux):
+    UL, n = _states(200, dim, 1)
+    UR, _ = _states(200, dim, 2)
+    assert np.allclose(flux(UL, UL, n, GAMMA), euler.normal_flux(UL, n, GAMMA), atol=1e-13)
+    assert np.allclose(flux(UL, UR, n, GAMMA), -flux(UR, UL, -n, GAMMA), atol=1e-13)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_roe_property(dim):
+    """Roe 1981: F(U_R).n - F(U_L).n = A(U~)(U_R - U_L) with A the exact flux
+    Jacobian at the Roe-averaged state (built here from the physical flux)."""
+    UL, n = _states(50, dim, 3)
+    UR, _ = _states(50, dim, 4)
+    rL, vL, pL = euler.primitives(UL, GAMMA)
+    rR, vR, pR = euler.primitives(UR, GAMMA)
+    HL, HR = (UL[:, -1] + pL) / rL, (UR[:, -1] + pR) / rR
+    sL, sR = np.sqrt(rL), np.sqrt(rR)
+    ut = (sL[:, None] * vL + sR[:, None] * vR) / (sL + sR)[:, None]
+    Ht = (sL * HL + sR * HR) / (sL + sR)
+    rt = sL * sR
+    Et = (Ht + (GAMMA - 1) * 0.5 * np.sum(ut * ut, 1)) / GAMMA
+    Ut = np.concatenate([rt[:, None], rt[:, None] * ut, (rt * Et)[:, None]], 1)
+    nv = dim + 2
+    A = np.zeros((50, nv, nv))
+    for j in range(nv):
+        e = np.zeros(nv)
+        e[j] = 1e-30
+        A[:, :, j] = np.imag(euler.normal_flux(Ut + 1j * e, n, GAMMA)) / 1e-30
+    lhs = euler.normal_flux(UR, n, GAMMA) - euler.normal_flux(UL, n, GAMMA)
+    rhs = np.einsum("eij,ej->ei", A, UR - UL)
+    assert np.allclose(lhs, rhs, atol=1e-12)
+
+
+def test_roe_supersonic_upwinding():
+    """All Roe wave speeds positive (negative) => F~ = F(U_L).n (F(U_R).n)."""
+    dim = 2
+    n = np.tile([1.0, 0.0], (20, 1))
+    rng = np.random.default_rng(5)
+    prim = lambda u: np.concatenate([rng.uniform(0.8, 1.2, (20, 1)), np.full((20, 1), u),
+                                     rng.uniform(-0.2, 0.2, (20, 1)), rng.uniform(0.8, 1.2, (20, 1))], 1)
+    UL, UR = W.prim_to_cons(prim(4.0)), W.prim_to_cons(prim(4.0))
+    assert np.allclose(euler.roe(UL, UR, n, GAMMA), euler.normal_flux(UL, n, GAMMA), atol=1e-12)
+    UL, UR = W.prim_to_cons(prim(-4.0)), W.prim_to_cons(prim(-4.0))
+    assert np.allclose(euler.roe(UL, UR, n, GAMMA), euler.normal_flux(UR, n, GAMMA), atol=1e-12)
+
+
+def test_ghost_states():
+    UL, n = _states(30, 2, 8)
+    G = euler.slip_wall_ghost(UL, n, GAMMA)
+    # mirror: same density, energy, tangential momentum; reversed normal momentum
+    assert np.allclose(G[:, 0], UL[:, 0]) and np.allclose(G[:, -1], UL[:, -1])
+    assert np.allclose(np.sum(G[:, 1:3] * n, 1), -np.sum(UL[:, 1:3] * n, 1))
+    # far field: the free stream is its own ghost
+    prim = W.freestream_prim(2, angle_deg=0.0)
+    Uinf = np.tile(W.prim_to_cons(prim), (30, 1))
+    assert np.allclose(euler.farfield_ghost(Uinf, n, prim, GAMMA), Uinf, atol=1e-13)
+
+
+def test_appendix_flux_jacobian():
+    """Appendix eq. (dfdu) at omega = 0 with a_1 = gamma E - a_0 (= H; the printed
+    'gamma e' is an erratum): grad(psi).dF/dU against the complex-step derivative."""
+    dim = 3
+    U, _ = _states(40, dim, 9)
+    g = np.random.default_rng(10).standard_normal((40, dim))
+    g1 = 1.4
+    rho, vel, p = euler.primitives(U, g1)
+    u, v, w = vel.T
+    E = U[:, -1] / rho
+    a0 = 0.5 * (g1 - 1) * (u * u + v * v + w * w)
+    a1 = g1 * E - a0
+    a2, a3 = g1 - 1, g1 - 2
+    px, py, pz = g.T
+    B1 = u * px + v * py + w * pz
+    B2 = 0.0
+    M = np.zeros((40, 5, 5))
+    M[:, 0] = np.stack([-B2 + 0 * u, px, py, pz, 0 * u], 1)
+    M[:, 1] = np.stack([a0 * px - B1 * u, B1 - B2 - a3 * u * px, u * py - a2 * v * px, u * pz - a2 * w * px, a2 * px], 1)
+    M[:, 2] = np.stack([a0 * py - B1 * v, v * px - a2 * u * py, B1 - B2 - a3 * v * py, v * pz - a2 * w * py, a2 * py], 1)
+    M[:, 3] = np.stack([a0 * pz - B1 * w, w * px - a2 * u * pz, w * py - a2 * v * pz, B1 - B2 - a3 * w * pz, a2 * pz], 1)
+    M[:, 4] = np.stack([(a0 - a1) * B1, a1 * px - a2 * B1 * u, a1 * py - a2 * v * B1, a1 * pz - a2 * B1 * w, g1 * B1 - B2], 1)
+    A = np.zeros((40, 5, 5))
+    for j in range(5):
+        e = np.zeros(5)
+        e[j] = 1e-30
+        A[:, :, j] = np.imag(np.einsum("ekd,ed->ek", euler.physical_flux(U + 1j * e, g1), g)) / 1e-30
+    assert np.allclose(A, M, atol=1e-12)
+
+
+# --------------------------------------------------------------- residual
+@pytest.mark.parametrize("p", [0, 1, 2])
+@pytest.mark.parametrize("flux", ["lf", "roe"])
+@pytest.mark.parametrize("name,m,ang", _meshes())
+def test_free_stream_preservation(name, m, ang, flux, p):
+    if name == "chan":
+        m = W.channel_bump(8, 4, height=0.0, seed=5)   # flat walls: the free stream is exact
+    prim = W.freestream_prim(m.dim, angle_deg=ang)
+    g = DG(m, p, flux, farfield_prim=prim)
+    u = g.project(lambda x: W.uniform_state(x, prim))
+    R = g.residual(u)
+    Fscale = np.max(np.abs(W.prim_to_cons(prim))) * np.max(g.mesh.area) / np.sqrt(np.min(g.mesh.vol))
+    assert np.max(np.abs(R)) < 1e-13 * Fscale
+
+
+@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("flux", ["lf", "roe"])
+@pytest.mark.parametrize("name,m,ang", _meshes()[:3])
+def test_discrete_conservation(name, m, ang, flux, p):
+    """Periodic domain: sum_E |E|^{1/2} R_{E,k,1} = 0 (the totals are invariant;
+    this is also why J is singular, Sec. 2.2)."""
+    g = DG(m, p, flux)
+    u = g.project(lambda x: W.isentropic_vortex(x, center=(5.0, 5.0), period=m.period))
+    u += W.perturbation(u.shape, 3, 1e-3)
+    R = g.residual(u)
+    tot = np.sum(np.sqrt(g.mesh.vol)[:, None] * R[:, :, 0], axis=0)
+    assert np.max(np.abs(tot)) < 1e-12 * np.sum(np.abs(np.sqrt(g.mesh.vol)[:, None] * R[:, :, 0]))
+
+
+@pytest.mark.parametrize("flux", ["lf", "roe"])
+def test_p0_is_finite_volume(flux):
+    """p = 0: R_E = -|E|^{-1/2} sum_f |f| F~(U_E, U_N, n_f) (first-order FV)."""
+    m = W.periodic_square(4, 10.0, 0.15, 21)
+    g = DG(m, 0, flux)
+    rng = np.random.default_rng(1)
+    Ucell = W.prim_to_cons(np.concatenate([rng.uniform(0.8, 1.2, (g.nE, 1)), rng.uniform(-.3, .3, (g.nE, 2)),
+                                           rng.uniform(0.8, 1.2, (g.nE, 1))], 1))
+    u = (Ucell * np.sqrt(g.mesh.vol)[:, None])[:, :, None]
+    R = g.residual(u)[:, :, 0]
+    fl = euler.lax_friedrichs if flux == "lf" else euler.roe
+    want = np.zeros_like(Ucell)
+    for f in range(3):
+        want -= g.mesh.area[:, f, None] * fl(Ucell, Ucell[g.mesh.nbr[:, f]], g.mesh.normal[:, f], GAMMA)
+    want /= np.sqrt(g.mesh.vol)[:, None]
+    assert np.allclose(R, want, atol=1e-13)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_residual_consistency_order(p):
+    """For the translating vortex U(x,t), R(Pi U) approximates Pi dU/dt; the
+    error ||R(Pi U) - Pi dU/dt||_2 falls at least like h^p."""
+    errs = []
+    for n in (16, 32, 64):
+        m = W.periodic_square(n, 10.0)
+        g = DG(m, p, "roe")
+        f = lambda x, t=0.0: W.isentropic_vortex(x, t=t, center=(5.0, 5.0), period=m.period)
+        u = g.project(f)
+        dt = 1e-5
+        dudt = (g.project(lambda x: f(x, dt)) - g.project(lambda x: f(x, -dt))) / (2 * dt)
+        errs.append(np.linalg.norm(g.residual(u) - dudt))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > p - 0.3) and rates[-1] > p - 0.1, (errs, rates)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_projection_convergence(p):
+    """L2 projection error of the smooth vortex converges at order p+1."""
+    errs = []
+    for n in (16, 32, 64):
+        m = W.periodic_square(n, 10.0)
+        g = DG(m, p, "lf")
+        f = lambda x: W.isentropic_vortex(x, center=(5.0, 5.0), period=m.period)
+        from oracle.diagnostics import l2_error
+        errs.append(l2_error(g, g.project(f), f))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > p + 1 - 0.1), (errs, rates)

@@ -1,0 +1,235 @@
+"""Pins of the oracle's JVPs, Krylov phi-functions and PCEXP stepper against
+closed forms, library routines on small systems and invariants (Sec. 2, 3, 4.4)."""
+
+from math import factorial
+
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+import workloads as W
+from oracle import krylov
+from oracle.dg import DG
+from oracle.derivatives import jvp_cs, jvp_fd, dense_jacobian
+from oracle.integrators import (pcexp_step, heun_step, ExactJacobian, DenseSplit,
+                                stable_dt, cfl_ramp, res_rho_norm)
+from oracle.diagnostics import conserved_totals
+
+
+def _tiny(flux="roe", p=1, n=3, jitter=0.1, dim=2, amp=1e-6, uinf=None):
+    if dim == 2:
+        m = W.periodic_square(n, 10.0, jitter, 17)
+    else:
+        m = W.periodic_cube(n, 10.0)
+    g = DG(m, p, flux)
+    u = g.project(lambda x: W.isentropic_vortex(x, center=(5.0, 5.0), period=m.period, uinf=uinf))
+    u = u + W.perturbation(u.shape, 101, amp)
+    return g, u
+
+
+# ------------------------------------------------------------------ JVP
+@pytest.mark.parametrize("flux", ["lf", "roe"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_complex_step_vs_central_fd(flux, dim):
+    # keep the state away from the kinks of |v.n| and max(): the vortex column
+    # has v.n = 0 on z-faces, so give it a z-velocity here
+    uinf = (0.42, 0.42, 0.3) if dim == 3 else None
+    g, u = _tiny(flux, 1, 3, dim=dim, amp=1e-3, uinf=uinf)
+    v = W.random_unit_vector(u.shape, 5)
+    Jv = jvp_cs(g, u, v)
+    h = 1e-5
+    cfd = (g.residual(u + h * v) - g.residual(u - h * v)) / (2 * h)
+    assert np.linalg.norm(Jv - cfd) < 1e-7 * np.linalg.norm(Jv)
+    # FD-JVP baseline agrees to first order
+    fd = jvp_fd(g, u, v)
+    assert np.linalg.norm(Jv - fd) < 1e-6 * np.linalg.norm(Jv)
+
+
+def test_jvp_linear_and_conservative():
+    g, u = _tiny("roe", 2, 3)
+    v1 = W.random_unit_vector(u.shape, 1)
+    v2 = W.random_unit_vector(u.shape, 2)
+    J = lambda v: jvp_cs(g, u, v)
+    lhs = J(0.3 * v1 - 2.0 * v2)
+    assert np.linalg.norm(lhs - (0.3 * J(v1) - 2.0 * J(v2))) < 1e-13 * np.linalg.norm(lhs)
+    tot = np.sum(np.sqrt(g.mesh.vol)[:, None] * J(v1)[:, :, 0], axis=0)
+    assert np.max(np.abs(tot)) < 1e-12 * np.linalg.norm(J(v1))
+
+
+def test_dense_jacobian_columns():
+    g, u = _tiny("lf", 1, 3)
+    J = dense_jacobian(g, u)
+    v = W.random_unit_vector(u.shape, 9)
+    assert np.allclose(J @ v.ravel(), jvp_cs(g, u, v).ravel(), atol=1e-12)
+    # periodic: J is singular (Sec. 2.2): the conserved totals are a left null space
+    ell = np.zeros(u.shape)
+    ell[:, 0, 0] = np.sqrt(g.mesh.vol)
+    assert np.linalg.norm(ell.ravel() @ J) < 1e-12 * np.linalg.norm(J)
+
+
+# ------------------------------------------------------------ phi closed forms
+def _phi_closed(k, z):
+    """phi_k(z) = (e^z - sum_{j<k} z^j/j!) / z^k, series near 0."""
+    z = np.asarray(z, dtype=np.float64)
+    out = np.empty_like(z)
+    small = np.abs(z) < 1e-2
+    zs = z[small]
+    out[small] = sum(zs ** j / factorial(j + k) for j in range(12))
+    zb = z[~small]
+    out[~small] = (np.exp(zb) - sum(zb ** j / factorial(j) for j in range(k))) / zb ** k
+    return out
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_phi_diagonal_closed_forms(k):
+    """Diagonal J: phi_1 = (e^z-1)/z (eq. (Phi1)), phi_2 = (e^z-1-z)/z^2 (eq.
+    (Phi2)), ...; with m >= the number of distinct eigenvalues the Krylov
+    result is exact (breakdown)."""
+    z = np.array([-40.0, -7.5, -1.0, -1e-3, 0.0, 1e-9, 0.5, 2.0])
+    rng = np.random.default_rng(0)
+    b = rng.uniform(0.5, 1.5, z.size)
+    dt = 0.7
+    got, info = krylov.arnoldi_phi(lambda v: (z / dt) * v, b, dt, k, 12, return_info=True)
+    want = _phi_closed(k, z) * b
+    assert np.all(np.abs(got - want) <= 1e-12 * np.abs(want) + 1e-14 * np.linalg.norm(b))
+    # 0 and 1e-9 are distinct but numerically close: breakdown may come one step late
+    assert info["breakdown"] and info["m_eff"] <= z.size + 1
+
+
+def test_phi_recursion():
+    """Eq. (s6): phi_{k+1}(z) = (phi_k(z) - 1/k!)/z."""
+    for z in (-3.0, -0.25, 0.8):
+        A = np.array([[z]])
+        ph = [krylov.phi_augmented(A, k)[0] for k in range(5)]
+        for k in range(1, 4):
+            assert abs(ph[k + 1] - (ph[k] - 1.0 / factorial(k)) / z) < 1e-14 * max(1, abs(ph[k + 1]))
+
+
+def test_krylov_vs_dense_random():
+    """Random 50x50 matrix with a prescribed (complex, left-half-plane) spectrum:
+    the Krylov phi_k(dt A) b with m = 50 equals the dense one."""
+    rng = np.random.default_rng(3)
+    n = 50
+    lam = np.concatenate([-rng.uniform(0, 5, 25) + 1j * rng.uniform(0, 8, 25)])
+    D = np.zeros((n, n))
+    for i, l in enumerate(lam):
+        D[2 * i:2 * i + 2, 2 * i:2 * i + 2] = [[l.real, l.imag], [-l.imag, l.real]]
+    Q = rng.standard_normal((n, n)) + 3 * np.eye(n)
+    A = Q @ D @ np.linalg.inv(Q)
+    b = rng.standard_normal(n)
+    for k in (0, 1, 2):
+        got = krylov.arnoldi_phi(lambda v: A @ v, b, 0.3, k, n)
+        want = krylov.dense_phi(A, b, 0.3, k)
+        assert np.linalg.norm(got - want) < 1e-11 * np.linalg.norm(want)
+    # dense phi_1 itself against its definition A^{-1}(e^{dtA} - I)/dt b  (eq. (Phi1))
+    want1 = np.linalg.solve(0.3 * A, (expm(0.3 * A) - np.eye(n)) @ b)
+    assert np.linalg.norm(krylov.dense_phi(A, b, 0.3, 1) - want1) < 1e-11 * np.linalg.norm(want1)
+
+
+@pytest.mark.parametrize("flux", ["lf", "roe"])
+def test_krylov_vs_dense_dg_jacobian(flux):
+    g, u = _tiny(flux, 1, 3)
+    J = dense_jacobian(g, u)
+    b = g.residual(u)
+    dt = stable_dt(g, u, 2.0)
+    got = krylov.arnoldi_phi(lambda v: jvp_cs(g, u, v.reshape(u.shape)), b, dt, 1, 60)
+    want = krylov.dense_phi(J, b.ravel(), dt, 1).reshape(u.shape)
+    assert np.linalg.norm(got - want) < 1e-12 * np.linalg.norm(want)
+
+
+def test_zero_vector_and_nilpotent_breakdown():
+    out, info = krylov.arnoldi_phi(lambda v: v, np.zeros(7), 1.0, 1, 5, return_info=True)
+    assert np.all(out == 0) and info["m_eff"] == 0
+    N = np.diag(np.ones(5), 1)     # nilpotent shift: Krylov space of e_6 has dimension 6
+    b = np.zeros(6)
+    b[-1] = 1.0
+    got, info = krylov.arnoldi_phi(lambda v: N @ v, b, 1.0, 1, 20, return_info=True)
+    assert info["breakdown"] and info["m_eff"] == 6
+    assert np.allclose(got, krylov.dense_phi(N, b, 1.0, 1), atol=1e-14)
+
+
+# ------------------------------------------------------------- integrators
+def test_pcexp_exact_on_linear_systems():
+    """Sec. 3.1: with no nonlinear part PCEXP is exact: u_{n+1} = e^{dt A} u_n."""
+    rng = np.random.default_rng(4)
+    n = 20
+    A = rng.standard_normal((n, n)) - 4 * np.eye(n)
+    u = rng.standard_normal(n)
+    op = DenseSplit(A, A)
+    got = pcexp_step(op, u, 0.4, n)
+    want = expm(0.4 * A) @ u
+    assert np.linalg.norm(got - want) < 1e-12 * np.linalg.norm(want)
+
+
+def test_pcexp_scalar_split_model_eq_grow():
+    """1x1 split operator A_jac = [b], A_res = [a + b] (dt = 1): the stepper's
+    growth factor is eq. (grow); EXP1's is eq. (exp1_grow)."""
+    for a in (-3.0, -0.7, 0.4):
+        for b in (-6.0, -1.3, 0.25, 1.5):
+            op = DenseSplit([[b]], [[a + b]])
+            r = pcexp_step(op, np.array([1.0]), 1.0, 1)[0]
+            printed = (a * (a - b) + np.exp(2 * b) * (a + b) * a + 2 * np.exp(b) * (b * b - a * a)) / (2 * b * b)
+            assert abs(r - printed) < 1e-12 * max(1, abs(printed))
+            r1 = pcexp_step(op, np.array([1.0]), 1.0, 1, scheme="exp1")[0]
+            assert abs(r1 - (a * (np.exp(b) - 1) + b * np.exp(b)) / b) < 1e-12 * max(1, abs(r1))
+
+
+def test_pcexp_zero_jacobian_is_heun():
+    """Eq. (rk2) / Sec. 3.1 item 2: J -> 0 gives Heun's method, on the DG residual."""
+    g, u = _tiny("roe", 1, 3)
+    dt = stable_dt(g, u, 0.5)
+    got = pcexp_step(ExactJacobian(g, "zero"), u, dt, 10)
+    want = heun_step(ExactJacobian(g), u, dt)
+    assert np.linalg.norm(got - want) < 1e-14 * np.linalg.norm(want)
+
+
+def test_pcexp_conserves_totals():
+    """Periodic: the conserved totals drift by rounding only over 10 steps."""
+    g, u = _tiny("lf", 1, 4)
+    op = ExactJacobian(g)
+    q0 = conserved_totals(g, u)
+    for _ in range(10):
+        u = pcexp_step(op, u, stable_dt(g, u, 5.0), 20)
+    assert np.max(np.abs(conserved_totals(g, u) - q0) / np.abs(q0).max()) < 1e-13
+
+
+def test_pcexp_temporal_order_two():
+    """Sec. 5.1 analogue: CFL = 0.1*2^n; error against the smallest CFL falls
+    like dt^2 (second order in time)."""
+    m = W.periodic_square(6, 10.0)
+    g = DG(m, 1, "lf")
+    u0 = g.project(lambda x: W.isentropic_vortex(x, center=(5.0, 5.0), period=m.period))
+    op = ExactJacobian(g)
+    dt0 = stable_dt(g, u0, 0.1)
+    T = 32 * dt0 * 2          # two steps of the largest CFL (3.2)
+    def run(cfl_mult):
+        u, dt = u0.copy(), dt0 * cfl_mult
+        for _ in range(int(round(T / dt))):
+            u = pcexp_step(op, u, dt, 20)
+        return u
+    ref = run(2)               # CFL 0.2 serves as the time-exact solution
+    errs = [np.linalg.norm(run(mult) - ref) for mult in (8, 16, 32)]
+    rates = np.log2(np.array(errs[1:]) / np.array(errs[:-1]))
+    assert np.all(rates > 1.7), (errs, rates)
+
+
+def test_dt_and_cfl_ramp():
+    """Eq. (x3d) on a uniform mesh at the free stream, and eq. (cfl)."""
+    m = W.periodic_square(4, 10.0)
+    g = DG(m, 2, "lf")
+    prim = W.freestream_prim(2)
+    u = g.project(lambda x: W.uniform_state(x, prim))
+    h_tri = 2 * 2 * (0.5 * 2.5 ** 2) / (2.5 * 2 + 2.5 * np.sqrt(2))   # 2d|E|/|dE|
+    speed = np.linalg.norm(prim[1:3]) + np.sqrt(1.4)
+    assert abs(stable_dt(g, u, 3.0) - 3.0 * h_tri / (5 * speed)) < 1e-14
+    # eq. (x2d) with d = 2: 2/h_2D = 3/h_3D - 1/dz for an extruded prism equals 4|E|/|dE|
+    dz = 0.37
+    area, perim = 0.5 * 2.5 ** 2, 2.5 * 2 + 2.5 * np.sqrt(2)
+    h3 = 2 * 3 * area * dz / (2 * area + perim * dz)
+    assert abs(2.0 / (3.0 / h3 - 1.0 / dz) - h_tri) < 1e-14
+    assert cfl_ramp(1, 10.0, 2, 1000.0) == 1.0
+    assert cfl_ramp(11, 10.0, 2, 1000.0) == 3.0
+    assert cfl_ramp(5, 0.05, 2, 1000.0) == 1000.0
+    assert abs(cfl_ramp(5, 0.5, 2, 1000.0) - 8.0) < 1e-12
+    R = g.residual(u + W.perturbation(u.shape, 1, 1e-3))
+    assert abs(res_rho_norm(g, R) - np.sqrt(np.sum(R[:, 0, :] ** 2)) / 100.0) < 1e-15
