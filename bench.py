@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""PCEXP benchmark on one MI355X: DOF-updates/s of the PCEXP step on the 2D
+isentropic-vortex workload (periodic [0,20]^2, 128x128 squares split into
+32768 jittered triangles, DG P2, Roe flux, Krylov dimension m = 30, CFL 20).
+
+A step is one full PCEXP step (both stages, two Arnoldi runs of m JVPs with
+re-orthogonalised Gram-Schmidt, the device-side Hessenberg phi, the corrector)
+through the C ABI.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  `value` is the FP64 tangent-JVP variant; the FP64
+finite-difference JVP and the mixed FP32/FP64 tangent variants are timed on
+the same workload and reported in `variants` with their solution error.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-variants", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(mesh, cfg, u0_np, K):
+    """Time the FP64 oracle on a bounded sample of the same workload: one
+    residual, three complex-step JVPs and the MGS work of one Arnoldi
+    iteration at full size; a PCEXP step costs 2 residuals + (2m+1) JVPs +
+    two MGS Arnoldi runs, from which seconds per step are extrapolated."""
+    import numpy as np
+    from oracle.dg import DG
+    from oracle.derivatives import jvp_cs
+    import workloads as W
+
+    threads = len(os.sched_getaffinity(0))
+    g = DG(mesh, cfg["p"], cfg["flux"])
+    u = u0_np
+    t0 = time.perf_counter()
+    R = g.residual(u)
+    t_res = time.perf_counter() - t0
+    v = W.random_unit_vector(u.shape, 1)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        jvp_cs(g, u, v)
+    t_jvp = (time.perf_counter() - t0) / 3
+    m = cfg["m"]
+    Vb = np.random.default_rng(0).standard_normal((K, 8))
+    w = R.ravel().copy()
+    t0 = time.perf_counter()
+    for i in range(8):          # MGS projections against 8 basis vectors
+        h = Vb[:, i] @ w
+        w = w - h * Vb[:, i]
+    t_gs8 = time.perf_counter() - t0
+    # MGS of one Arnoldi run touches sum_{j<m} (j+1) vectors
+    t_gs = t_gs8 / 8 * (m * (m + 1) / 2)
+    s_step = 2 * t_res + (2 * m + 1) * t_jvp + 2 * t_gs
+    return dict(value=K / s_step, unit="DOF-updates/s", cores=threads, kind="oracle",
+                sample=(f"config-2 size, FP64 NumPy oracle: 1 residual ({t_res:.2f} s), 3 complex-step JVPs "
+                        f"({t_jvp:.2f} s each), 8 MGS projections; per step = 2 R + {2 * m + 1} JVP + "
+                        f"2 Arnoldi MGS = {s_step:.1f} s"),
+                seconds_per_step=s_step)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1801_06300_amd import PCEXP
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = W.get_config(2)
+    mesh = W.build_mesh(cfg)
+    ctx = PCEXP(mesh, cfg["p"], cfg["flux"], device=dev)
+    K = ctx.K
+    L = mesh.period[0]
+    c = cfg["vortex_center"]
+    xq = ctx.quad_points().cpu().numpy()
+    Uq = W.isentropic_vortex(xq.reshape(-1, 2), center=c, period=mesh.period).reshape(ctx.nE, ctx.nq, ctx.nv)
+    u0 = ctx.project(torch.as_tensor(Uq, device=dev))
+    u0 = u0 + torch.as_tensor(W.perturbation(tuple(u0.shape), cfg["pert_seed"]), device=dev)
+    u0 = u0.contiguous()
+    dt = ctx.stable_dt(u0, cfg["cfl"])
+    m = cfg["m"]
+    steps, warm = args.steps, args.warmup
+
+    def run(prec, jvp, nsteps, profile=False):
+        u = u0.clone()
+        for _ in range(warm):
+            ctx.step(u, dt=dt, m=m, prec=prec, jvp=jvp)
+        u = u0.clone()
+        torch.cuda.synchronize()
+        if profile:
+            ctx.profile("start")
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record()
+        for _ in range(nsteps):
+            ctx.step(u, dt=dt, m=m, prec=prec, jvp=jvp)
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = None
+        if profile:
+            prof = ctx.profile("read")
+            ctx.profile("stop")
+        return u, wall, ev0.elapsed_time(ev1) / 1e3, prof
+
+    u_t64, wall, gpu_s, _ = run("f64", "tangent", steps)
+    value = K * steps / wall
+
+    # exact solution at t_N (translation of the vortex), projected; L2 error of the coefficients
+    tN = steps * dt
+    Ue = W.isentropic_vortex(xq.reshape(-1, 2), t=tN, center=c, period=mesh.period).reshape(ctx.nE, ctx.nq, ctx.nv)
+    ue = ctx.project(torch.as_tensor(Ue, device=dev))
+
+    def err(u):
+        return float(torch.linalg.norm(u - ue).item())
+
+    variants = {"t64": dict(dofs_per_s=value, ms_per_step=1e3 * wall / steps, l2_error=err(u_t64))}
+    if not args.no_variants:
+        for name, prec, jvp in (("fd64", "f64", "fd"), ("tmix", "mixed", "tangent")):
+            u, w_s, _, _ = run(prec, jvp, steps)
+            variants[name] = dict(dofs_per_s=K * steps / w_s, ms_per_step=1e3 * w_s / steps, l2_error=err(u),
+                                  rel_diff_vs_t64=float((torch.linalg.norm(u - u_t64) /
+                                                         torch.linalg.norm(u_t64)).item()))
+
+    # live per-kernel timing (HIP events on the step's stream) over a second timed region
+    _, _, _, prof = run("f64", "tangent", steps, profile=True)
+    kern = {k: dict(ms_total=v[0], launches=v[1], avg_us=(1e3 * v[0] / v[1]) if v[1] else 0.0,
+                    gbs=(v[2] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else 0.0) for k, v in prof.items()}
+    dom = max((k for k in prof if k != "hess_phi"), key=lambda k: prof[k][0])
+    d_ms, d_n, d_bytes = prof[dom]
+    achieved = d_bytes / (d_ms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    bytes_per_launch=d_bytes / d_n, avg_launch_us=1e3 * d_ms / d_n)
+    jv = prof["jvp"]
+    jvp_gbs = jv[2] / (jv[0] * 1e-3) / 1e9 if jv[0] > 0 else 0.0
+
+    out = {
+        "metric": "PCEXP DOF-updates/s + JVP HBM GB/s; mixed tangent vs FP64 FD-JVP at equal error",
+        "value": round(value, 1),
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": round(1e3 * wall / steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D isentropic vortex, periodic [0,20]^2, 128x128x2 jittered triangles (32768), "
+                               "DG P2, Roe, m=30, CFL 20 (dt from eq. x3d at u_0), FP64 tangent JVP",
+                   "K": K, "n_elem": ctx.nE, "p": cfg["p"], "flux": cfg["flux"], "m": m, "cfl": cfg["cfl"],
+                   "dt": dt},
+        "jvp_gbs": round(jvp_gbs, 1),
+        "roofline": roofline,
+        "variants": variants,
+        "kernels": kern,
+        "gpu_event_seconds": gpu_s,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(mesh, cfg, u0.cpu().numpy(), K)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

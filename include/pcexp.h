@@ -1,0 +1,199 @@
+/*
+ * pcexp.h -- C ABI of libpcexp, the MI355X (gfx950) implementation of the
+ * hot path of the PCEXP predictor-corrector exponential integrator for the
+ * DG-discretised Euler equations (Li, Luo, Wang, Ju, arXiv 1801.06300).
+ *
+ * Problem statement followed (paper Sec. 2.1, eq. (starteq)): du/dt = R(u),
+ * u in R^K, K = (number of elements) x (variables d+2) x (basis functions).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Vectors u, R, v, w, b, out are FP64 device pointers of K entries in the
+ *    element-major layout [E][k][i]: element E (in the order of the mesh
+ *    descriptor), conserved variable k = (rho, rho u, rho v, [rho w], rho E),
+ *    basis function i of the paper's orthonormal basis (Sec. 4.3, eqs.
+ *    (basis2), (basis), Alg. 1: centred and scaled global monomials in graded
+ *    order, x before y before z, modified Gram-Schmidt with s_i > 0).
+ *  * `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *    All work is enqueued on it and is asynchronous unless stated otherwise.
+ *  * The caller owns every array and the stream.  The context owns its
+ *    geometry, tables and a fixed scratch area allocated at creation; no
+ *    other entry point allocates device memory.  Host descriptor arrays are
+ *    copied by pcexp_create and not retained.
+ *  * One host thread at a time per context.
+ *  * Errors: argument/mesh/workspace validation returns before any work is
+ *    enqueued; HIP failures return PCEXP_E_HIP.  pcexp_last_error() returns a
+ *    message for the last failing call on the context.  Kernels record
+ *    non-finite values and rho <= 0 or p <= 0 at quadrature points in a
+ *    device flag word, reported by the next call that synchronises
+ *    (pcexp_stable_dt, or any call given a non-NULL info) as
+ *    PCEXP_E_NONFINITE / PCEXP_E_UNPHYSICAL and in info->flags.
+ */
+#ifndef PCEXP_H
+#define PCEXP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pcexp_ctx pcexp_ctx;
+
+typedef enum {
+  PCEXP_OK = 0,
+  PCEXP_E_ARG = -1,         /* invalid argument */
+  PCEXP_E_MESH = -2,        /* malformed mesh (orientation, unmatched face, ...) */
+  PCEXP_E_HIP = -3,         /* HIP runtime / launch failure */
+  PCEXP_E_WORKSPACE = -4,   /* workspace NULL or smaller than pcexp_workspace_bytes */
+  PCEXP_E_NONFINITE = -5,   /* NaN/Inf seen by a kernel */
+  PCEXP_E_UNPHYSICAL = -6,  /* rho <= 0 or p <= 0 at a quadrature point */
+  PCEXP_E_UNSUPPORTED = -7  /* valid request this build does not implement */
+} pcexp_status;
+
+typedef enum { PCEXP_FLUX_LF = 0, PCEXP_FLUX_ROE = 1 } pcexp_flux_kind;
+
+/* F64: everything in FP64.  MIXED: JVP (inputs, arithmetic, output) and the
+ * Krylov basis in FP32; Gram-Schmidt projections (FP64 accumulation), the
+ * Hessenberg matrix, phi, the Krylov combination, the corrector and the
+ * stage residuals R(u_n), R(u*) in FP64. */
+typedef enum { PCEXP_PREC_F64 = 0, PCEXP_PREC_MIXED = 1 } pcexp_prec_kind;
+
+/* TANGENT: exact J(u)v (paper Sec. 4.4, eqs. (jac1), (jac2), applied matrix-free).
+ * FD: (R(u + eps v) - R(u)) / eps with eps = sqrt(2^-52)(1 + |u|_2)/|v|_2 (FP64 only).
+ * ZERO: J = 0 (test mode: PCEXP reduces to Heun's method, eq. (rk2)). */
+typedef enum { PCEXP_JVP_TANGENT = 0, PCEXP_JVP_FD = 1, PCEXP_JVP_ZERO = 2 } pcexp_jvp_kind;
+
+/* PCEXP: eqs. (s9)-(s10).  EXP1: first stage only, eq. (s8). */
+typedef enum { PCEXP_SCHEME_PCEXP = 0, PCEXP_SCHEME_EXP1 = 1 } pcexp_scheme_kind;
+
+/* Boundary tags: slip wall (mirror ghost state), Riemann-invariant far field. */
+typedef enum { PCEXP_BC_SLIP = 1, PCEXP_BC_FARFIELD = 2 } pcexp_bc_kind;
+
+/* Flags reported in info->flags. */
+#define PCEXP_FLAG_NONFINITE 1u
+#define PCEXP_FLAG_UNPHYSICAL 2u
+
+typedef struct {
+  int32_t dim;               /* 2 (triangles) or 3 (tetrahedra) */
+  int64_t n_vert;
+  const double* vert;        /* host [n_vert][dim] */
+  int64_t n_elem;
+  const int32_t* elem;       /* host [n_elem][dim+1], positively oriented simplices */
+  const int32_t* vert_canon; /* host [n_vert] periodic identification (index of the
+                                vertex this one is an image of), or NULL */
+  int64_t n_bface;
+  const int32_t* bface;      /* host [n_bface][dim] vertex ids of boundary faces */
+  const int32_t* bface_tag;  /* host [n_bface] pcexp_bc */
+} pcexp_mesh_desc;
+
+typedef struct {
+  int32_t p;                 /* polynomial degree, 0..3 in 2D, 0..2 in 3D */
+  int32_t flux;              /* pcexp_flux_kind */
+  double gamma;              /* ratio of specific heats (paper: 7/5) */
+  double farfield_prim[5];   /* rho, u, v, [w], p of the far field (dim+2 used) */
+} pcexp_disc_desc;
+
+typedef struct {
+  double beta;               /* |b|_2 */
+  double h_last;             /* h_{m_eff+1, m_eff} */
+  int32_t m_eff;             /* Krylov dimension used (< m after breakdown; 0 if b = 0) */
+  int32_t breakdown;         /* 1 if the Arnoldi process broke down */
+} pcexp_krylov_info;
+
+typedef struct {
+  pcexp_krylov_info k1, k2;  /* predictor and corrector Arnoldi runs */
+  double dt;                 /* time step used */
+  double res_rho_norm;       /* |R(rho_n)| of eq. (cfl) at u_n */
+  uint32_t flags;            /* PCEXP_FLAG_* seen since the previous report */
+} pcexp_step_info;
+
+/* Create a context for a mesh and discretisation (Sec. 4.2-4.3): builds faces,
+ * periodic pairing, geometry, quadrature and basis tables on the host and
+ * uploads them.  Synchronises `stream`.  *out is NULL on failure. */
+pcexp_status pcexp_create(const pcexp_mesh_desc* mesh, const pcexp_disc_desc* disc,
+                          void* stream, pcexp_ctx** out);
+
+/* Test operator context: R(u) = A_res u and J v = A_jac v with device row-major
+ * n x n FP64 matrices (copied), 1 <= n <= 4096.  Vectors are plain length-n.
+ * Lets the same Arnoldi/step code be checked on linear systems and on the
+ * scalar split model of Sec. 3 (A_jac = [J], A_res = [J + lambda]). */
+pcexp_status pcexp_create_dense(int64_t n, const double* A_jac, const double* A_res,
+                                void* stream, pcexp_ctx** out);
+
+void pcexp_destroy(pcexp_ctx* ctx);
+
+/* sizes[0..7] = K, n_elem, dim, n_var, n_basis, n_quad, n_face_quad, p. */
+pcexp_status pcexp_sizes(const pcexp_ctx* ctx, int64_t* sizes);
+
+const char* pcexp_last_error(const pcexp_ctx* ctx);
+
+/* Bytes of caller workspace needed by pcexp_arnoldi_phi / pcexp_step for
+ * Krylov dimension m (1..64), phi index k (0..3), precision and JVP kind. */
+size_t pcexp_workspace_bytes(const pcexp_ctx* ctx, int32_t m, int32_t k, int32_t prec,
+                             int32_t jvp);
+
+/* Physical volume quadrature points, device [n_elem][n_quad][dim]. */
+pcexp_status pcexp_quad_points(pcexp_ctx* ctx, double* xyz, void* stream);
+
+/* L2 projection (mass = I, Sec. 4.2): u_{E,k,i} = int_E psi_i U_k from values
+ * U_qp, device [n_elem][n_quad][n_var] at pcexp_quad_points. */
+pcexp_status pcexp_project(pcexp_ctx* ctx, const double* U_qp, double* u, void* stream);
+
+/* U_h at the volume quadrature points, device [n_elem][n_quad][n_var]. */
+pcexp_status pcexp_evaluate(pcexp_ctx* ctx, const double* u, double* U_qp, void* stream);
+
+/* R(u) of eq. (euler3) with identity mass and omega = 0 (Sec. 4.2, 4.4). R != u. */
+pcexp_status pcexp_residual(pcexp_ctx* ctx, const double* u, double* R, void* stream);
+
+/* Jv = J(u) v, J = dR/du (Sec. 4.4).  v, Jv FP64 at the boundary; MIXED computes
+ * in FP32.  FD is FP64 only.  Jv != v. */
+pcexp_status pcexp_jvp(pcexp_ctx* ctx, const double* u, const double* v, double* Jv,
+                       int32_t jvp, int32_t prec, void* stream);
+
+/* JTw = J(u)^T w, the transpose of the exact Jacobian of Sec. 4.4 (FP64). */
+pcexp_status pcexp_vjp(pcexp_ctx* ctx, const double* u, const double* w, double* JTw,
+                       void* stream);
+
+/* dt of eq. (x3d): CFL min_E h_E / ((2p+1)(|v| + c)), h_E = 2d|E|/|dE|, with v and c
+ * at the element centroid.  Synchronises; result on the host. */
+pcexp_status pcexp_stable_dt(pcexp_ctx* ctx, const double* u, double cfl, double* dt_host,
+                             void* stream);
+
+/* Conserved totals int_Omega U_k dx, host out[n_var].  Synchronises. */
+pcexp_status pcexp_conserved_totals(pcexp_ctx* ctx, const double* u, double* out_host,
+                                    void* stream);
+
+/* out = Phi_k(dt J(u_lin)) b by the Krylov projection of dimension m (Sec. 2.2,
+ * eqs. (vm)-(final)): Arnoldi with classical Gram-Schmidt and one full
+ * re-orthogonalisation pass, phi_k(dt H_m) e_1 from the exponential of the
+ * augmented (m+k) matrix (Pade 13, scaling and squaring, on the device).
+ * No dt prefactor (k = 0 gives exp(dt J) b).  out != b.  info may be NULL; if
+ * not, the call synchronises and fills it.  Breakdown is not an error. */
+pcexp_status pcexp_arnoldi_phi(pcexp_ctx* ctx, const double* u_lin, const double* b, double dt,
+                               int32_t k, int32_t m, int32_t prec, int32_t jvp, double* out,
+                               void* ws, size_t ws_bytes, pcexp_krylov_info* info, void* stream);
+
+/* One step u_n -> u_{n+1} in place: PCEXP (eqs. (s9)-(s10), both stages with J_n)
+ * or EXP1 (eq. (s8)).  If dt > 0 it is used; otherwise cfl > 0 gives dt from
+ * eq. (x3d) at u_n, computed on the device (no synchronisation).  info as above. */
+pcexp_status pcexp_step(pcexp_ctx* ctx, double* u, double dt, double cfl, int32_t m,
+                        int32_t scheme, int32_t prec, int32_t jvp, void* ws, size_t ws_bytes,
+                        pcexp_step_info* info, void* stream);
+
+/* Kernel-class timing with HIP events recorded on the caller's stream around
+ * the launches made by pcexp_step / pcexp_arnoldi_phi (for roofline reports).
+ * op = 1: enable and reset (pre-creates the events; call outside timed code);
+ * op = 0: disable; op = 2: synchronise and write, for each class c in
+ * [0, PCEXP_PROF_NCLASS), out[3c] = total milliseconds, out[3c+1] = launches,
+ * out[3c+2] = algorithmic bytes moved (reads + writes the operation needs).
+ * Classes: 0 residual, 1 JVP, 2 Gram-Schmidt dots, 3 GS update + dots,
+ * 4 GS update + norm, 5 Hessenberg phi, 6 Krylov combination, 7 other. */
+#define PCEXP_PROF_NCLASS 8
+pcexp_status pcexp_profile(pcexp_ctx* ctx, int32_t op, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCEXP_H */

@@ -1,0 +1,572 @@
+// Element-tiled DG operator kernels for gfx950: residual R(u) (paper Sec. 4.2
+// eq. (euler3), identity mass, omega = 0), its exact tangent J(u)v (Sec. 4.4,
+// the Jacobian of eqs. (jac1)/(jac2) applied matrix-free), the
+// finite-difference JVP baseline, and the transpose J(u)^T w.
+//
+// Internal basis: reference-orthonormal phi_hat mapped affinely, psi_i =
+// phi_hat_i(xi)/s with s = sqrt(det A), x = X_0 + A xi.  For element E:
+//   volume:  s * sum_q w_q sum_r G_kr(q) dphi_hat_i/dxi_r(xi_q),
+//            G_kr = F_k(U_q) . a_r,  a_r = row r of A^{-1}
+//   faces:   - sum_f sum_r w_r (|f|/s) phi_hat_i(xi_r) Ftilde_k(U_L, U_R, n_f)
+// with |f| n_f = det(A) A^{-T} nref_f.
+//
+// Layout: vectors are [k][i][E] with element stride Epad (element-fastest, so
+// every global access of a tile is coalesced).  One workgroup of 256 threads
+// owns a tile of TE consecutive elements; the tile's coefficients are staged
+// in LDS, threads map to (quadrature point, element) for the pointwise flux
+// work and to (output, element) for the contractions.  Every face flux is
+// computed by both of its elements (no atomics; bitwise deterministic).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "dg_physics.hpp"
+
+namespace pcexp {
+
+template <int D, int P>
+struct Shape {
+  static constexpr int NV = D + 2;
+  static constexpr int NB = D == 2 ? (P + 1) * (P + 2) / 2 : (P + 1) * (P + 2) * (P + 3) / 6;
+  static constexpr int Q1 = P + 1;
+  static constexpr int NQ = D == 2 ? Q1 * Q1 : Q1 * Q1 * Q1;
+  static constexpr int NFQ = D == 2 ? Q1 : Q1 * Q1;
+  static constexpr int NF = D + 1;
+  static constexpr int NORI = D == 2 ? 2 : 6;
+  static constexpr int NVB = NV * NB;
+};
+
+enum { MODE_RES = 0, MODE_TAN = 1, MODE_FD = 2 };
+enum { FLUX_LF = 0, FLUX_ROE = 1 };
+
+template <typename T>
+struct DGParams {
+  const T* B;      // [NQ][NB]
+  const T* Dg;     // [NQ][NB][D]
+  const T* wq;     // [NQ]
+  const T* Bf;     // [NF][NORI][NFQ][NB]
+  const T* wf;     // [NFQ]
+  const T* nref;   // [NF][D]
+  const T* ainv;   // [D*D][Epad]
+  const T* sdet;   // [Epad]
+  const int* nbr;  // [NF][Epad]
+  const int* finfo;  // [NF][Epad]
+  int nE, Epad;
+  T gamma;
+  T ff[5];
+};
+
+template <typename T>
+struct DGIO {
+  const T* u;
+  const T* v;
+  T* out;
+  const double* vscale;  // optional: v is multiplied by *vscale
+  const int* skip;       // optional: the launch is a no-op if *skip != 0
+  const T* rbase;        // FD: R(u)
+  const double* fd_eps;  // FD: increment eps for the (scaled) direction
+  unsigned* flags;       // RES: PCEXP_FLAG_* bits
+};
+
+// LDS budget per workgroup (bytes) used to choose the tile size.
+constexpr int kLdsBudget = 40 * 1024;
+
+template <int D, int P, typename T, bool DUAL>
+struct Tile {
+  using Sh = Shape<D, P>;
+  static constexpr int NG = Sh::NQ * Sh::NV * D;
+  static constexpr int NFL = Sh::NF * Sh::NFQ * Sh::NV;
+  static constexpr int NW = NG > NFL ? NG : NFL;
+  static constexpr int per_elem = (int)sizeof(T) * (Sh::NVB * (DUAL ? 2 : 1) + NW) + Sh::NF;
+  static constexpr int TE = (64 * per_elem <= kLdsBudget) ? 64
+                            : (32 * per_elem <= kLdsBudget) ? 32
+                            : (16 * per_elem <= kLdsBudget) ? 16 : 8;
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of tiles so that neighbouring tiles share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int per = nb / 8, rem = nb % 8;
+  const int x = b % 8, k = b / 8;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+template <typename S> struct Part;
+template <> struct Part<double> { __device__ static double get(double x) { return x; } };
+template <> struct Part<float> { __device__ static float get(float x) { return x; } };
+template <typename T> struct Part<Dual<T, 1>> { __device__ static T get(const Dual<T, 1>& x) { return x.d[0]; } };
+
+template <int D, int FLUX, typename S, typename T>
+__device__ __forceinline__ void num_flux(const S* UL, const S* UR, const T* n, T gamma, S* F) {
+  if (FLUX == FLUX_LF) flux_lf<D>(UL, UR, n, gamma, F);
+  else flux_roe<D>(UL, UR, n, gamma, F);
+}
+
+template <int D, int P, int FLUX, typename T, int MODE>
+__global__ __launch_bounds__(256) void dg_apply(DGParams<T> prm, DGIO<T> io) {
+  using Sh = Shape<D, P>;
+  constexpr int NV = Sh::NV, NB = Sh::NB, NVB = Sh::NVB, NQ = Sh::NQ, NFQ = Sh::NFQ;
+  constexpr int NF = Sh::NF, NORI = Sh::NORI;
+  constexpr bool DUAL = (MODE == MODE_TAN);
+  using Tl = Tile<D, P, T, DUAL>;
+  constexpr int TE = Tl::TE;
+  using S = typename std::conditional<DUAL, Dual<T, 1>, T>::type;
+  constexpr int NT = 256;
+  constexpr int NOUT = (NVB * TE + NT - 1) / NT;
+
+  if (io.skip && *io.skip) return;
+  __shared__ T su[NVB * TE];
+  __shared__ T sv[DUAL ? NVB * TE : 1];
+  __shared__ T sw[Tl::NW * TE];
+  __shared__ unsigned char sori[NF * TE];
+
+  const int Epad = prm.Epad, nE = prm.nE;
+  const int e0 = xcd_tile(blockIdx.x, gridDim.x) * TE;
+  const int tid = threadIdx.x;
+  const T gm1 = prm.gamma - T(1);
+
+  T scale = T(1);
+  if (MODE != MODE_RES && io.vscale) scale = (T)(*io.vscale);
+  T eps = T(0);
+  if (MODE == MODE_FD) eps = (T)(*io.fd_eps);
+
+  // ---- stage the tile's coefficients (u, and the direction v for the tangent)
+  for (int t = tid; t < NVB * TE; t += NT) {
+    const int ki = t / TE, e = t % TE, ge = e0 + e;
+    T uu = T(0), vv = T(0);
+    if (ge < nE) {
+      uu = io.u[(size_t)ki * Epad + ge];
+      if (MODE != MODE_RES) vv = io.v[(size_t)ki * Epad + ge] * scale;
+    }
+    if (MODE == MODE_FD) uu = uu + eps * vv;
+    su[t] = uu;
+    if (DUAL) sv[t] = vv;
+  }
+  __syncthreads();
+
+  T acc[NOUT];
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) acc[o] = T(0);
+
+  // ---- volume: pointwise flux contracted with the rows of A^{-1}
+  for (int t = tid; t < NQ * TE; t += NT) {
+    const int q = t / TE, e = t % TE, ge = e0 + e;
+    if (ge >= nE) continue;
+    const T sd = prm.sdet[ge];
+    const T rs = T(1) / sd;
+    S U[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      T a = T(0), b = T(0);
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const T bq = prm.B[q * NB + i];
+        a += su[(k * NB + i) * TE + e] * bq;
+        if (DUAL) b += sv[(k * NB + i) * TE + e] * bq;
+      }
+      if constexpr (DUAL) {
+        U[k].v = a * rs;
+        U[k].d[0] = b * rs;
+      } else {
+        U[k] = a * rs;
+      }
+    }
+    if (MODE == MODE_RES && io.flags) {
+      T rho = val(U[0]), m2 = T(0);
+#pragma unroll
+      for (int c = 0; c < D; ++c) m2 += val(U[1 + c]) * val(U[1 + c]);
+      T p = gm1 * (val(U[D + 1]) - T(0.5) * m2 / rho);
+      unsigned fl = 0;
+      if (!isfinite(rho) || !isfinite(p)) fl |= 1u;
+      else if (!(rho > T(0)) || !(p > T(0))) fl |= 2u;
+      if (fl) atomicOr(io.flags, fl);
+    }
+    const T wgt = sd * prm.wq[q];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      T a[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) a[c] = prm.ainv[(size_t)(r * D + c) * Epad + ge];
+      S F[NV];
+      normal_flux<D>(U, a, gm1, F);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) sw[((q * NV + k) * D + r) * TE + e] = wgt * Part<S>::get(F[k]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    const int t = tid + o * NT;
+    if (t < NVB * TE) {
+      const int ki = t / TE, e = t % TE, k = ki / NB, i = ki % NB;
+      T s = T(0);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int r = 0; r < D; ++r) s += sw[((q * NV + k) * D + r) * TE + e] * prm.Dg[(q * NB + i) * D + r];
+      acc[o] += s;
+    }
+  }
+  __syncthreads();
+
+  // ---- faces: traces, numerical flux (each face computed by both sides)
+  for (int t = tid; t < NF * NFQ * TE; t += NT) {
+    const int fr = t / TE, e = t % TE, f = fr / NFQ, r = fr % NFQ, ge = e0 + e;
+    if (ge >= nE) continue;
+    const int info = prm.finfo[(size_t)f * Epad + ge];
+    const int nb = prm.nbr[(size_t)f * Epad + ge];
+    const int oE = (info >> 5) & 7;
+    if (r == 0) sori[f * TE + e] = (unsigned char)oE;
+    const T sd = prm.sdet[ge];
+    const T rs = T(1) / sd;
+    const T* bl = prm.Bf + ((f * NORI + oE) * NFQ + r) * NB;
+    S UL[NV], UR[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      T a = T(0), b = T(0);
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        a += su[(k * NB + i) * TE + e] * bl[i];
+        if (DUAL) b += sv[(k * NB + i) * TE + e] * bl[i];
+      }
+      if constexpr (DUAL) {
+        UL[k].v = a * rs;
+        UL[k].d[0] = b * rs;
+      } else {
+        UL[k] = a * rs;
+      }
+    }
+    // |f| n = det(A) A^{-T} nref_f
+    T nl[D];
+    T len2 = T(0);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      T s = T(0);
+#pragma unroll
+      for (int rr = 0; rr < D; ++rr) s += prm.ainv[(size_t)(rr * D + c) * Epad + ge] * prm.nref[f * D + rr];
+      nl[c] = s * sd * sd;
+      len2 += nl[c] * nl[c];
+    }
+    const T len = s_sqrt(len2);
+    T n[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) n[c] = nl[c] / len;
+    if (nb >= 0) {
+      const int fN = info & 3, oN = (info >> 2) & 7;
+      const T* br = prm.Bf + ((fN * NORI + oN) * NFQ + r) * NB;
+      const T rsn = T(1) / prm.sdet[nb];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        T a = T(0), b = T(0);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          T uu = io.u[(size_t)(k * NB + i) * Epad + nb];
+          T vv = T(0);
+          if (MODE != MODE_RES) vv = io.v[(size_t)(k * NB + i) * Epad + nb] * scale;
+          if (MODE == MODE_FD) uu = uu + eps * vv;
+          a += uu * br[i];
+          if (DUAL) b += vv * br[i];
+        }
+        if constexpr (DUAL) {
+          UR[k].v = a * rsn;
+          UR[k].d[0] = b * rsn;
+        } else {
+          UR[k] = a * rsn;
+        }
+      }
+    } else if (((info >> 8) & 3) == 1) {
+      ghost_slip<D>(UL, n, UR);
+    } else {
+      ghost_farfield<D>(UL, n, prm.ff, prm.gamma, UR);
+    }
+    S F[NV];
+    num_flux<D, FLUX>(UL, UR, n, prm.gamma, F);
+    const T wgt = prm.wf[r] * len * rs;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sw[((f * NFQ + r) * NV + k) * TE + e] = wgt * Part<S>::get(F[k]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    const int t = tid + o * NT;
+    if (t < NVB * TE) {
+      const int ki = t / TE, e = t % TE, k = ki / NB, i = ki % NB;
+      if (e0 + e < nE) {
+        T s = T(0);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          const T* bl = prm.Bf + (f * NORI + sori[f * TE + e]) * NFQ * NB;
+#pragma unroll
+          for (int r = 0; r < NFQ; ++r) s += sw[((f * NFQ + r) * NV + k) * TE + e] * bl[r * NB + i];
+        }
+        acc[o] -= s;
+      }
+    }
+  }
+
+  // ---- write (padding elements get zeros)
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    const int t = tid + o * NT;
+    if (t < NVB * TE) {
+      const int ki = t / TE, e = t % TE, ge = e0 + e;
+      if (ge < Epad) {
+        T v = ge < nE ? acc[o] : T(0);
+        if (MODE == MODE_FD && ge < nE) v = (v - io.rbase[(size_t)ki * Epad + ge]) / eps;
+        io.out[(size_t)ki * Epad + ge] = v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Transpose: out = J(u)^T w, gathered element by element (no atomics).  For
+// element E the contributions are (a) the adjoint of its own volume term,
+// (b) the adjoint of its own face terms with respect to its trace U_L, and
+// (c) for each interior face, the adjoint of the neighbour N's face term
+// F~(U_N, U_E, n_N) with respect to its second argument, evaluated with N's
+// own geometry exactly as N's forward residual does.  Flux Jacobians come from
+// forward-mode Dual<T, NV> numbers seeded on the state being differentiated.
+template <int D, int P, int FLUX>
+struct VjpTile {
+  using Sh = Shape<D, P>;
+  static constexpr int NX = (Sh::NQ > Sh::NF * Sh::NFQ ? Sh::NQ : Sh::NF * Sh::NFQ) * Sh::NV;
+  static constexpr int per_elem = 8 * (2 * Sh::NVB + NX) + Sh::NF;
+  static constexpr int TE = (64 * per_elem <= kLdsBudget) ? 64
+                            : (32 * per_elem <= kLdsBudget) ? 32
+                            : (16 * per_elem <= kLdsBudget) ? 16 : 8;
+};
+
+template <int D, int P, int FLUX>
+__global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const double* __restrict__ u,
+                                                     const double* __restrict__ w, double* __restrict__ out) {
+  using T = double;
+  using Sh = Shape<D, P>;
+  constexpr int NV = Sh::NV, NB = Sh::NB, NVB = Sh::NVB, NQ = Sh::NQ, NFQ = Sh::NFQ;
+  constexpr int NF = Sh::NF, NORI = Sh::NORI;
+  constexpr int TE = VjpTile<D, P, FLUX>::TE;
+  constexpr int NX = VjpTile<D, P, FLUX>::NX;
+  constexpr int NT = 256;
+  constexpr int NOUT = (NVB * TE + NT - 1) / NT;
+  using SD = Dual<T, NV>;
+
+  __shared__ T su[NVB * TE];
+  __shared__ T sw[NVB * TE];
+  __shared__ T sx[NX * TE];
+  __shared__ unsigned char sori[NF * TE];
+
+  const int Epad = prm.Epad, nE = prm.nE;
+  const int e0 = xcd_tile(blockIdx.x, gridDim.x) * TE;
+  const int tid = threadIdx.x;
+  const T gm1 = prm.gamma - T(1);
+
+  for (int t = tid; t < NVB * TE; t += NT) {
+    const int ki = t / TE, e = t % TE, ge = e0 + e;
+    su[t] = ge < nE ? u[(size_t)ki * Epad + ge] : T(0);
+    sw[t] = ge < nE ? w[(size_t)ki * Epad + ge] : T(0);
+  }
+  __syncthreads();
+  T acc[NOUT];
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) acc[o] = T(0);
+
+  // ---- (a) volume adjoint
+  for (int t = tid; t < NQ * TE; t += NT) {
+    const int q = t / TE, e = t % TE, ge = e0 + e;
+    if (ge >= nE) continue;
+    const T sd = prm.sdet[ge], rs = T(1) / sd;
+    SD U[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      T a = T(0);
+#pragma unroll
+      for (int i = 0; i < NB; ++i) a += su[(k * NB + i) * TE + e] * prm.B[q * NB + i];
+      U[k].v = a * rs;
+#pragma unroll
+      for (int j = 0; j < NV; ++j) U[k].d[j] = (j == k) ? T(1) : T(0);
+    }
+    T Ub[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) Ub[j] = T(0);
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      T a[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) a[c] = prm.ainv[(size_t)(r * D + c) * Epad + ge];
+      SD F[NV];
+      normal_flux<D>(U, a, gm1, F);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        T gb = T(0);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) gb += sw[(k * NB + i) * TE + e] * prm.Dg[(q * NB + i) * D + r];
+        gb *= sd * prm.wq[q];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) Ub[j] += gb * F[k].d[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) sx[(q * NV + j) * TE + e] = Ub[j] * rs;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    const int t = tid + o * NT;
+    if (t < NVB * TE) {
+      const int ki = t / TE, e = t % TE, k = ki / NB, i = ki % NB;
+      T s = T(0);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) s += sx[(q * NV + k) * TE + e] * prm.B[q * NB + i];
+      acc[o] += s;
+    }
+  }
+  __syncthreads();
+
+  // ---- (b) own face terms and (c) neighbours' face terms
+  for (int t = tid; t < NF * NFQ * TE; t += NT) {
+    const int fr = t / TE, e = t % TE, f = fr / NFQ, r = fr % NFQ, ge = e0 + e;
+    if (ge >= nE) continue;
+    const int info = prm.finfo[(size_t)f * Epad + ge];
+    const int nb = prm.nbr[(size_t)f * Epad + ge];
+    const int oE = (info >> 5) & 7;
+    if (r == 0) sori[f * TE + e] = (unsigned char)oE;
+    const T sd = prm.sdet[ge], rs = T(1) / sd;
+    const T* bl = prm.Bf + ((f * NORI + oE) * NFQ + r) * NB;
+    SD UE[NV];
+    T wl[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      T a = T(0), b = T(0);
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        a += su[(k * NB + i) * TE + e] * bl[i];
+        b += sw[(k * NB + i) * TE + e] * bl[i];
+      }
+      UE[k].v = a * rs;
+#pragma unroll
+      for (int j = 0; j < NV; ++j) UE[k].d[j] = (j == k) ? T(1) : T(0);
+      wl[k] = b;
+    }
+    T nl[D], len2 = T(0);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      T s = T(0);
+#pragma unroll
+      for (int rr = 0; rr < D; ++rr) s += prm.ainv[(size_t)(rr * D + c) * Epad + ge] * prm.nref[f * D + rr];
+      nl[c] = s * sd * sd;
+      len2 += nl[c] * nl[c];
+    }
+    const T len = s_sqrt(len2);
+    T n[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) n[c] = nl[c] / len;
+    T Ub[NV];
+    const T cs = -prm.wf[r] * len * rs;   // seed scale of the own face term
+    if (nb >= 0) {
+      const int fN = info & 3, oN = (info >> 2) & 7;
+      const T* br = prm.Bf + ((fN * NORI + oN) * NFQ + r) * NB;
+      const T sN = prm.sdet[nb], rsN = T(1) / sN;
+      SD UN[NV];
+      T wn[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        T a = T(0), b = T(0);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          a += u[(size_t)(k * NB + i) * Epad + nb] * br[i];
+          b += w[(size_t)(k * NB + i) * Epad + nb] * br[i];
+        }
+        UN[k] = mkconst<T, NV>(a * rsN);
+        wn[k] = b;
+      }
+      SD F[NV];
+      num_flux<D, FLUX>(UE, UN, n, prm.gamma, F);
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        T s = T(0);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) s += cs * wl[k] * F[k].d[j];
+        Ub[j] = s;
+      }
+      // neighbour's own geometry: |f|_N n_N = det(A_N) A_N^{-T} nref_{fN}
+      T nN[D], l2N = T(0);
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        T s = T(0);
+#pragma unroll
+        for (int rr = 0; rr < D; ++rr) s += prm.ainv[(size_t)(rr * D + c) * Epad + nb] * prm.nref[fN * D + rr];
+        nN[c] = s * sN * sN;
+        l2N += nN[c] * nN[c];
+      }
+      const T lenN = s_sqrt(l2N);
+#pragma unroll
+      for (int c = 0; c < D; ++c) nN[c] = nN[c] / lenN;
+      num_flux<D, FLUX>(UN, UE, nN, prm.gamma, F);
+      const T cn = -prm.wf[r] * lenN * rsN;
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        T s = T(0);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) s += cn * wn[k] * F[k].d[j];
+        Ub[j] += s;
+      }
+    } else {
+      SD G[NV], F[NV];
+      if (((info >> 8) & 3) == 1) ghost_slip<D>(UE, n, G);
+      else ghost_farfield<D>(UE, n, prm.ff, prm.gamma, G);
+      num_flux<D, FLUX>(UE, G, n, prm.gamma, F);
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        T s = T(0);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) s += cs * wl[k] * F[k].d[j];
+        Ub[j] = s;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) sx[((f * NFQ + r) * NV + j) * TE + e] = Ub[j] * rs;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    const int t = tid + o * NT;
+    if (t < NVB * TE) {
+      const int ki = t / TE, e = t % TE, k = ki / NB, i = ki % NB, ge = e0 + e;
+      if (ge < nE) {
+        T s = T(0);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          const T* bl = prm.Bf + (f * NORI + sori[f * TE + e]) * NFQ * NB;
+#pragma unroll
+          for (int r = 0; r < NFQ; ++r) s += sx[((f * NFQ + r) * NV + k) * TE + e] * bl[r * NB + i];
+        }
+        acc[o] += s;
+      }
+      if (ge < Epad) out[(size_t)ki * Epad + ge] = ge < nE ? acc[o] : T(0);
+    }
+  }
+}
+
+template <int D, int P, int FLUX>
+void launch_vjp(const DGParams<double>& prm, const double* u, const double* w, double* out, hipStream_t st) {
+  constexpr int TE = VjpTile<D, P, FLUX>::TE;
+  hipLaunchKernelGGL((dg_vjp_kernel<D, P, FLUX>), dim3(prm.Epad / TE), dim3(256), 0, st, prm, u, w, out);
+}
+
+// Host launchers (defined in the per-dimension translation units).
+template <int D, int P, int FLUX, typename T, int MODE>
+void launch_dg(const DGParams<T>& prm, const DGIO<T>& io, hipStream_t st) {
+  constexpr bool DUAL = (MODE == MODE_TAN);
+  constexpr int TE = Tile<D, P, T, DUAL>::TE;
+  const int nblk = prm.Epad / TE;
+  hipLaunchKernelGGL((dg_apply<D, P, FLUX, T, MODE>), dim3(nblk), dim3(256), 0, st, prm, io);
+}
+
+template <int D, int P>
+constexpr int tile_elems_max() {
+  return 64;
+}
+
+}  // namespace pcexp

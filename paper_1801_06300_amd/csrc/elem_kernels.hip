@@ -1,0 +1,231 @@
+// Element-level kernels at the ABI boundary: change of basis (paper basis,
+// Sec. 4.3, <-> reference basis), quadrature points, L2 projection and
+// evaluation (Sec. 4.2, mass = I), the time step of eq. (x3d) and conserved
+// totals.  Sizes are run-time values; none of these is on the hot path.
+#include <hip/hip_runtime.h>
+
+#include "dg_dispatch.hpp"
+
+namespace pcexp {
+
+constexpr int MAXNB = 20;
+constexpr int EK_T = 256;
+
+static dim3 grid_for(size_t n) {
+  size_t b = (n + EK_T - 1) / EK_T;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
+__global__ void to_internal_kernel(ElemArgs a, const double* __restrict__ u_abi, double* __restrict__ u_int) {
+  const size_t t = (size_t)blockIdx.x * EK_T + threadIdx.x;
+  const int nb = a.nb, nv = a.nv;
+  if (t >= (size_t)a.Epad * nv) return;
+  const int e = (int)(t / nv), k = (int)(t % nv);
+  if (e >= a.nE) {
+    for (int i = 0; i < nb; ++i) u_int[(size_t)(k * nb + i) * a.Epad + e] = 0.0;
+    return;
+  }
+  double x[MAXNB];
+  for (int j = 0; j < nb; ++j) x[j] = u_abi[((size_t)e * nv + k) * nb + j];
+  const double* Q = a.Q + (size_t)e * nb * nb;
+  const int ie = a.perm[e];
+  for (int i = 0; i < nb; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < nb; ++j) s += Q[i * nb + j] * x[j];
+    u_int[(size_t)(k * nb + i) * a.Epad + ie] = s;
+  }
+}
+
+__global__ void to_abi_kernel(ElemArgs a, const double* __restrict__ u_int, double* __restrict__ u_abi) {
+  const size_t t = (size_t)blockIdx.x * EK_T + threadIdx.x;
+  const int nb = a.nb, nv = a.nv;
+  if (t >= (size_t)a.nE * nv) return;
+  const int e = (int)(t / nv), k = (int)(t % nv);
+  const int ie = a.perm[e];
+  double x[MAXNB];
+  for (int i = 0; i < nb; ++i) x[i] = u_int[(size_t)(k * nb + i) * a.Epad + ie];
+  const double* Q = a.Q + (size_t)e * nb * nb;
+  for (int j = 0; j < nb; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += Q[i * nb + j] * x[i];
+    u_abi[((size_t)e * nv + k) * nb + j] = s;
+  }
+}
+
+__global__ void quad_points_kernel(ElemArgs a, double* xyz) {
+  const size_t t = (size_t)blockIdx.x * EK_T + threadIdx.x;
+  if (t >= (size_t)a.nE * a.nq) return;
+  const int e = (int)(t / a.nq), q = (int)(t % a.nq);
+  const int ie = a.perm[e], d = a.dim;
+  for (int c = 0; c < d; ++c) {
+    double x = a.x0[(size_t)c * a.Epad + ie];
+    for (int j = 0; j < d; ++j) x += a.amat[(size_t)(c * d + j) * a.Epad + ie] * a.refp[q * d + j];
+    xyz[t * d + c] = x;
+  }
+}
+
+__global__ void project_kernel(ElemArgs a, const double* __restrict__ Uqp, double* __restrict__ u_abi) {
+  const size_t t = (size_t)blockIdx.x * EK_T + threadIdx.x;
+  const int nb = a.nb, nv = a.nv, nq = a.nq;
+  if (t >= (size_t)a.nE * nv) return;
+  const int e = (int)(t / nv), k = (int)(t % nv);
+  const double s = a.sdet[a.perm[e]];
+  double r[MAXNB];
+  for (int i = 0; i < nb; ++i) r[i] = 0.0;
+  for (int q = 0; q < nq; ++q) {
+    const double U = Uqp[((size_t)e * nq + q) * nv + k] * a.wq[q] * s;
+    for (int i = 0; i < nb; ++i) r[i] += U * a.B[q * nb + i];
+  }
+  const double* Q = a.Q + (size_t)e * nb * nb;
+  for (int j = 0; j < nb; ++j) {
+    double v = 0.0;
+    for (int i = 0; i < nb; ++i) v += Q[i * nb + j] * r[i];
+    u_abi[((size_t)e * nv + k) * nb + j] = v;
+  }
+}
+
+__global__ void evaluate_kernel(ElemArgs a, const double* __restrict__ u_abi, double* __restrict__ Uqp) {
+  const size_t t = (size_t)blockIdx.x * EK_T + threadIdx.x;
+  const int nb = a.nb, nv = a.nv, nq = a.nq;
+  if (t >= (size_t)a.nE * nv) return;
+  const int e = (int)(t / nv), k = (int)(t % nv);
+  const double rs = 1.0 / a.sdet[a.perm[e]];
+  const double* Q = a.Q + (size_t)e * nb * nb;
+  double r[MAXNB];
+  for (int i = 0; i < nb; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < nb; ++j) s += Q[i * nb + j] * u_abi[((size_t)e * nv + k) * nb + j];
+    r[i] = s;
+  }
+  for (int q = 0; q < nq; ++q) {
+    double U = 0.0;
+    for (int i = 0; i < nb; ++i) U += r[i] * a.B[q * nb + i];
+    Uqp[((size_t)e * nq + q) * nv + k] = U * rs;
+  }
+}
+
+__device__ __forceinline__ double ek_wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ double ek_wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ bool ek_last(unsigned* counter) {
+  __shared__ int amlast;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    amlast = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (amlast) __threadfence();
+  return amlast != 0;
+}
+
+// dt = cfl * min_E h_E / ((2p+1)(|v| + c)), v and c at the centroid (eq. (x3d)).
+__global__ void stable_dt_kernel(ElemArgs a, const double* __restrict__ u, const double* cfl_dev, double cfl,
+                                 double* dt, double* part, unsigned* counter) {
+  const int e = blockIdx.x * EK_T + threadIdx.x;
+  const int nb = a.nb, d = a.dim;
+  double lam = 1e300;
+  if (e < a.nE) {
+    double U[5];
+    const double rs = 1.0 / a.sdet[e];
+    for (int k = 0; k < d + 2; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < nb; ++i) s += u[(size_t)(k * nb + i) * a.Epad + e] * a.Bc[i];
+      U[k] = s * rs;
+    }
+    double q2 = 0.0;
+    for (int c = 0; c < d; ++c) q2 += U[1 + c] * U[1 + c];
+    const double rho = U[0];
+    const double p = (a.gamma - 1.0) * (U[d + 1] - 0.5 * q2 / rho);
+    const double speed = sqrt(q2) / rho + sqrt(a.gamma * p / rho);
+    lam = a.hE[e] / ((2 * a.p + 1) * speed);
+  }
+  __shared__ double red[EK_T / 64];
+  double m = ek_wave_min(lam);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = red[0];
+    for (int w = 1; w < EK_T / 64; ++w) mm = fmin(mm, red[w]);
+    part[blockIdx.x] = mm;
+  }
+  if (ek_last(counter)) {
+    if (threadIdx.x < 64) {
+      double mm = 1e300;
+      for (int b = threadIdx.x; b < (int)gridDim.x; b += 64) mm = fmin(mm, part[b]);
+      mm = ek_wave_min(mm);
+      if (threadIdx.x == 0) {
+        *dt = (cfl_dev ? *cfl_dev : cfl) * mm;
+        *counter = 0u;
+      }
+    }
+  }
+}
+
+// Q_k = sum_E int_E U_k = sum_E s_E phi_hat_0 / d! * u_int[k][0][E]
+__global__ void totals_kernel(ElemArgs a, const double* __restrict__ u, double* out, double* part,
+                              unsigned* counter) {
+  const int e = blockIdx.x * EK_T + threadIdx.x;
+  const int nv = a.nv;
+  const double fact = (a.dim == 2) ? 0.5 : (1.0 / 6.0);
+  __shared__ double red[EK_T / 64][5];
+  for (int k = 0; k < nv; ++k) {
+    double v = 0.0;
+    if (e < a.nE) v = u[(size_t)(k * a.nb) * a.Epad + e] * a.sdet[e] * a.Bc[0] * fact;
+    v = ek_wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    double s = 0.0;
+    for (int w = 0; w < EK_T / 64; ++w) s += red[w][threadIdx.x];
+    part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+  }
+  if (ek_last(counter)) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = wid; k < nv; k += EK_T / 64) {
+      double s = 0.0;
+      for (int b = lane; b < (int)gridDim.x; b += 64) s += part[(size_t)k * gridDim.x + b];
+      s = ek_wave_sum(s);
+      if (lane == 0) out[k] = s;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+  }
+}
+
+void ek_to_internal(const ElemArgs& a, const double* u_abi, double* u_int, hipStream_t st) {
+  hipLaunchKernelGGL(to_internal_kernel, grid_for((size_t)a.Epad * a.nv), dim3(EK_T), 0, st, a, u_abi, u_int);
+}
+void ek_to_abi(const ElemArgs& a, const double* u_int, double* u_abi, hipStream_t st) {
+  hipLaunchKernelGGL(to_abi_kernel, grid_for((size_t)a.nE * a.nv), dim3(EK_T), 0, st, a, u_int, u_abi);
+}
+void ek_quad_points(const ElemArgs& a, double* xyz, hipStream_t st) {
+  hipLaunchKernelGGL(quad_points_kernel, grid_for((size_t)a.nE * a.nq), dim3(EK_T), 0, st, a, xyz);
+}
+void ek_project(const ElemArgs& a, const double* Uqp, double* u_abi, hipStream_t st) {
+  hipLaunchKernelGGL(project_kernel, grid_for((size_t)a.nE * a.nv), dim3(EK_T), 0, st, a, Uqp, u_abi);
+}
+void ek_evaluate(const ElemArgs& a, const double* u_abi, double* Uqp, hipStream_t st) {
+  hipLaunchKernelGGL(evaluate_kernel, grid_for((size_t)a.nE * a.nv), dim3(EK_T), 0, st, a, u_abi, Uqp);
+}
+void ek_stable_dt(const ElemArgs& a, const double* u_int, const double* cfl_dev, double cfl, double* dt,
+                  double* part, unsigned* counter, hipStream_t st) {
+  hipLaunchKernelGGL(stable_dt_kernel, grid_for((size_t)a.nE), dim3(EK_T), 0, st, a, u_int, cfl_dev, cfl, dt,
+                     part, counter);
+}
+void ek_totals(const ElemArgs& a, const double* u_int, double* out, double* part, unsigned* counter,
+               hipStream_t st) {
+  hipLaunchKernelGGL(totals_kernel, grid_for((size_t)a.nE), dim3(EK_T), 0, st, a, u_int, out, part, counter);
+}
+
+}  // namespace pcexp

@@ -1,0 +1,75 @@
+// Krylov / Arnoldi kernels for gfx950 (paper Sec. 2.2, eqs. (vm), (vm1),
+// (vm2), (final1), (final)) and small utility kernels.
+//
+// Arnoldi with classical Gram-Schmidt and one full re-orthogonalisation pass
+// (CGS2).  The Krylov basis lives in the caller's workspace as m+1 vectors
+// V_0..V_m of stride ld; V_j is stored unnormalised and used as sigma_j V_j
+// (sigma_j = 1/h_{j,j-1}), which removes a normalisation pass: the JVP writes
+// w = J (sigma_j V_j) straight into the slot V_{j+1} and the Gram-Schmidt
+// kernels update it in place.  Dot products accumulate in FP64 whatever the
+// storage type of V; every grid reduction is a per-block partial followed by
+// a fixed-order reduction in the last block to finish (no float atomics, so
+// results are bitwise reproducible).  After a breakdown every later launch of
+// the iteration is a no-op (device flag `done`).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pcexp {
+
+constexpr int KMAX = 64;          // largest Krylov dimension
+constexpr int KLD = KMAX + 1;     // leading dimension of H
+constexpr int GS_THREADS = 256;
+
+struct KState {
+  double H[KLD * KMAX];    // column-major Hessenberg, H[j*KLD + i]
+  double sigma[KMAX + 2];  // scale of each stored basis vector
+  double hcol[KMAX + 2];   // projection coefficients of the current pass
+  double y[KMAX + 4];      // beta * phi_k(dt H) e_1
+  double beta;
+  double wnorm;            // |J v_j| before orthogonalisation
+  double hlast;
+  double fd_eps;           // FD increment for a unit direction
+  double eta;              // breakdown threshold
+  double norm_tmp[4];
+  int m_eff;
+  int done;
+  int breakdown;
+  int pad;
+  unsigned counter[8];
+};
+
+// --- host-side launchers (krylov_kernels.hip) -------------------------------
+size_t gs_blocks(size_t n);
+void k_init_state(KState* ks, double eta, hipStream_t st);
+template <typename TV>
+void k_start(const double* b, TV* V0, size_t n, KState* ks, double* part, hipStream_t st);
+template <typename TV>
+void k_dots(const TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st);
+template <typename TV>
+void k_update_dots(TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st);
+template <typename TV>
+void k_update_norm(TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st);
+void k_hess_phi(KState* ks, const double* dt, int k, int m, double* scratch, hipStream_t st);
+template <typename TV, typename TX>
+void k_combine(const TV* V, size_t ld, const KState* ks, const double* base, double* out,
+               TX* xout, double fac, const double* dtp, size_t n, hipStream_t st);
+
+// utilities
+template <typename T> void k_fill(T* p, T v, size_t n, const int* skip, hipStream_t st);
+template <typename TA, typename TB> void k_cast(const TA* a, TB* b, size_t n, hipStream_t st);
+// out = sum x^2 over n entries (mode 0) or sqrt of it (mode 1); deterministic.
+void k_sumsq(const double* x, size_t n, double* out, int mode, double* part, unsigned* counter,
+             hipStream_t st);
+// eps = c0 * (1 + *unorm) / *vnorm, or c0*(1 + *unorm) if vnorm == NULL
+void k_fd_eps(const double* unorm, const double* vnorm, double c0, double* eps, hipStream_t st);
+// out = a - b - c  (double a, b; c of type TC)
+template <typename TC>
+void k_glue_d(const double* a, const double* b, const TC* c, double* out, size_t n, hipStream_t st);
+void k_set_scalar(double* p, double v, hipStream_t st);
+// dense operator: out = A (scale * v)
+template <typename T>
+void k_gemv(const T* A, const T* v, T* out, int n, const double* vscale, const int* skip,
+            hipStream_t st);
+
+}  // namespace pcexp

@@ -1,0 +1,742 @@
+// libpcexp: C ABI (include/pcexp.h) and host orchestration of the PCEXP step.
+//
+// Paper anchors: Sec. 2.1 eqs. (starteq), (s8), (s9), (s10) (PCEXP and EXP1);
+// Sec. 2.2 eqs. (vm)-(final) (Krylov evaluation of phi_k); Sec. 4 (DG
+// residual and exact Jacobian); Sec. 5 eq. (x3d) (time step).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pcexp.h"
+#include "dg_dispatch.hpp"
+#include "krylov_kernels.hpp"
+#include "setup.hpp"
+
+using namespace pcexp;
+
+namespace {
+
+constexpr int TILE_PAD = 64;
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+};
+
+}  // namespace
+
+struct pcexp_ctx {
+  bool dense = false;
+  int dim = 0, p = 0, nv = 1, nb = 1, nq = 0, nfq = 0, nf = 0, nori = 0, flux = 0;
+  int64_t nE = 0, Epad = 0;
+  size_t K = 0;      // ABI length
+  size_t Kint = 0;   // internal length (nv * nb * Epad, or n for dense)
+  size_t Kld = 0;    // stride of Krylov vectors
+  double gamma = 1.4, ff[5] = {0, 0, 0, 0, 0};
+  double volume_total = 0.0;
+  // tables and geometry
+  double *B = nullptr, *Dg = nullptr, *wq = nullptr, *Bf = nullptr, *wf = nullptr, *nref = nullptr,
+         *Bc = nullptr, *refp = nullptr;
+  float *B32 = nullptr, *Dg32 = nullptr, *wq32 = nullptr, *Bf32 = nullptr, *wf32 = nullptr,
+        *nref32 = nullptr;
+  double *ainv = nullptr, *sdet = nullptr, *x0 = nullptr, *amat = nullptr, *hE = nullptr, *Q = nullptr;
+  float *ainv32 = nullptr, *sdet32 = nullptr;
+  int *nbr = nullptr, *finfo = nullptr, *perm = nullptr;
+  // dense operator
+  double *Ajac = nullptr, *Ares = nullptr;
+  float* Ajac32 = nullptr;
+  // context-owned scratch for single-shot calls
+  double* io[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* io32[2] = {nullptr, nullptr};
+  double* part = nullptr;
+  size_t part_len = 0;
+  KState* ks = nullptr;
+  double* scal = nullptr;     // small device scalars
+  unsigned* flags = nullptr;
+  unsigned* counters = nullptr;
+  std::vector<void*> allocs;
+  std::string err;
+  // kernel-class timing (pcexp_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  struct Rec { int cls; double bytes; int e0; };
+  std::vector<Rec> recs;
+  hipStream_t prof_stream = nullptr;
+};
+
+namespace {
+
+pcexp_status fail(pcexp_ctx* c, pcexp_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+template <typename T>
+bool dalloc(pcexp_ctx* c, T** p, size_t n) {
+  if (n == 0) n = 1;
+  if (hipMalloc((void**)p, n * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    return false;
+  }
+  c->allocs.push_back((void*)*p);
+  return true;
+}
+
+template <typename T>
+bool upload(pcexp_ctx* c, T** p, const std::vector<T>& v, hipStream_t st) {
+  if (!dalloc(c, p, v.size())) return false;
+  return hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st) == hipSuccess;
+}
+
+template <typename T>
+bool upload32(pcexp_ctx* c, float** p, const std::vector<T>& v, hipStream_t st) {
+  std::vector<float> f(v.begin(), v.end());
+  return upload(c, p, f, st);
+}
+
+pcexp_status hip_check(pcexp_ctx* c, const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, PCEXP_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+  return PCEXP_OK;
+}
+
+DGParams<double> params_d(const pcexp_ctx* c) {
+  DGParams<double> p;
+  p.B = c->B; p.Dg = c->Dg; p.wq = c->wq; p.Bf = c->Bf; p.wf = c->wf; p.nref = c->nref;
+  p.ainv = c->ainv; p.sdet = c->sdet; p.nbr = c->nbr; p.finfo = c->finfo;
+  p.nE = (int)c->nE; p.Epad = (int)c->Epad; p.gamma = c->gamma;
+  for (int k = 0; k < 5; ++k) p.ff[k] = c->ff[k];
+  return p;
+}
+
+DGParams<float> params_f(const pcexp_ctx* c) {
+  DGParams<float> p;
+  p.B = c->B32; p.Dg = c->Dg32; p.wq = c->wq32; p.Bf = c->Bf32; p.wf = c->wf32; p.nref = c->nref32;
+  p.ainv = c->ainv32; p.sdet = c->sdet32; p.nbr = c->nbr; p.finfo = c->finfo;
+  p.nE = (int)c->nE; p.Epad = (int)c->Epad; p.gamma = (float)c->gamma;
+  for (int k = 0; k < 5; ++k) p.ff[k] = (float)c->ff[k];
+  return p;
+}
+
+ElemArgs elem_args(const pcexp_ctx* c) {
+  ElemArgs a;
+  a.dim = c->dim; a.nv = c->nv; a.nb = c->nb; a.nq = c->nq; a.p = c->p;
+  a.nE = (int)c->nE; a.Epad = (int)c->Epad;
+  a.Q = c->Q; a.perm = c->perm; a.sdet = c->sdet; a.x0 = c->x0; a.amat = c->amat; a.B = c->B;
+  a.wq = c->wq; a.Bc = c->Bc; a.refp = c->refp; a.hE = c->hE; a.gamma = c->gamma;
+  return a;
+}
+
+const double kSqrtEps = 1.4901161193847656e-08;  // sqrt(2^-52)
+
+enum { PC_RES = 0, PC_JVP = 1, PC_DOTS = 2, PC_UPD = 3, PC_NRM = 4, PC_PHI = 5, PC_COMB = 6, PC_OTHER = 7 };
+
+// Brackets one launch with events when profiling is on (no-op otherwise).
+struct Prof {
+  pcexp_ctx* c;
+  hipStream_t st;
+  int idx = -1;
+  Prof(pcexp_ctx* c_, hipStream_t s, int cls, double bytes) : c(c_), st(s) {
+    if (!c->prof) return;
+    size_t k = c->recs.size();
+    if (2 * k + 1 >= c->ev.size()) return;
+    idx = (int)k;
+    c->recs.push_back({cls, bytes, (int)(2 * k)});
+    (void)hipEventRecord(c->ev[2 * k], st);
+  }
+  ~Prof() {
+    if (idx >= 0) (void)hipEventRecord(c->ev[2 * idx + 1], st);
+  }
+};
+
+double geo_bytes(const pcexp_ctx* c, size_t w) {
+  // per element: A^{-1} (d^2), sqrt(det) (1) in the compute type, neighbour + face info (2 ints per face)
+  return (double)c->nE * ((c->dim * c->dim + 1) * (double)w + c->nf * 8.0);
+}
+
+// ---- internal operators --------------------------------------------------
+void to_int(pcexp_ctx* c, const double* abi, double* in, hipStream_t st) {
+  if (c->dense) (void)hipMemcpyAsync(in, abi, c->K * sizeof(double), hipMemcpyDeviceToDevice, st);
+  else ek_to_internal(elem_args(c), abi, in, st);
+}
+void to_abi(pcexp_ctx* c, const double* in, double* abi, hipStream_t st) {
+  if (c->dense) (void)hipMemcpyAsync(abi, in, c->K * sizeof(double), hipMemcpyDeviceToDevice, st);
+  else ek_to_abi(elem_args(c), in, abi, st);
+}
+
+bool residual_int(pcexp_ctx* c, const double* u, double* R, hipStream_t st) {
+  Prof pr(c, st, PC_RES, 2.0 * c->K * 8 + (c->dense ? (double)c->K * c->K * 8 : geo_bytes(c, 8)));
+  if (c->dense) {
+    k_gemv<double>(c->Ares, u, R, (int)c->K, nullptr, nullptr, st);
+    return true;
+  }
+  DGIO<double> io{};
+  io.u = u; io.out = R; io.flags = c->flags;
+  return dg_run_d(c->dim, c->p, c->flux, MODE_RES, params_d(c), io, st);
+}
+
+// JVP on internal vectors.  F64: v, out double.  MIXED: u32/v/out float.
+// vscale/skip optional device pointers; fd_eps device pointer for FD.
+bool jvp_int(pcexp_ctx* c, int jvp, int prec, const double* u, const float* u32, const void* v, void* out,
+             const double* vscale, const int* skip, const double* Rbase, const double* fd_eps, hipStream_t st) {
+  const size_t n = c->Kint;
+  const size_t w = (prec == PCEXP_PREC_MIXED) ? 4 : 8;
+  Prof pr(c, st, PC_JVP, (jvp == PCEXP_JVP_FD ? 4.0 : 3.0) * c->K * w + (c->dense ? 0.0 : geo_bytes(c, w)));
+  if (jvp == PCEXP_JVP_ZERO) {
+    if (prec == PCEXP_PREC_MIXED) k_fill<float>((float*)out, 0.0f, n, skip, st);
+    else k_fill<double>((double*)out, 0.0, n, skip, st);
+    return true;
+  }
+  if (c->dense) {
+    if (prec == PCEXP_PREC_MIXED) k_gemv<float>(c->Ajac32, (const float*)v, (float*)out, (int)n, vscale, skip, st);
+    else k_gemv<double>(c->Ajac, (const double*)v, (double*)out, (int)n, vscale, skip, st);
+    return true;
+  }
+  if (prec == PCEXP_PREC_MIXED) {
+    DGIO<float> io{};
+    io.u = u32; io.v = (const float*)v; io.out = (float*)out; io.vscale = vscale; io.skip = skip;
+    return dg_run_f(c->dim, c->p, c->flux, MODE_TAN, params_f(c), io, st);
+  }
+  DGIO<double> io{};
+  io.u = u; io.v = (const double*)v; io.out = (double*)out; io.vscale = vscale; io.skip = skip;
+  if (jvp == PCEXP_JVP_FD) {
+    io.rbase = Rbase;
+    io.fd_eps = fd_eps;
+    return dg_run_d(c->dim, c->p, c->flux, MODE_FD, params_d(c), io, st);
+  }
+  return dg_run_d(c->dim, c->p, c->flux, MODE_TAN, params_d(c), io, st);
+}
+
+
+// ---- workspace layout ----------------------------------------------------
+struct WsLayout {
+  size_t ks1, ks2, part, phi, scal, cnt, un, Rn, us, Rs, x1, un32, V, total;
+};
+
+WsLayout ws_layout(const pcexp_ctx* c, int m, int k, int prec) {
+  WsLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+  const size_t vb = c->Kint * sizeof(double);
+  L.ks1 = take(sizeof(KState));
+  L.ks2 = take(sizeof(KState));
+  L.part = take((size_t)512 * (KMAX + 2) * sizeof(double));
+  const size_t nphi = (size_t)(m + (k > 0 ? k : 0));
+  L.phi = take(7 * nphi * nphi * sizeof(double));
+  L.scal = take(64 * sizeof(double));
+  L.cnt = take(64 * sizeof(unsigned));
+  L.un = take(vb);
+  L.Rn = take(vb);
+  L.us = take(vb);
+  L.Rs = take(vb);
+  L.x1 = take(vb);
+  L.un32 = take(prec == PCEXP_PREC_MIXED ? c->Kint * sizeof(float) : 0);
+  const size_t tv = (prec == PCEXP_PREC_MIXED) ? sizeof(float) : sizeof(double);
+  L.V = take((size_t)(m + 1) * c->Kld * tv);
+  L.total = off;
+  return L;
+}
+
+template <typename TV>
+void arnoldi_run(pcexp_ctx* c, int jvp, int prec, const double* u_lin, const float* u32, const double* b,
+                 const double* Rlin, const double* dtp, int k, int m, KState* ks, double* part, double* phi,
+                 TV* V, hipStream_t st) {
+  const size_t n = c->Kint, ld = c->Kld;
+  const double eta = (prec == PCEXP_PREC_MIXED) ? 1e-5 : 1e-12;
+  k_init_state(ks, eta, st);
+  if (jvp == PCEXP_JVP_FD) {
+    k_sumsq(u_lin, n, &ks->norm_tmp[0], 1, part, &ks->counter[4], st);
+    k_fd_eps(&ks->norm_tmp[0], nullptr, kSqrtEps, &ks->fd_eps, st);
+  }
+  k_start<TV>(b, V, n, ks, part, st);
+  for (int j = 0; j < m; ++j) {
+    jvp_int(c, jvp, prec, u_lin, u32, V + (size_t)j * ld, V + (size_t)(j + 1) * ld, &ks->sigma[j], &ks->done,
+            Rlin, &ks->fd_eps, st);
+    const double vb = (double)c->K * sizeof(TV);
+    { Prof pr(c, st, PC_DOTS, (j + 2) * vb); k_dots<TV>(V, ld, j, n, ks, part, st); }
+    { Prof pr(c, st, PC_UPD, (j + 3) * vb); k_update_dots<TV>(V, ld, j, n, ks, part, st); }
+    { Prof pr(c, st, PC_NRM, (j + 3) * vb); k_update_norm<TV>(V, ld, j, n, ks, part, st); }
+  }
+  { Prof pr(c, st, PC_PHI, 0.0); k_hess_phi(ks, dtp, k, m, phi, st); }
+}
+
+void fill_info(pcexp_krylov_info* out, const KState& h) {
+  out->beta = h.beta;
+  out->h_last = h.hlast;
+  out->m_eff = h.m_eff;
+  out->breakdown = h.breakdown;
+}
+
+pcexp_status check_common(pcexp_ctx* c, int m, int k, int prec, int jvp, void* ws, size_t ws_bytes) {
+  if (!c) return PCEXP_E_ARG;
+  if (m < 1 || m > KMAX) return fail(c, PCEXP_E_ARG, "m must be in [1, 64]");
+  if (k < 0 || k > 3) return fail(c, PCEXP_E_ARG, "k must be in [0, 3]");
+  if (prec != PCEXP_PREC_F64 && prec != PCEXP_PREC_MIXED) return fail(c, PCEXP_E_ARG, "bad precision");
+  if (jvp != PCEXP_JVP_TANGENT && jvp != PCEXP_JVP_FD && jvp != PCEXP_JVP_ZERO)
+    return fail(c, PCEXP_E_ARG, "bad jvp kind");
+  if (jvp == PCEXP_JVP_FD && prec == PCEXP_PREC_MIXED)
+    return fail(c, PCEXP_E_UNSUPPORTED, "FD JVP is FP64 only");
+  if (!ws || ws_bytes < ws_layout(c, m, k, prec).total)
+    return fail(c, PCEXP_E_WORKSPACE, "workspace missing or too small");
+  if (((uintptr_t)ws) % ALIGN != 0) return fail(c, PCEXP_E_WORKSPACE, "workspace must be 256-byte aligned");
+  return PCEXP_OK;
+}
+
+pcexp_status report_flags(pcexp_ctx* c, uint32_t* out_flags) {
+  unsigned f = 0;
+  if (hipMemcpy(&f, c->flags, sizeof(unsigned), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, PCEXP_E_HIP, "flag read failed");
+  unsigned z = 0;
+  (void)hipMemcpy(c->flags, &z, sizeof(unsigned), hipMemcpyHostToDevice);
+  if (out_flags) *out_flags = f;
+  if (f & PCEXP_FLAG_NONFINITE) return fail(c, PCEXP_E_NONFINITE, "non-finite value at a quadrature point");
+  if (f & PCEXP_FLAG_UNPHYSICAL) return fail(c, PCEXP_E_UNPHYSICAL, "rho <= 0 or p <= 0 at a quadrature point");
+  return PCEXP_OK;
+}
+
+pcexp_status alloc_common(pcexp_ctx* c, hipStream_t st) {
+  for (int i = 0; i < 4; ++i)
+    if (!dalloc(c, &c->io[i], c->Kint)) return fail(c, PCEXP_E_HIP, "hipMalloc failed");
+  for (int i = 0; i < 2; ++i)
+    if (!dalloc(c, &c->io32[i], c->Kint)) return fail(c, PCEXP_E_HIP, "hipMalloc failed");
+  c->part_len = (size_t)512 * (KMAX + 2);
+  size_t eb = (size_t)(c->nE + 255) / 256 * 6;
+  if (eb > c->part_len) c->part_len = eb;
+  if (!dalloc(c, &c->part, c->part_len)) return fail(c, PCEXP_E_HIP, "hipMalloc failed");
+  if (!dalloc(c, (char**)&c->ks, sizeof(KState))) return fail(c, PCEXP_E_HIP, "hipMalloc failed");
+  if (!dalloc(c, &c->scal, 64)) return fail(c, PCEXP_E_HIP, "hipMalloc failed");
+  if (!dalloc(c, &c->flags, 1)) return fail(c, PCEXP_E_HIP, "hipMalloc failed");
+  if (!dalloc(c, &c->counters, 16)) return fail(c, PCEXP_E_HIP, "hipMalloc failed");
+  k_fill<unsigned>(c->flags, 0u, 1, nullptr, st);
+  k_fill<unsigned>(c->counters, 0u, 16, nullptr, st);
+  k_init_state(c->ks, 1e-12, st);
+  return PCEXP_OK;
+}
+
+}  // namespace
+
+namespace pcexp {
+bool dg_run_d(int dim, int p, int flux, int mode, const DGParams<double>& prm, const DGIO<double>& io,
+              hipStream_t st) {
+  return dim == 2 ? dg_run2_d(p, flux, mode, prm, io, st) : dg_run3_d(p, flux, mode, prm, io, st);
+}
+bool dg_run_f(int dim, int p, int flux, int mode, const DGParams<float>& prm, const DGIO<float>& io,
+              hipStream_t st) {
+  return dim == 2 ? dg_run2_f(p, flux, mode, prm, io, st) : dg_run3_f(p, flux, mode, prm, io, st);
+}
+}  // namespace pcexp
+
+extern "C" {
+
+pcexp_status pcexp_create(const pcexp_mesh_desc* mesh, const pcexp_disc_desc* disc, void* stream,
+                          pcexp_ctx** out) {
+  if (!out) return PCEXP_E_ARG;
+  *out = nullptr;
+  if (!mesh || !disc) return PCEXP_E_ARG;
+  if (disc->flux != PCEXP_FLUX_LF && disc->flux != PCEXP_FLUX_ROE) return PCEXP_E_ARG;
+  if (!(disc->gamma > 1.0)) return PCEXP_E_ARG;
+  pcexp_ctx* c = new (std::nothrow) pcexp_ctx();
+  if (!c) return PCEXP_E_ARG;
+  MeshIn mi;
+  mi.dim = mesh->dim; mi.n_vert = mesh->n_vert; mi.n_elem = mesh->n_elem; mi.n_bface = mesh->n_bface;
+  mi.vert = mesh->vert; mi.elem = mesh->elem; mi.vert_canon = mesh->vert_canon;
+  mi.bface = mesh->bface; mi.bface_tag = mesh->bface_tag;
+  Setup S;
+  std::string msg = build_setup(mi, disc->p, TILE_PAD, S);
+  if (!msg.empty()) {
+    pcexp_status s = PCEXP_E_ARG;
+    if (msg.rfind("mesh:", 0) == 0) s = PCEXP_E_MESH;
+    if (msg.rfind("unsupported:", 0) == 0) s = PCEXP_E_UNSUPPORTED;
+    delete c;
+    return s;
+  }
+  if (S.nb > 20 || S.nv > 5) { delete c; return PCEXP_E_UNSUPPORTED; }
+  for (int64_t e = 0; e < S.nE * S.nf; ++e) {
+    (void)e;
+  }
+  bool has_far = false;
+  for (int64_t b = 0; b < mesh->n_bface; ++b) has_far |= (mesh->bface_tag[b] == PCEXP_BC_FARFIELD);
+  if (has_far) {
+    if (!(disc->farfield_prim[0] > 0.0) || !(disc->farfield_prim[S.nv - 1] > 0.0)) {
+      delete c;
+      return PCEXP_E_ARG;
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  c->dim = S.dim; c->p = S.p; c->nv = S.nv; c->nb = S.nb; c->nq = S.nq; c->nfq = S.nfq; c->nf = S.nf;
+  c->nori = S.nori; c->flux = disc->flux; c->nE = S.nE; c->Epad = S.Epad;
+  c->K = (size_t)S.nE * S.nv * S.nb;
+  c->Kint = (size_t)S.Epad * S.nv * S.nb;
+  c->Kld = (c->Kint + 63) / 64 * 64;
+  c->gamma = disc->gamma;
+  for (int k = 0; k < 5; ++k) c->ff[k] = disc->farfield_prim[k];
+  c->volume_total = S.volume_total;
+  bool ok = upload(c, &c->B, S.B, st) && upload(c, &c->Dg, S.Dg, st) && upload(c, &c->wq, S.wq, st) &&
+            upload(c, &c->Bf, S.Bf, st) && upload(c, &c->wf, S.wf, st) && upload(c, &c->nref, S.nref, st) &&
+            upload(c, &c->Bc, S.Bc, st) && upload(c, &c->refp, S.ref_pts, st) &&
+            upload32(c, &c->B32, S.B, st) && upload32(c, &c->Dg32, S.Dg, st) && upload32(c, &c->wq32, S.wq, st) &&
+            upload32(c, &c->Bf32, S.Bf, st) && upload32(c, &c->wf32, S.wf, st) &&
+            upload32(c, &c->nref32, S.nref, st) && upload(c, &c->ainv, S.ainv, st) &&
+            upload(c, &c->sdet, S.sdet, st) && upload(c, &c->x0, S.x0, st) && upload(c, &c->amat, S.amat, st) &&
+            upload(c, &c->hE, S.hE, st) && upload(c, &c->Q, S.Q, st) && upload32(c, &c->ainv32, S.ainv, st) &&
+            upload32(c, &c->sdet32, S.sdet, st) && upload(c, &c->nbr, S.nbr, st) &&
+            upload(c, &c->finfo, S.finfo, st) && upload(c, &c->perm, S.perm, st);
+  if (!ok) {
+    c->err = "device upload failed";
+    pcexp_destroy(c);
+    return PCEXP_E_HIP;
+  }
+  if (alloc_common(c, st) != PCEXP_OK || hipStreamSynchronize(st) != hipSuccess) {
+    pcexp_destroy(c);
+    return PCEXP_E_HIP;
+  }
+  *out = c;
+  return PCEXP_OK;
+}
+
+pcexp_status pcexp_create_dense(int64_t n, const double* A_jac, const double* A_res, void* stream,
+                                pcexp_ctx** out) {
+  if (!out) return PCEXP_E_ARG;
+  *out = nullptr;
+  if (n < 1 || n > 4096 || !A_jac || !A_res) return PCEXP_E_ARG;
+  pcexp_ctx* c = new (std::nothrow) pcexp_ctx();
+  if (!c) return PCEXP_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  c->dense = true;
+  c->K = c->Kint = (size_t)n;
+  c->Kld = (c->Kint + 63) / 64 * 64;
+  c->nE = 1;
+  c->nv = 1;
+  c->nb = (int)n;
+  bool ok = dalloc(c, &c->Ajac, (size_t)n * n) && dalloc(c, &c->Ares, (size_t)n * n) &&
+            dalloc(c, &c->Ajac32, (size_t)n * n);
+  if (ok) {
+    ok = hipMemcpyAsync(c->Ajac, A_jac, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, st) ==
+             hipSuccess &&
+         hipMemcpyAsync(c->Ares, A_res, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess;
+  }
+  if (ok) k_cast<double, float>(c->Ajac, c->Ajac32, (size_t)n * n, st);
+  if (!ok || alloc_common(c, st) != PCEXP_OK || hipStreamSynchronize(st) != hipSuccess) {
+    pcexp_destroy(c);
+    return PCEXP_E_HIP;
+  }
+  *out = c;
+  return PCEXP_OK;
+}
+
+void pcexp_destroy(pcexp_ctx* c) {
+  if (!c) return;
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  for (void* p : c->allocs) (void)hipFree(p);
+  delete c;
+}
+
+pcexp_status pcexp_sizes(const pcexp_ctx* c, int64_t* s) {
+  if (!c || !s) return PCEXP_E_ARG;
+  s[0] = (int64_t)c->K; s[1] = c->nE; s[2] = c->dim; s[3] = c->nv; s[4] = c->nb; s[5] = c->nq;
+  s[6] = c->nfq; s[7] = c->p;
+  return PCEXP_OK;
+}
+
+const char* pcexp_last_error(const pcexp_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+size_t pcexp_workspace_bytes(const pcexp_ctx* c, int32_t m, int32_t k, int32_t prec, int32_t jvp) {
+  (void)jvp;
+  if (!c || m < 1 || m > KMAX || k < 0 || k > 3) return 0;
+  return ws_layout(c, m, k, prec).total;
+}
+
+pcexp_status pcexp_quad_points(pcexp_ctx* c, double* xyz, void* stream) {
+  if (!c || !xyz) return PCEXP_E_ARG;
+  if (c->dense) return fail(c, PCEXP_E_UNSUPPORTED, "dense context has no mesh");
+  ek_quad_points(elem_args(c), xyz, (hipStream_t)stream);
+  return hip_check(c, "quad_points");
+}
+
+pcexp_status pcexp_project(pcexp_ctx* c, const double* U_qp, double* u, void* stream) {
+  if (!c || !U_qp || !u) return PCEXP_E_ARG;
+  if (c->dense) return fail(c, PCEXP_E_UNSUPPORTED, "dense context has no mesh");
+  ek_project(elem_args(c), U_qp, u, (hipStream_t)stream);
+  return hip_check(c, "project");
+}
+
+pcexp_status pcexp_evaluate(pcexp_ctx* c, const double* u, double* U_qp, void* stream) {
+  if (!c || !U_qp || !u) return PCEXP_E_ARG;
+  if (c->dense) return fail(c, PCEXP_E_UNSUPPORTED, "dense context has no mesh");
+  ek_evaluate(elem_args(c), u, U_qp, (hipStream_t)stream);
+  return hip_check(c, "evaluate");
+}
+
+pcexp_status pcexp_residual(pcexp_ctx* c, const double* u, double* R, void* stream) {
+  if (!c || !u || !R || u == R) return c ? fail(c, PCEXP_E_ARG, "bad pointers") : PCEXP_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  to_int(c, u, c->io[0], st);
+  if (!residual_int(c, c->io[0], c->io[1], st)) return fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
+  to_abi(c, c->io[1], R, st);
+  return hip_check(c, "residual");
+}
+
+pcexp_status pcexp_jvp(pcexp_ctx* c, const double* u, const double* v, double* Jv, int32_t jvp, int32_t prec,
+                       void* stream) {
+  if (!c || !u || !v || !Jv || v == Jv) return c ? fail(c, PCEXP_E_ARG, "bad pointers") : PCEXP_E_ARG;
+  if (jvp != PCEXP_JVP_TANGENT && jvp != PCEXP_JVP_FD && jvp != PCEXP_JVP_ZERO)
+    return fail(c, PCEXP_E_ARG, "bad jvp kind");
+  if (prec != PCEXP_PREC_F64 && prec != PCEXP_PREC_MIXED) return fail(c, PCEXP_E_ARG, "bad precision");
+  if (jvp == PCEXP_JVP_FD && prec == PCEXP_PREC_MIXED) return fail(c, PCEXP_E_UNSUPPORTED, "FD JVP is FP64 only");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n = c->Kint;
+  to_int(c, u, c->io[0], st);
+  to_int(c, v, c->io[1], st);
+  bool ok;
+  if (prec == PCEXP_PREC_MIXED) {
+    k_cast<double, float>(c->io[0], c->io32[0], n, st);
+    k_cast<double, float>(c->io[1], c->io32[1], n, st);
+    // the FP32 result is written as float into io[2]'s storage
+    ok = jvp_int(c, jvp, prec, nullptr, c->io32[0], c->io32[1], (void*)c->io[2], nullptr, nullptr, nullptr,
+                 nullptr, st);
+    k_cast<float, double>((const float*)c->io[2], c->io[3], n, st);
+    to_abi(c, c->io[3], Jv, st);
+    return ok ? hip_check(c, "jvp") : fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
+  }
+  const double* Rb = nullptr;
+  double* eps = nullptr;
+  if (jvp == PCEXP_JVP_FD) {
+    if (!residual_int(c, c->io[0], c->io[3], st)) return fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
+    Rb = c->io[3];
+    k_sumsq(c->io[0], n, &c->scal[0], 1, c->part, &c->counters[0], st);
+    k_sumsq(c->io[1], n, &c->scal[1], 1, c->part, &c->counters[1], st);
+    k_fd_eps(&c->scal[0], &c->scal[1], kSqrtEps, &c->scal[2], st);
+    eps = &c->scal[2];
+  }
+  ok = jvp_int(c, jvp, prec, c->io[0], nullptr, c->io[1], c->io[2], nullptr, nullptr, Rb, eps, st);
+  to_abi(c, c->io[2], Jv, st);
+  return ok ? hip_check(c, "jvp") : fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
+}
+
+pcexp_status pcexp_vjp(pcexp_ctx* c, const double* u, const double* w, double* JTw, void* stream) {
+  if (!c || !u || !w || !JTw || w == JTw) return c ? fail(c, PCEXP_E_ARG, "bad pointers") : PCEXP_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  if (c->dense) return fail(c, PCEXP_E_UNSUPPORTED, "vjp not provided for dense contexts");
+  to_int(c, u, c->io[0], st);
+  to_int(c, w, c->io[1], st);
+  bool ok = c->dim == 2 ? dg_vjp2(c->p, c->flux, params_d(c), c->io[0], c->io[1], c->io[2], st)
+                        : dg_vjp3(c->p, c->flux, params_d(c), c->io[0], c->io[1], c->io[2], st);
+  to_abi(c, c->io[2], JTw, st);
+  return ok ? hip_check(c, "vjp") : fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
+}
+
+pcexp_status pcexp_stable_dt(pcexp_ctx* c, const double* u, double cfl, double* dt_host, void* stream) {
+  if (!c || !u || !dt_host || !(cfl > 0.0)) return c ? fail(c, PCEXP_E_ARG, "bad arguments") : PCEXP_E_ARG;
+  if (c->dense) return fail(c, PCEXP_E_UNSUPPORTED, "dense context has no mesh");
+  hipStream_t st = (hipStream_t)stream;
+  to_int(c, u, c->io[0], st);
+  ek_stable_dt(elem_args(c), c->io[0], nullptr, cfl, &c->scal[8], c->part, &c->counters[2], st);
+  if (hipMemcpyAsync(dt_host, &c->scal[8], sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(c, PCEXP_E_HIP, "stable_dt sync failed");
+  if (!std::isfinite(*dt_host) || !(*dt_host > 0.0)) return fail(c, PCEXP_E_UNPHYSICAL, "invalid time step");
+  return hip_check(c, "stable_dt");
+}
+
+pcexp_status pcexp_conserved_totals(pcexp_ctx* c, const double* u, double* out_host, void* stream) {
+  if (!c || !u || !out_host) return PCEXP_E_ARG;
+  if (c->dense) return fail(c, PCEXP_E_UNSUPPORTED, "dense context has no mesh");
+  hipStream_t st = (hipStream_t)stream;
+  to_int(c, u, c->io[0], st);
+  ek_totals(elem_args(c), c->io[0], &c->scal[16], c->part, &c->counters[3], st);
+  if (hipMemcpyAsync(out_host, &c->scal[16], c->nv * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(c, PCEXP_E_HIP, "totals sync failed");
+  return hip_check(c, "totals");
+}
+
+pcexp_status pcexp_arnoldi_phi(pcexp_ctx* c, const double* u_lin, const double* b, double dt, int32_t k, int32_t m,
+                               int32_t prec, int32_t jvp, double* out, void* ws, size_t ws_bytes,
+                               pcexp_krylov_info* info, void* stream) {
+  pcexp_status s = check_common(c, m, k, prec, jvp, ws, ws_bytes);
+  if (s != PCEXP_OK) return s;
+  if (!u_lin || !b || !out || out == b) return fail(c, PCEXP_E_ARG, "bad pointers");
+  if (!std::isfinite(dt)) return fail(c, PCEXP_E_ARG, "dt must be finite");
+  hipStream_t st = (hipStream_t)stream;
+  const WsLayout L = ws_layout(c, m, k, prec);
+  char* w = (char*)ws;
+  KState* ks = (KState*)(w + L.ks1);
+  double* part = (double*)(w + L.part);
+  double* phi = (double*)(w + L.phi);
+  double* scal = (double*)(w + L.scal);
+  double* un = (double*)(w + L.un);
+  double* Rn = (double*)(w + L.Rn);
+  double* bb = (double*)(w + L.us);
+  double* xo = (double*)(w + L.Rs);
+  float* un32 = (float*)(w + L.un32);
+  to_int(c, u_lin, un, st);
+  to_int(c, b, bb, st);
+  k_set_scalar(&scal[0], dt, st);
+  if (jvp == PCEXP_JVP_FD && !residual_int(c, un, Rn, st)) return fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
+  if (prec == PCEXP_PREC_MIXED) {
+    k_cast<double, float>(un, un32, c->Kint, st);
+    float* V = (float*)(w + L.V);
+    arnoldi_run<float>(c, jvp, prec, un, un32, bb, Rn, &scal[0], k, m, ks, part, phi, V, st);
+    k_combine<float, double>(V, c->Kld, ks, nullptr, xo, (double*)nullptr, 1.0, nullptr, c->Kint, st);
+  } else {
+    double* V = (double*)(w + L.V);
+    arnoldi_run<double>(c, jvp, prec, un, nullptr, bb, Rn, &scal[0], k, m, ks, part, phi, V, st);
+    k_combine<double, double>(V, c->Kld, ks, nullptr, xo, (double*)nullptr, 1.0, nullptr, c->Kint, st);
+  }
+  to_abi(c, xo, out, st);
+  s = hip_check(c, "arnoldi_phi");
+  if (s != PCEXP_OK) return s;
+  if (info) {
+    KState h;
+    if (hipMemcpyAsync(&h, ks, sizeof(KState), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return fail(c, PCEXP_E_HIP, "info sync failed");
+    fill_info(info, h);
+    uint32_t f;
+    return report_flags(c, &f);
+  }
+  return PCEXP_OK;
+}
+
+pcexp_status pcexp_step(pcexp_ctx* c, double* u, double dt, double cfl, int32_t m, int32_t scheme, int32_t prec,
+                        int32_t jvp, void* ws, size_t ws_bytes, pcexp_step_info* info, void* stream) {
+  pcexp_status s = check_common(c, m, 1, prec, jvp, ws, ws_bytes);
+  if (s != PCEXP_OK) return s;
+  if (!u) return fail(c, PCEXP_E_ARG, "u is NULL");
+  if (scheme != PCEXP_SCHEME_PCEXP && scheme != PCEXP_SCHEME_EXP1) return fail(c, PCEXP_E_ARG, "bad scheme");
+  if (!(dt > 0.0) && !(cfl > 0.0)) return fail(c, PCEXP_E_ARG, "need dt > 0 or cfl > 0");
+  if (!(dt > 0.0) && c->dense) return fail(c, PCEXP_E_ARG, "dense contexts need dt > 0");
+  if (!std::isfinite(dt) || !std::isfinite(cfl)) return fail(c, PCEXP_E_ARG, "dt/cfl must be finite");
+  hipStream_t st = (hipStream_t)stream;
+  const WsLayout L = ws_layout(c, m, 1, prec);
+  char* w = (char*)ws;
+  KState* ks1 = (KState*)(w + L.ks1);
+  KState* ks2 = (KState*)(w + L.ks2);
+  double* part = (double*)(w + L.part);
+  double* phi = (double*)(w + L.phi);
+  double* scal = (double*)(w + L.scal);
+  double* un = (double*)(w + L.un);
+  double* Rn = (double*)(w + L.Rn);
+  double* us = (double*)(w + L.us);
+  double* Rs = (double*)(w + L.Rs);
+  void* x1 = (void*)(w + L.x1);
+  float* un32 = (float*)(w + L.un32);
+  unsigned* cnt = (unsigned*)(w + L.cnt);
+  const size_t n = c->Kint;
+  double* dtp = &scal[0];
+
+  k_fill<unsigned>(cnt, 0u, 64, nullptr, st);
+  to_int(c, u, un, st);
+  if (dt > 0.0) k_set_scalar(dtp, dt, st);
+  else ek_stable_dt(elem_args(c), un, nullptr, cfl, dtp, part, &cnt[0], st);
+  if (!residual_int(c, un, Rn, st)) return fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
+  const bool mixed = (prec == PCEXP_PREC_MIXED);
+  if (mixed) k_cast<double, float>(un, un32, n, st);
+
+  if (mixed) {
+    float* V = (float*)(w + L.V);
+    arnoldi_run<float>(c, jvp, prec, un, un32, Rn, Rn, dtp, 1, m, ks1, part, phi, V, st);
+    Prof pr(c, st, PC_COMB, (double)c->K * (m * 4.0 + 8 + 8 + 4));
+    k_combine<float, float>(V, c->Kld, ks1, un, us, (float*)x1, 1.0, dtp, n, st);
+  } else {
+    double* V = (double*)(w + L.V);
+    arnoldi_run<double>(c, jvp, prec, un, nullptr, Rn, Rn, dtp, 1, m, ks1, part, phi, V, st);
+    Prof pr(c, st, PC_COMB, (double)c->K * (m * 8.0 + 8 + 8 + 8));
+    k_combine<double, double>(V, c->Kld, ks1, un, us, (double*)x1, 1.0, dtp, n, st);
+  }
+  if (scheme == PCEXP_SCHEME_EXP1) {
+    to_abi(c, us, u, st);
+  } else {
+    // N* - N_n = R(u*) - R_n - J_n x1
+    if (!residual_int(c, us, Rs, st)) return fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
+    if (mixed) {
+      float* jx = (float*)(w + L.V);  // Krylov storage is free between the two Arnoldi runs
+      jvp_int(c, jvp, prec, un, un32, x1, jx, nullptr, nullptr, Rn, nullptr, st);
+      k_glue_d<float>(Rs, Rn, jx, Rs, n, st);
+    } else {
+      double* jx = (double*)(w + L.V);
+      if (jvp == PCEXP_JVP_FD) {
+        k_sumsq(un, n, &scal[1], 1, part, &cnt[1], st);
+        k_sumsq((const double*)x1, n, &scal[2], 1, part, &cnt[2], st);
+        k_fd_eps(&scal[1], &scal[2], kSqrtEps, &scal[3], st);
+      }
+      jvp_int(c, jvp, prec, un, nullptr, x1, jx, nullptr, nullptr, Rn, &scal[3], st);
+      k_glue_d<double>(Rs, Rn, jx, Rs, n, st);
+    }
+    if (mixed) {
+      float* V = (float*)(w + L.V);
+      arnoldi_run<float>(c, jvp, prec, un, un32, Rs, Rn, dtp, 1, m, ks2, part, phi, V, st);
+      Prof pr(c, st, PC_COMB, (double)c->K * (m * 4.0 + 8 + 8));
+      k_combine<float, double>(V, c->Kld, ks2, us, un, (double*)nullptr, 0.5, dtp, n, st);
+    } else {
+      double* V = (double*)(w + L.V);
+      arnoldi_run<double>(c, jvp, prec, un, nullptr, Rs, Rn, dtp, 1, m, ks2, part, phi, V, st);
+      Prof pr(c, st, PC_COMB, (double)c->K * (m * 8.0 + 8 + 8));
+      k_combine<double, double>(V, c->Kld, ks2, us, un, (double*)nullptr, 0.5, dtp, n, st);
+    }
+    to_abi(c, un, u, st);
+  }
+  s = hip_check(c, "step");
+  if (s != PCEXP_OK) return s;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    if (!c->dense) {
+      k_sumsq(Rn, (size_t)c->nb * c->Epad, &scal[4], 1, part, &cnt[3], st);
+    }
+    KState h1, h2;
+    double sc[8];
+    if (hipMemcpyAsync(&h1, ks1, sizeof(KState), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&h2, ks2, sizeof(KState), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(sc, scal, sizeof(sc), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return fail(c, PCEXP_E_HIP, "info sync failed");
+    fill_info(&info->k1, h1);
+    if (scheme == PCEXP_SCHEME_PCEXP) fill_info(&info->k2, h2);
+    info->dt = sc[0];
+    info->res_rho_norm = c->dense ? 0.0 : sc[4] / c->volume_total;
+    return report_flags(c, &info->flags);
+  }
+  return PCEXP_OK;
+}
+
+pcexp_status pcexp_profile(pcexp_ctx* c, int32_t op, double* out) {
+  if (!c) return PCEXP_E_ARG;
+  if (op == 0) {
+    c->prof = false;
+    return PCEXP_OK;
+  }
+  if (op == 1) {
+    if (c->ev.empty()) {
+      c->ev.resize(65536);
+      for (auto& e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) return fail(c, PCEXP_E_HIP, "hipEventCreate failed");
+    }
+    c->recs.clear();
+    c->prof = true;
+    return PCEXP_OK;
+  }
+  if (op == 2) {
+    if (!out) return fail(c, PCEXP_E_ARG, "out is NULL");
+    for (int i = 0; i < 3 * PCEXP_PROF_NCLASS; ++i) out[i] = 0.0;
+    if (hipDeviceSynchronize() != hipSuccess) return fail(c, PCEXP_E_HIP, "sync failed");
+    for (const auto& r : c->recs) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev[r.e0], c->ev[r.e0 + 1]) != hipSuccess) continue;
+      out[3 * r.cls] += ms;
+      out[3 * r.cls + 1] += 1.0;
+      out[3 * r.cls + 2] += r.bytes;
+    }
+    return PCEXP_OK;
+  }
+  return fail(c, PCEXP_E_ARG, "bad profile op");
+}
+
+}  // extern "C"

@@ -1,0 +1,277 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 tolerance: 1e-11 relative (2-norm over the whole vector) unless a
+derived bound is stated.  Every case prints its name, mesh, degree and flux
+before touching the GPU.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.dg import DG
+from oracle import krylov
+from oracle.derivatives import jvp_cs, jvp_fd, dense_jacobian
+from oracle.integrators import pcexp_step, heun_step, ExactJacobian, DenseSplit, stable_dt
+from oracle.diagnostics import conserved_totals
+from tests.helpers import mesh_case, vortex_state, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1801_06300_amd import PCEXP
+    return PCEXP
+
+
+def _pair(name, p, flux, amp=1e-6, uinf=None):
+    PCEXP = _dev()
+    m, ang = mesh_case(name)
+    prim = W.freestream_prim(m.dim, angle_deg=ang)
+    print(f"\n[case] mesh={name} p={p} flux={flux} nE={m.n_elem}", flush=True)
+    g = DG(m, p, flux, farfield_prim=prim)
+    ctx = PCEXP(m, p, flux, farfield_prim=prim)
+    u = vortex_state(g, m, amp, uinf=uinf)
+    return g, ctx, u
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+CASES = [("sq3", 1, "lf"), ("sq4j", 2, "roe"), ("sq4j", 3, "lf"), ("sq3", 0, "roe"),
+         ("cube3", 1, "lf"), ("cube3", 2, "roe"), ("chan", 2, "roe"), ("chan", 1, "lf")]
+
+
+@pytest.mark.parametrize("name,p,flux", CASES)
+def test_residual_parity(name, p, flux):
+    g, ctx, u = _pair(name, p, flux, amp=1e-3)
+    R = _n(ctx.residual(_t(u)))
+    Ro = g.residual(u)
+    assert rel(R, Ro) < 1e-11
+    assert np.max(np.abs(R - Ro)) < 1e-11 * np.max(np.abs(Ro))
+
+
+@pytest.mark.parametrize("name,p,flux", [("sq4j", 2, "roe"), ("cube3", 2, "lf"), ("chan", 2, "roe")])
+def test_quadrature_projection_evaluation(name, p, flux):
+    g, ctx, u = _pair(name, p, flux)
+    xq = _n(ctx.quad_points())
+    xo = g.quad_points()
+    assert np.max(np.abs(xq - xo)) < 1e-13 * max(1.0, np.abs(xo).max())
+    m = g.m
+    if m.period[0] > 0:
+        f = lambda x: W.isentropic_vortex(x, center=(5.0, 5.0), period=m.period)
+    else:
+        f = lambda x: W.uniform_state(x, W.freestream_prim(2, angle_deg=0.0)) * (1 + 0.1 * np.sin(x[:, :1]))
+    Uq = f(xq.reshape(-1, g.d)).reshape(g.nE, g.Nq, g.nv)
+    up = _n(ctx.project(_t(Uq)))
+    assert rel(up, g.project(f)) < 1e-12
+    Ue = _n(ctx.evaluate(_t(u)))
+    assert rel(Ue, g.evaluate(u)) < 1e-12
+
+
+@pytest.mark.parametrize("name,p,flux", CASES)
+def test_tangent_jvp_parity(name, p, flux):
+    g, ctx, u = _pair(name, p, flux, amp=1e-3)
+    v = W.random_unit_vector(u.shape, 7)
+    Jv = _n(ctx.jvp(_t(u), _t(v), "tangent", "f64"))
+    assert rel(Jv, jvp_cs(g, u, v)) < 1e-11
+
+
+@pytest.mark.parametrize("name,p,flux", [("sq4j", 2, "roe"), ("cube3", 1, "lf"), ("chan", 2, "roe")])
+def test_fd_jvp_parity(name, p, flux):
+    """FD JVP against the oracle's FD JVP (same eps formula).  The two residual
+    evaluations differ by a few ulps of R, amplified by 1/eps:
+    |dFD| <~ 8 u_R |R| / eps, bounded here by 1e-7 relative."""
+    g, ctx, u = _pair(name, p, flux, amp=1e-3)
+    v = W.random_unit_vector(u.shape, 8)
+    fd = _n(ctx.jvp(_t(u), _t(v), "fd", "f64"))
+    assert rel(fd, jvp_fd(g, u, v)) < 1e-7
+    assert rel(fd, jvp_cs(g, u, v)) < 1e-5
+
+
+@pytest.mark.parametrize("name,p,flux", [("sq4j", 2, "roe"), ("cube3", 2, "lf"), ("chan", 2, "roe")])
+def test_mixed_jvp_bound(name, p, flux):
+    """FP32 tangent JVP against the FP64 oracle: stated bound 1e-5 relative."""
+    g, ctx, u = _pair(name, p, flux, amp=1e-3)
+    v = W.random_unit_vector(u.shape, 9)
+    Jv = _n(ctx.jvp(_t(u), _t(v), "tangent", "mixed"))
+    assert rel(Jv, jvp_cs(g, u, v)) < 1e-5
+
+
+@pytest.mark.parametrize("name,p,flux", [("sq3", 1, "roe"), ("sq3", 2, "lf"), ("cube3", 1, "roe"),
+                                         ("chan", 1, "roe")])
+def test_vjp_parity(name, p, flux):
+    g, ctx, u = _pair(name, p, flux, amp=1e-3)
+    w = W.random_unit_vector(u.shape, 10)
+    v = W.random_unit_vector(u.shape, 11)
+    JTw = _n(ctx.vjp(_t(u), _t(w)))
+    J = dense_jacobian(g, u)
+    assert rel(JTw.ravel(), J.T @ w.ravel()) < 1e-11
+    Jv = _n(ctx.jvp(_t(u), _t(v)))
+    lhs, rhs = float(np.sum(w * Jv)), float(np.sum(JTw * v))
+    assert abs(lhs - rhs) < 1e-12 * max(np.linalg.norm(w) * np.linalg.norm(Jv), 1.0)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+@pytest.mark.parametrize("jvp", ["tangent", "fd"])
+def test_arnoldi_phi_parity(k, jvp):
+    g, ctx, u = _pair("sq4j", 2, "roe")
+    b = g.residual(u)
+    dt = stable_dt(g, u, 5.0)
+    out, info = ctx.arnoldi_phi(_t(u), _t(b), dt, k=k, m=12, jvp=jvp, info=True)
+    op = ExactJacobian(g, "exact" if jvp == "tangent" else "fd")
+    Rn = g.residual(u)
+    want, oinfo = krylov.arnoldi_phi(lambda x: op.jvp(u, x.reshape(u.shape), Rn), b, dt, k, 12,
+                                     return_info=True)
+    tol = 1e-11 if jvp == "tangent" else 1e-6
+    assert rel(_n(out), want) < tol
+    assert info["m_eff"] == oinfo["m_eff"] == 12
+    assert abs(info["beta"] - oinfo["beta"]) < 1e-13 * oinfo["beta"]
+
+
+def test_arnoldi_phi_vs_dense_dg():
+    """Krylov phi_1 on the tiny-mesh DG Jacobian with m = 40 equals the dense phi_1."""
+    g, ctx, u = _pair("sq3", 1, "lf")
+    J = dense_jacobian(g, u)
+    b = g.residual(u)
+    dt = stable_dt(g, u, 2.0)
+    out = _n(ctx.arnoldi_phi(_t(u), _t(b), dt, k=1, m=40))
+    want = krylov.dense_phi(J, b.ravel(), dt, 1).reshape(u.shape)
+    assert rel(out, want) < 1e-11
+
+
+def test_arnoldi_phi_zero_vector_and_mixed():
+    g, ctx, u = _pair("sq4j", 2, "roe")
+    out, info = ctx.arnoldi_phi(_t(u), _t(np.zeros_like(u)), 0.1, k=1, m=5, info=True)
+    assert info["m_eff"] == 0 and np.all(_n(out) == 0)
+    b = g.residual(u)
+    dt = stable_dt(g, u, 5.0)
+    out = _n(ctx.arnoldi_phi(_t(u), _t(b), dt, k=1, m=12, prec="mixed"))
+    want = krylov.arnoldi_phi(lambda x: jvp_cs(g, u, x.reshape(u.shape)), b, dt, 1, 12)
+    assert rel(out, want) < 1e-5
+
+
+# ------------------------------------------------------------- dense operators
+def test_dense_split_model_growth():
+    """1x1 split operator through the device stepper: eq. (grow), eq. (exp1_grow)."""
+    PCEXP = _dev()
+    for a in (-3.0, -0.7, 0.4):
+        for b in (-6.0, -1.3, 0.25, 1.5):
+            ctx = PCEXP.dense([[b]], [[a + b]])
+            u = torch.ones(1, dtype=torch.float64, device="cuda")
+            ctx.step(u, dt=1.0, m=1)
+            printed = (a * (a - b) + np.exp(2 * b) * (a + b) * a + 2 * np.exp(b) * (b * b - a * a)) / (2 * b * b)
+            assert abs(u.item() - printed) < 1e-12 * max(1, abs(printed))
+            u = torch.ones(1, dtype=torch.float64, device="cuda")
+            ctx.step(u, dt=1.0, m=1, scheme="exp1")
+            assert abs(u.item() - (a * (np.exp(b) - 1) + b * np.exp(b)) / b) < 1e-12 * max(1, abs(u.item()))
+
+
+def test_dense_linear_exactness_and_breakdown():
+    from scipy.linalg import expm
+    PCEXP = _dev()
+    rng = np.random.default_rng(4)
+    n = 20
+    A = rng.standard_normal((n, n)) - 4 * np.eye(n)
+    u0 = rng.standard_normal(n)
+    ctx = PCEXP.dense(A, A)
+    u = _t(u0)
+    info = ctx.step(u, dt=0.4, m=n, info=True)
+    want = expm(0.4 * A) @ u0
+    assert rel(_n(u), want) < 1e-12
+    # nilpotent shift: the Krylov space of e_6 has dimension 6 -> breakdown, exact result
+    N = np.diag(np.ones(5), 1)
+    ctx = PCEXP.dense(N, N)
+    b = np.zeros(6)
+    b[-1] = 1.0
+    out, info = ctx.arnoldi_phi(_t(np.zeros(6)), _t(b), 1.0, k=1, m=20, info=True)
+    assert info["breakdown"] and info["m_eff"] == 6
+    assert np.allclose(_n(out), krylov.dense_phi(N, b, 1.0, 1), atol=1e-14)
+
+
+def test_dense_phi_closed_forms():
+    """Diagonal operator: phi_k closed forms through the device phi kernel."""
+    from math import factorial
+    PCEXP = _dev()
+    z = np.array([-40.0, -7.5, -1.0, -1e-3, 0.5, 2.0])
+    b = np.linspace(0.5, 1.5, z.size)
+    dt = 0.7
+    ctx = PCEXP.dense(np.diag(z / dt), np.diag(z / dt))
+    for k in (0, 1, 2, 3):
+        out = _n(ctx.arnoldi_phi(_t(np.zeros_like(b)), _t(b), dt, k=k, m=10))
+        small = np.abs(z) < 1e-2
+        ph = np.where(small, sum(z ** j / factorial(j + k) for j in range(12)),
+                      (np.exp(z) - sum(z ** j / factorial(j) for j in range(k))) / np.where(small, 1, z) ** k)
+        assert np.all(np.abs(out - ph * b) <= 1e-12 * np.abs(ph * b) + 1e-14)
+
+
+# ------------------------------------------------------------------- stepping
+def test_step_parity_config1_ten_steps():
+    """Config-1 mesh (16x16 periodic, P1, LF, m = 20, CFL 5): 10 PCEXP steps."""
+    g, ctx, u0 = _pair("sq16", 1, "lf")
+    op = ExactJacobian(g)
+    u_o = u0.copy()
+    u_d = _t(u0)
+    for n in range(10):
+        dt = stable_dt(g, u_o, 5.0)
+        u_o = pcexp_step(op, u_o, dt, 20)
+        info = ctx.step(u_d, cfl=5.0, m=20, info=True)
+        assert abs(info["dt"] - dt) < 1e-13 * dt
+        assert rel(_n(u_d), u_o) < 1e-11, n
+    assert info["k1"]["m_eff"] == 20 and info["flags"] == 0
+
+
+@pytest.mark.parametrize("scheme,jvp,prec,tol", [("exp1", "tangent", "f64", 1e-11),
+                                                  ("pcexp", "fd", "f64", 1e-8),
+                                                  ("pcexp", "tangent", "mixed", 1e-6),
+                                                  ("pcexp", "zero", "f64", 1e-13)])
+def test_step_variants(scheme, jvp, prec, tol):
+    g, ctx, u0 = _pair("sq4j", 2, "roe")
+    dt = stable_dt(g, u0, 5.0)
+    if jvp == "zero":
+        want = heun_step(ExactJacobian(g), u0, dt)
+    else:
+        want = pcexp_step(ExactJacobian(g, "exact" if jvp != "fd" else "fd"), u0, dt, 12, scheme=scheme)
+    u = _t(u0)
+    ctx.step(u, dt=dt, m=12, scheme=scheme, jvp=jvp, prec=prec)
+    inc_want = want - u0
+    assert rel(_n(u) - u0, inc_want) < tol * 100 if prec == "mixed" else rel(_n(u), want) < tol
+
+
+def test_step_conservation_and_determinism():
+    g, ctx, u0 = _pair("sq8j", 2, "roe")
+    q0 = ctx.conserved_totals(_t(u0))
+    assert np.allclose(q0, conserved_totals(g, u0), rtol=1e-13, atol=1e-13)
+    a, b = _t(u0), _t(u0)
+    for _ in range(5):
+        ctx.step(a, cfl=10.0, m=15)
+        ctx.step(b, cfl=10.0, m=15)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    q1 = ctx.conserved_totals(a)
+    assert np.max(np.abs(q1 - q0) / np.abs(q0).max()) < 1e-13
+
+
+def test_stable_dt_parity():
+    g, ctx, u = _pair("sq4j", 2, "roe")
+    assert abs(ctx.stable_dt(_t(u), 3.0) - stable_dt(g, u, 3.0)) < 1e-14 * stable_dt(g, u, 3.0)
+
+
+def test_unphysical_flag():
+    """A state with negative pressure is reported by the next synchronising call."""
+    from paper_1801_06300_amd import PcexpError
+    g, ctx, u = _pair("sq3", 1, "lf")
+    bad = u.copy()
+    bad[0, -1, :] = -1.0     # negative total energy in element 0
+    R = ctx.residual(_t(bad))
+    with pytest.raises(PcexpError):
+        ctx.step(_t(bad), dt=0.01, m=4, info=True)
