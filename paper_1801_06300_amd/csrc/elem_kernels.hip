@@ -116,22 +116,9 @@ __device__ __forceinline__ double ek_wave_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ bool ek_last(unsigned* counter) {
-  __shared__ int amlast;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    amlast = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (amlast) __threadfence();
-  return amlast != 0;
-}
-
 // dt = cfl * min_E h_E / ((2p+1)(|v| + c)), v and c at the centroid (eq. (x3d)).
-__global__ void stable_dt_kernel(ElemArgs a, const double* __restrict__ u, const double* cfl_dev, double cfl,
-                                 double* dt, double* part, unsigned* counter) {
+// Per-block minima, then a one-block kernel takes the minimum (order-free).
+__global__ void stable_dt_kernel(ElemArgs a, const double* __restrict__ u, double* part) {
   const int e = blockIdx.x * EK_T + threadIdx.x;
   const int nb = a.nb, d = a.dim;
   double lam = 1e300;
@@ -149,6 +136,7 @@ __global__ void stable_dt_kernel(ElemArgs a, const double* __restrict__ u, const
     const double p = (a.gamma - 1.0) * (U[d + 1] - 0.5 * q2 / rho);
     const double speed = sqrt(q2) / rho + sqrt(a.gamma * p / rho);
     lam = a.hE[e] / ((2 * a.p + 1) * speed);
+    if (!(lam > 0.0)) lam = -1.0;   // NaN or non-positive: propagate an invalid step
   }
   __shared__ double red[EK_T / 64];
   double m = ek_wave_min(lam);
@@ -159,22 +147,17 @@ __global__ void stable_dt_kernel(ElemArgs a, const double* __restrict__ u, const
     for (int w = 1; w < EK_T / 64; ++w) mm = fmin(mm, red[w]);
     part[blockIdx.x] = mm;
   }
-  if (ek_last(counter)) {
-    if (threadIdx.x < 64) {
-      double mm = 1e300;
-      for (int b = threadIdx.x; b < (int)gridDim.x; b += 64) mm = fmin(mm, part[b]);
-      mm = ek_wave_min(mm);
-      if (threadIdx.x == 0) {
-        *dt = (cfl_dev ? *cfl_dev : cfl) * mm;
-        *counter = 0u;
-      }
-    }
-  }
+}
+
+__global__ void stable_dt_finalize(const double* part, int nblk, const double* cfl_dev, double cfl, double* dt) {
+  double mm = 1e300;
+  for (int b = threadIdx.x; b < nblk; b += 64) mm = fmin(mm, part[b]);
+  mm = ek_wave_min(mm);
+  if (threadIdx.x == 0) *dt = (cfl_dev ? *cfl_dev : cfl) * mm;
 }
 
 // Q_k = sum_E int_E U_k = sum_E s_E phi_hat_0 / d! * u_int[k][0][E]
-__global__ void totals_kernel(ElemArgs a, const double* __restrict__ u, double* out, double* part,
-                              unsigned* counter) {
+__global__ void totals_kernel(ElemArgs a, const double* __restrict__ u, double* part) {
   const int e = blockIdx.x * EK_T + threadIdx.x;
   const int nv = a.nv;
   const double fact = (a.dim == 2) ? 0.5 : (1.0 / 6.0);
@@ -191,15 +174,15 @@ __global__ void totals_kernel(ElemArgs a, const double* __restrict__ u, double* 
     for (int w = 0; w < EK_T / 64; ++w) s += red[w][threadIdx.x];
     part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
   }
-  if (ek_last(counter)) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int k = wid; k < nv; k += EK_T / 64) {
-      double s = 0.0;
-      for (int b = lane; b < (int)gridDim.x; b += 64) s += part[(size_t)k * gridDim.x + b];
-      s = ek_wave_sum(s);
-      if (lane == 0) out[k] = s;
-    }
-    if (threadIdx.x == 0) *counter = 0u;
+}
+
+__global__ void totals_finalize(const double* part, int nblk, int nv, double* out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = wid; k < nv; k += EK_T / 64) {
+    double s = 0.0;
+    for (int b = lane; b < nblk; b += 64) s += part[(size_t)k * nblk + b];
+    s = ek_wave_sum(s);
+    if (lane == 0) out[k] = s;
   }
 }
 
@@ -220,12 +203,17 @@ void ek_evaluate(const ElemArgs& a, const double* u_abi, double* Uqp, hipStream_
 }
 void ek_stable_dt(const ElemArgs& a, const double* u_int, const double* cfl_dev, double cfl, double* dt,
                   double* part, unsigned* counter, hipStream_t st) {
-  hipLaunchKernelGGL(stable_dt_kernel, grid_for((size_t)a.nE), dim3(EK_T), 0, st, a, u_int, cfl_dev, cfl, dt,
-                     part, counter);
+  (void)counter;
+  const dim3 g = grid_for((size_t)a.nE);
+  hipLaunchKernelGGL(stable_dt_kernel, g, dim3(EK_T), 0, st, a, u_int, part);
+  hipLaunchKernelGGL(stable_dt_finalize, dim3(1), dim3(64), 0, st, part, (int)g.x, cfl_dev, cfl, dt);
 }
 void ek_totals(const ElemArgs& a, const double* u_int, double* out, double* part, unsigned* counter,
                hipStream_t st) {
-  hipLaunchKernelGGL(totals_kernel, grid_for((size_t)a.nE), dim3(EK_T), 0, st, a, u_int, out, part, counter);
+  (void)counter;
+  const dim3 g = grid_for((size_t)a.nE);
+  hipLaunchKernelGGL(totals_kernel, g, dim3(EK_T), 0, st, a, u_int, part);
+  hipLaunchKernelGGL(totals_finalize, dim3(1), dim3(EK_T), 0, st, part, (int)g.x, a.nv, out);
 }
 
 }  // namespace pcexp

@@ -31,23 +31,13 @@ __device__ __forceinline__ double wave_min(double a) {
   return a;
 }
 
-// Called by all threads after the block has written its partials.  Returns
-// true (in every thread) in the last block to arrive.
-__device__ __forceinline__ bool arrive_last(unsigned* counter) {
-  __shared__ int amlast;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    amlast = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (amlast) __threadfence();
-  return amlast != 0;
-}
+// Reductions: every kernel writes one partial per block and column
+// (part[col * PLD + block]); the next kernel on the stream -- which sees them
+// by kernel-boundary ordering -- sums each column in a fixed order.  No
+// grid-wide fences or atomics: on gfx950 an agent-scope fence writes back
+// the L2 and costs far more than the streaming work of these kernels.
 
-// Fixed-order sum of column c of the partials over nblk blocks, computed by
-// one wave; the result is returned in every lane.
+// Fixed-order sum of column c over nblk partials, by one wave (all lanes get it).
 __device__ __forceinline__ double col_sum(const double* part, int c, int nblk) {
   const int lane = threadIdx.x & 63;
   double a = 0.0;
@@ -99,38 +89,44 @@ void k_init_state(KState* ks, double eta, hipStream_t st) {
   hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(256), 0, st, ks, eta);
 }
 
+// Partial buffers of one Arnoldi run: three column blocks of (KMAX+2) columns.
+__device__ __forceinline__ double* pbuf(double* part, int which) { return part + (size_t)which * (KMAX + 2) * PLD; }
+__device__ __forceinline__ const double* pbuf(const double* part, int which) {
+  return part + (size_t)which * (KMAX + 2) * PLD;
+}
+
 // ------------------------------------------------- start: V_0 = b, beta = |b|
 template <typename TV>
 __global__ __launch_bounds__(RT) void start_kernel(const double* __restrict__ b, TV* __restrict__ V0,
-                                                   size_t n, KState* ks, double* part) {
+                                                   size_t n, double* part) {
   double acc[1] = {0.0};
   for (size_t i = (size_t)blockIdx.x * RT + threadIdx.x; i < n; i += (size_t)gridDim.x * RT) {
     double x = b[i];
     V0[i] = (TV)x;
     acc[0] += x * x;
   }
-  block_partials<1>(acc, 1, part);
-  if (arrive_last(&ks->counter[0])) {
-    if (threadIdx.x < 64) {
-      double s = col_sum(part, 0, gridDim.x);
-      if (threadIdx.x == 0) {
-        double beta = sqrt(s);
-        ks->beta = beta;
-        if (beta > 0.0) {
-          ks->sigma[0] = 1.0 / beta;
-        } else {
-          ks->done = 1;
-          ks->m_eff = 0;
-        }
-        ks->counter[0] = 0u;
-      }
+  block_partials<1>(acc, 1, pbuf(part, 2));
+}
+
+__global__ __launch_bounds__(64) void start_finalize(KState* ks, const double* part, int nblk) {
+  const double s = col_sum(pbuf(part, 2), 0, nblk);
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(s);
+    ks->beta = beta;
+    if (beta > 0.0) {
+      ks->sigma[0] = 1.0 / beta;
+    } else {
+      ks->done = 1;
+      ks->m_eff = 0;
     }
   }
 }
 
 template <typename TV>
 void k_start(const double* b, TV* V0, size_t n, KState* ks, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(start_kernel<TV>, dim3(gs_blocks(n)), dim3(RT), 0, st, b, V0, n, ks, part);
+  const int nb = (int)gs_blocks(n);
+  hipLaunchKernelGGL(start_kernel<TV>, dim3(nb), dim3(RT), 0, st, b, V0, n, part);
+  hipLaunchKernelGGL(start_finalize, dim3(1), dim3(64), 0, st, ks, part, nb);
 }
 
 // Vector loads of the Gram-Schmidt kernels are unconditional: slots beyond
@@ -138,10 +134,17 @@ void k_start(const double* b, TV* V0, size_t n, KState* ks, double* part, hipStr
 // coefficient, so the compiler can keep all NV loads of an element in flight.
 __device__ __forceinline__ int clampv(int i, int nvec) { return i < nvec ? i : nvec - 1; }
 
-// ------------------------------------------ pass-1 projections h = V^T w, |w|
+// Iteration j (vectors V_0..V_j live, w stored in slot V_{j+1}):
+//   dots:         raw1_i = V_i . w, |w|^2                         -> partials 0
+//   coeff:        hcol_i = sigma_i^2 raw1_i                          (one block)
+//   update_dots:  w -= sum hcol_i V_i;  raw2_i = V_i . w             -> partials 1
+//   coeff:        hcol_i = sigma_i^2 raw2_i                          (one block)
+//   update_norm:  w -= sum hcol_i V_i;  |w|^2                        -> partials 2
+//   finalize:     H[i][j] = sigma_i (raw1_i + raw2_i), h_{j+1,j} = |w|,
+//                 breakdown test, sigma_{j+1} = 1/h_{j+1,j}          (one block)
 template <typename TV, int NV>
 __global__ __launch_bounds__(RT) void dots_kernel(const TV* __restrict__ V, size_t ld, int j, size_t n,
-                                                  KState* ks, double* part) {
+                                                  const KState* ks, double* part) {
   if (ks->done) return;
   const int nvec = j + 1;
   const TV* w = V + (size_t)(j + 1) * ld;
@@ -158,54 +161,41 @@ __global__ __launch_bounds__(RT) void dots_kernel(const TV* __restrict__ V, size
     for (int i = 0; i < NV; ++i) acc[i] += (double)vr[i] * wv;
     aw += wv * wv;
   }
-  {
-    // block partials: columns 0..nvec-1 = projections, column nvec = |w|^2
-    __shared__ double red[RW][NV + 1];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // block partials: columns 0..nvec-1 = projections, column nvec = |w|^2
+  double* out = pbuf(part, 0);
+  __shared__ double red[RW][NV + 1];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      if (i < nvec) {
-        double a = wave_sum(acc[i]);
-        if (lane == 0) red[wid][i] = a;
-      }
-    }
-    double a = wave_sum(aw);
-    if (lane == 0) red[wid][NV] = a;
-    __syncthreads();
-    for (int i = threadIdx.x; i <= nvec; i += RT) {
-      const int src = (i == nvec) ? NV : i;
-      double s = 0.0;
-#pragma unroll
-      for (int w2 = 0; w2 < RW; ++w2) s += red[w2][src];
-      part[(size_t)i * PLD + blockIdx.x] = s;
+  for (int i = 0; i < NV; ++i) {
+    if (i < nvec) {
+      double a = wave_sum(acc[i]);
+      if (lane == 0) red[wid][i] = a;
     }
   }
-  if (arrive_last(&ks->counter[1])) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int c = wid; c <= nvec; c += RW) {
-      double s = col_sum(part, c, gridDim.x);
-      if (lane == 0) {
-        if (c < nvec) ks->hcol[c] = ks->sigma[c] * s;
-        else ks->wnorm = sqrt(s);
-      }
-    }
-    if (threadIdx.x == 0) ks->counter[1] = 0u;
+  double a = wave_sum(aw);
+  if (lane == 0) red[wid][NV] = a;
+  __syncthreads();
+  for (int i = threadIdx.x; i <= nvec; i += RT) {
+    const int src = (i == nvec) ? NV : i;
+    double s = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < RW; ++w2) s += red[w2][src];
+    out[(size_t)i * PLD + blockIdx.x] = s;
   }
 }
 
-// ---------------- w -= V (sigma .* h1), then pass-2 projections h2 = V^T w
-template <typename TV, int NV>
-__global__ __launch_bounds__(RT) void update_dots_kernel(TV* __restrict__ V, size_t ld, int j, size_t n,
-                                                         KState* ks, double* part) {
+template <typename TV, int NV, int IN, int OUT, bool DOTS>
+__global__ __launch_bounds__(RT) void update_kernel(TV* __restrict__ V, size_t ld, int j, size_t n,
+                                                    const KState* ks, double* part) {
   if (ks->done) return;
   const int nvec = j + 1;
   __shared__ double hs[NV];
-  for (int i = threadIdx.x; i < NV; i += RT) hs[i] = (i < nvec) ? ks->hcol[i] * ks->sigma[i] : 0.0;
+  for (int i = threadIdx.x; i < NV; i += RT) hs[i] = (i < nvec) ? ks->hcol[i] : 0.0;
   __syncthreads();
   TV* w = V + (size_t)(j + 1) * ld;
-  double acc[NV];
+  double acc[DOTS ? NV : 1];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  for (int i = 0; i < (DOTS ? NV : 1); ++i) acc[i] = 0.0;
   for (size_t idx = (size_t)blockIdx.x * RT + threadIdx.x; idx < n; idx += (size_t)gridDim.x * RT) {
     TV vr[NV];
     double wv = (double)w[idx];
@@ -216,64 +206,47 @@ __global__ __launch_bounds__(RT) void update_dots_kernel(TV* __restrict__ V, siz
     const TV ws = (TV)wv;
     w[idx] = ws;
     const double wq = (double)ws;
+    if constexpr (DOTS) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += (double)vr[i] * wq;
-  }
-  block_partials<NV>(acc, nvec, part);
-  if (arrive_last(&ks->counter[2])) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int c = wid; c < nvec; c += RW) {
-      double s = col_sum(part, c, gridDim.x);
-      if (lane == 0) {
-        ks->H[(size_t)j * KLD + c] = ks->hcol[c];   // pass-1 coefficient
-        ks->hcol[c] = ks->sigma[c] * s;              // pass-2 coefficient
-      }
+      for (int i = 0; i < NV; ++i) acc[i] += (double)vr[i] * wq;
+    } else {
+      acc[0] += wq * wq;
     }
-    if (threadIdx.x == 0) ks->counter[2] = 0u;
   }
+  if constexpr (DOTS) block_partials<NV>(acc, nvec, pbuf(part, OUT));
+  else block_partials<1>(acc, 1, pbuf(part, OUT));
 }
 
-// -------- w -= V (sigma .* h2); h_{j+1,j} = |w|; breakdown test; sigma_{j+1}
-template <typename TV, int NV>
-__global__ __launch_bounds__(RT) void update_norm_kernel(TV* __restrict__ V, size_t ld, int j, size_t n,
-                                                         KState* ks, double* part) {
+__global__ __launch_bounds__(RT) void finalize_kernel(KState* ks, const double* part, int j, int nblk) {
   if (ks->done) return;
   const int nvec = j + 1;
-  __shared__ double hs[NV];
-  for (int i = threadIdx.x; i < NV; i += RT) hs[i] = (i < nvec) ? ks->hcol[i] * ks->sigma[i] : 0.0;
-  __syncthreads();
-  TV* w = V + (size_t)(j + 1) * ld;
-  double acc[1] = {0.0};
-  for (size_t idx = (size_t)blockIdx.x * RT + threadIdx.x; idx < n; idx += (size_t)gridDim.x * RT) {
-    TV vr[NV];
-    double wv = (double)w[idx];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) vr[i] = V[(size_t)clampv(i, nvec) * ld + idx];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) wv -= hs[i] * (double)vr[i];
-    const TV ws = (TV)wv;
-    w[idx] = ws;
-    const double wq = (double)ws;
-    acc[0] += wq * wq;
+  __shared__ double r1[KMAX + 1], r2[KMAX + 1];
+  __shared__ double nrm;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int c = wid; c <= nvec; c += RW) {
+    const double s = col_sum(pbuf(part, 0), c, nblk);
+    if (lane == 0) r1[c] = s;
   }
-  block_partials<1>(acc, 1, part);
-  if (arrive_last(&ks->counter[3])) {
-    if (threadIdx.x < 64) {
-      double s = col_sum(part, 0, gridDim.x);
-      if (threadIdx.x == 0) {
-        for (int c = 0; c < nvec; ++c) ks->H[(size_t)j * KLD + c] += ks->hcol[c];
-        double h = sqrt(s);
-        ks->H[(size_t)j * KLD + j + 1] = h;
-        ks->hlast = h;
-        ks->m_eff = j + 1;
-        if (!(h > ks->eta * ks->wnorm)) {
-          ks->breakdown = 1;
-          ks->done = 1;
-        } else {
-          ks->sigma[j + 1] = 1.0 / h;
-        }
-        ks->counter[3] = 0u;
-      }
+  for (int c = wid; c <= nvec; c += RW) {
+    const double s = (c < nvec) ? col_sum(pbuf(part, 1), c, nblk) : col_sum(pbuf(part, 2), 0, nblk);
+    if (lane == 0) {
+      if (c < nvec) r2[c] = s;
+      else nrm = s;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < nvec; ++c) ks->H[(size_t)j * KLD + c] = ks->sigma[c] * (r1[c] + r2[c]);
+    ks->wnorm = sqrt(r1[nvec]);
+    const double h = sqrt(nrm);
+    ks->H[(size_t)j * KLD + j + 1] = h;
+    ks->hlast = h;
+    ks->m_eff = j + 1;
+    if (!(h > ks->eta * ks->wnorm)) {
+      ks->breakdown = 1;
+      ks->done = 1;
+    } else {
+      ks->sigma[j + 1] = 1.0 / h;
     }
   }
 }
@@ -283,45 +256,77 @@ __global__ __launch_bounds__(RT) void update_norm_kernel(TV* __restrict__ V, siz
   do {                                                                                          \
     const int nv_ = j + 1;                                                                      \
     dim3 g_(gs_blocks(n)), b_(RT);                                                              \
-    if (nv_ <= 4) hipLaunchKernelGGL((KERNEL<TV, 4>), g_, b_, 0, st, __VA_ARGS__);              \
-    else if (nv_ <= 8) hipLaunchKernelGGL((KERNEL<TV, 8>), g_, b_, 0, st, __VA_ARGS__);         \
-    else if (nv_ <= 12) hipLaunchKernelGGL((KERNEL<TV, 12>), g_, b_, 0, st, __VA_ARGS__);       \
-    else if (nv_ <= 16) hipLaunchKernelGGL((KERNEL<TV, 16>), g_, b_, 0, st, __VA_ARGS__);       \
-    else if (nv_ <= 20) hipLaunchKernelGGL((KERNEL<TV, 20>), g_, b_, 0, st, __VA_ARGS__);       \
-    else if (nv_ <= 24) hipLaunchKernelGGL((KERNEL<TV, 24>), g_, b_, 0, st, __VA_ARGS__);       \
-    else if (nv_ <= 28) hipLaunchKernelGGL((KERNEL<TV, 28>), g_, b_, 0, st, __VA_ARGS__);       \
-    else if (nv_ <= 32) hipLaunchKernelGGL((KERNEL<TV, 32>), g_, b_, 0, st, __VA_ARGS__);       \
-    else if (nv_ <= 40) hipLaunchKernelGGL((KERNEL<TV, 40>), g_, b_, 0, st, __VA_ARGS__);       \
-    else if (nv_ <= 48) hipLaunchKernelGGL((KERNEL<TV, 48>), g_, b_, 0, st, __VA_ARGS__);       \
-    else if (nv_ <= 56) hipLaunchKernelGGL((KERNEL<TV, 56>), g_, b_, 0, st, __VA_ARGS__);       \
-    else hipLaunchKernelGGL((KERNEL<TV, 64>), g_, b_, 0, st, __VA_ARGS__);                      \
+    if (nv_ <= 4) hipLaunchKernelGGL((KERNEL(4)), g_, b_, 0, st, __VA_ARGS__);                  \
+    else if (nv_ <= 8) hipLaunchKernelGGL((KERNEL(8)), g_, b_, 0, st, __VA_ARGS__);             \
+    else if (nv_ <= 12) hipLaunchKernelGGL((KERNEL(12)), g_, b_, 0, st, __VA_ARGS__);           \
+    else if (nv_ <= 16) hipLaunchKernelGGL((KERNEL(16)), g_, b_, 0, st, __VA_ARGS__);           \
+    else if (nv_ <= 20) hipLaunchKernelGGL((KERNEL(20)), g_, b_, 0, st, __VA_ARGS__);           \
+    else if (nv_ <= 24) hipLaunchKernelGGL((KERNEL(24)), g_, b_, 0, st, __VA_ARGS__);           \
+    else if (nv_ <= 28) hipLaunchKernelGGL((KERNEL(28)), g_, b_, 0, st, __VA_ARGS__);           \
+    else if (nv_ <= 32) hipLaunchKernelGGL((KERNEL(32)), g_, b_, 0, st, __VA_ARGS__);           \
+    else if (nv_ <= 40) hipLaunchKernelGGL((KERNEL(40)), g_, b_, 0, st, __VA_ARGS__);           \
+    else if (nv_ <= 48) hipLaunchKernelGGL((KERNEL(48)), g_, b_, 0, st, __VA_ARGS__);           \
+    else if (nv_ <= 56) hipLaunchKernelGGL((KERNEL(56)), g_, b_, 0, st, __VA_ARGS__);           \
+    else hipLaunchKernelGGL((KERNEL(64)), g_, b_, 0, st, __VA_ARGS__);                          \
   } while (0)
+
+#define PCEXP_K_DOTS(NV) dots_kernel<TV, NV>
+#define PCEXP_K_UPD(NV) update_kernel<TV, NV, 0, 1, true>
+#define PCEXP_K_NRM(NV) update_kernel<TV, NV, 1, 2, false>
+
+// One block: the coefficients on the stored vectors for the next update,
+// hcol[c] = sigma_c^2 * (V_c . w), from the partials of buffer `which`.
+__global__ __launch_bounds__(RT) void coeff_kernel(KState* ks, const double* part, int which, int nvec, int nblk) {
+  if (ks->done) return;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int c = wid; c < nvec; c += RW) {
+    const double s = col_sum(pbuf(part, which), c, nblk);
+    if (lane == 0) ks->hcol[c] = s * ks->sigma[c] * ks->sigma[c];
+  }
+}
 
 template <typename TV>
 void k_dots(const TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st) {
-  PCEXP_GS_DISPATCH(dots_kernel, V, ld, j, n, ks, part);
+  PCEXP_GS_DISPATCH(PCEXP_K_DOTS, V, ld, j, n, ks, part);
+  hipLaunchKernelGGL(coeff_kernel, dim3(1), dim3(RT), 0, st, ks, part, 0, j + 1, (int)gs_blocks(n));
 }
 template <typename TV>
 void k_update_dots(TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st) {
-  PCEXP_GS_DISPATCH(update_dots_kernel, V, ld, j, n, ks, part);
+  PCEXP_GS_DISPATCH(PCEXP_K_UPD, V, ld, j, n, ks, part);
+  hipLaunchKernelGGL(coeff_kernel, dim3(1), dim3(RT), 0, st, ks, part, 1, j + 1, (int)gs_blocks(n));
 }
 template <typename TV>
 void k_update_norm(TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st) {
-  PCEXP_GS_DISPATCH(update_norm_kernel, V, ld, j, n, ks, part);
+  PCEXP_GS_DISPATCH(PCEXP_K_NRM, V, ld, j, n, ks, part);
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(RT), 0, st, ks, part, j, (int)gs_blocks(n));
 }
 
 // ------------------------------------------------------------ Hessenberg phi
 // y = beta * phi_k(dt H_m) e_1, m = m_eff, from the exponential of the
 // augmented (m+k) x (m+k) matrix [[dt H, e_1, 0], [0, 0, I_{k-1}], [0, 0, 0]]
-// (k = 0: exp(dt H) e_1).  exp by the degree-13 Pade approximant with scaling
-// and squaring (Higham 2005).  One workgroup; matrices column-major in `mem`
-// (LDS or global scratch), n <= KMAX + 3.
+// (k = 0: exp(dt H) e_1).  exp(A) by scaling and squaring of the degree-18
+// Taylor polynomial: A is scaled by 2^-s so that |A|_1 <= 1, where the
+// truncation error is below 1/19! ~ 8e-18 relative; the polynomial is
+// evaluated by the Paterson-Stockmeyer scheme in powers of X^4 (7 matrix
+// products), then squared s times.  Matrix products only: no pivoting, few
+// barriers.  One workgroup; matrices column-major in `mem` (LDS or global).
 constexpr int PHI_T = 256;
 
 __device__ void mat_mul(const double* A, const double* B, double* C, int n) {
   for (int t = threadIdx.x; t < n * n; t += PHI_T) {
     const int i = t % n, jj = t / n;
     double s = 0.0;
+    for (int l = 0; l < n; ++l) s += A[l * n + i] * B[jj * n + l];
+    C[jj * n + i] = s;
+  }
+  __syncthreads();
+}
+
+// C = A * B + D  (D may alias neither A nor B nor C)
+__device__ void mat_mul_add(const double* A, const double* B, const double* D, double* C, int n) {
+  for (int t = threadIdx.x; t < n * n; t += PHI_T) {
+    const int i = t % n, jj = t / n;
+    double s = D[t];
     for (int l = 0; l < n; ++l) s += A[l * n + i] * B[jj * n + l];
     C[jj * n + i] = s;
   }
@@ -337,13 +342,13 @@ __device__ void phi_body(KState* ks, const double* dtp, int k, double* mem) {
   }
   const int n = (k >= 1) ? m + k : m;
   const int nn = n * n;
-  double* A = mem;
-  double* A2 = A + nn;
-  double* A4 = A2 + nn;
-  double* A6 = A4 + nn;
-  double* T1 = A6 + nn;
-  double* U = T1 + nn;
-  double* Vm = U + nn;
+  double* X = mem;          // scaled A
+  double* X2 = X + nn;
+  double* X3 = X2 + nn;
+  double* X4 = X3 + nn;
+  double* Bq = X4 + nn;     // current block polynomial
+  double* T0 = Bq + nn;     // ping-pong accumulators
+  double* T1 = T0 + nn;
   const double dt = *dtp;
   for (int t = tid; t < nn; t += PHI_T) {
     const int i = t % n, jj = t / n;
@@ -355,127 +360,64 @@ __device__ void phi_body(KState* ks, const double* dtp, int k, double* mem) {
     } else if (k >= 2 && jj >= m + 1 && i == jj - 1) {
       v = 1.0;
     }
-    A[t] = v;
+    X[t] = v;
   }
   __syncthreads();
-  // 1-norm and scaling
   __shared__ double colsum[KMAX + 4];
   __shared__ int s_sq;
   for (int jj = tid; jj < n; jj += PHI_T) {
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += fabs(A[jj * n + i]);
+    for (int i = 0; i < n; ++i) s += fabs(X[jj * n + i]);
     colsum[jj] = s;
   }
   __syncthreads();
   if (tid == 0) {
     double nrm = 0.0;
     for (int jj = 0; jj < n; ++jj) nrm = fmax(nrm, colsum[jj]);
-    const double theta13 = 5.371920351148152;
     int s = 0;
-    if (nrm > theta13) s = (int)ceil(log2(nrm / theta13));
-    if (s < 0) s = 0;
+    if (nrm > 1.0) s = (int)ceil(log2(nrm));
     s_sq = s;
   }
   __syncthreads();
   const int s = s_sq;
   const double sc = ldexp(1.0, -s);
-  for (int t = tid; t < nn; t += PHI_T) A[t] *= sc;
+  for (int t = tid; t < nn; t += PHI_T) X[t] *= sc;
   __syncthreads();
-  const double b[14] = {64764752532480000.0, 32382376266240000.0, 7771770303897600.0,
-                        1187353796428800.0, 129060195264000.0,  10559470521600.0,
-                        670442572800.0,     33522128640.0,      1323241920.0,
-                        40840800.0,         960960.0,           16380.0,
-                        182.0,              1.0};
-  mat_mul(A, A, A2, n);
-  mat_mul(A2, A2, A4, n);
-  mat_mul(A4, A2, A6, n);
-  for (int t = tid; t < nn; t += PHI_T) T1[t] = b[13] * A6[t] + b[11] * A4[t] + b[9] * A2[t];
-  __syncthreads();
-  mat_mul(A6, T1, U, n);
-  for (int t = tid; t < nn; t += PHI_T) {
-    const int i = t % n, jj = t / n;
-    T1[t] = U[t] + b[7] * A6[t] + b[5] * A4[t] + b[3] * A2[t] + (i == jj ? b[1] : 0.0);
-  }
-  __syncthreads();
-  mat_mul(A, T1, U, n);  // U = A (A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I)
-  for (int t = tid; t < nn; t += PHI_T) T1[t] = b[12] * A6[t] + b[10] * A4[t] + b[8] * A2[t];
-  __syncthreads();
-  mat_mul(A6, T1, Vm, n);
-  for (int t = tid; t < nn; t += PHI_T) {
-    const int i = t % n, jj = t / n;
-    const double v = Vm[t] + b[6] * A6[t] + b[4] * A4[t] + b[2] * A2[t] + (i == jj ? b[0] : 0.0);
-    // P = V - U (in A2), Q = V + U (in A4)
-    A2[t] = v - U[t];
-    A4[t] = v + U[t];
-  }
-  __syncthreads();
-  // Solve P X = Q by Gaussian elimination with partial pivoting (X in A4).
-  double* P = A2;
-  double* Q = A4;
-  __shared__ int piv;
-  for (int c = 0; c < n; ++c) {
-    if (tid < 64) {
-      // wave-parallel pivot search; ties go to the lowest row
-      int best = n;
-      double bv = -1.0;
-      for (int r = c + tid; r < n; r += 64) {
-        const double v = fabs(P[c * n + r]);
-        if (v > bv) { bv = v; best = r; }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(bv, off, 64);
-        const int ob = __shfl_xor(best, off, 64);
-        if (ov > bv || (ov == bv && ob < best)) { bv = ov; best = ob; }
-      }
-      if (tid == 0) piv = best;
+  mat_mul(X, X, X2, n);
+  mat_mul(X2, X, X3, n);
+  mat_mul(X2, X2, X4, n);
+  // Taylor coefficients c_k = 1/k!, k = 0..18; blocks B_i = sum_{r<4} c_{4i+r} X^r,
+  // T(X) = B_0 + X^4 (B_1 + X^4 (B_2 + X^4 (B_3 + X^4 B_4))), B_4 = c_16 + c_17 X + c_18 X^2
+  double c[19];
+  c[0] = 1.0;
+  for (int q = 1; q < 19; ++q) c[q] = c[q - 1] / q;
+  auto block = [&](int i, double* dst) {
+    const double a0 = c[4 * i], a1 = (4 * i + 1 < 19) ? c[4 * i + 1] : 0.0;
+    const double a2 = (4 * i + 2 < 19) ? c[4 * i + 2] : 0.0, a3 = (4 * i + 3 < 19) ? c[4 * i + 3] : 0.0;
+    for (int t = tid; t < nn; t += PHI_T) {
+      const int r = t % n, jj = t / n;
+      dst[t] = a1 * X[t] + a2 * X2[t] + a3 * X3[t] + (r == jj ? a0 : 0.0);
     }
     __syncthreads();
-    const int pr = piv;
-    if (pr != c) {
-      for (int jj = tid; jj < n; jj += PHI_T) {
-        double t1 = P[jj * n + c]; P[jj * n + c] = P[jj * n + pr]; P[jj * n + pr] = t1;
-        double t2 = Q[jj * n + c]; Q[jj * n + c] = Q[jj * n + pr]; Q[jj * n + pr] = t2;
-      }
-    }
-    __syncthreads();
-    const double inv = 1.0 / P[c * n + c];
-    const int rem = n - c - 1;
-    // eliminate rows r > c: columns > c of P and all columns of Q
-    for (int t = tid; t < rem * (n - c - 1 + n); t += PHI_T) {
-      const int r = c + 1 + t % rem;
-      const int cc = t / rem;  // 0..(n-c-2) -> P column c+1+cc ; then Q columns
-      const double l = P[c * n + r] * inv;
-      if (cc < n - c - 1) {
-        const int col = c + 1 + cc;
-        P[col * n + r] -= l * P[col * n + c];
-      } else {
-        const int col = cc - (n - c - 1);
-        Q[col * n + r] -= l * Q[col * n + c];
-      }
-    }
-    __syncthreads();
-  }
-  for (int c = n - 1; c >= 0; --c) {
-    const double inv = 1.0 / P[c * n + c];
-    for (int jj = tid; jj < n; jj += PHI_T) Q[jj * n + c] *= inv;
-    __syncthreads();
-    for (int t = tid; t < c * n; t += PHI_T) {
-      const int r = t % c, jj = t / c;
-      Q[jj * n + r] -= P[c * n + r] * Q[jj * n + c];
-    }
-    __syncthreads();
-  }
-  // squaring: X <- X^2, s times (ping-pong between Q and T1)
-  double* X = Q;
-  double* Y = T1;
+  };
+  block(4, T0);                      // T0 = B_4
+  block(3, Bq);
+  mat_mul_add(X4, T0, Bq, T1, n);    // T1 = B_3 + X^4 B_4
+  block(2, Bq);
+  mat_mul_add(X4, T1, Bq, T0, n);    // T0 = B_2 + X^4 T1
+  block(1, Bq);
+  mat_mul_add(X4, T0, Bq, T1, n);    // T1 = B_1 + X^4 T0
+  block(0, Bq);
+  mat_mul_add(X4, T1, Bq, T0, n);    // T0 = B_0 + X^4 T1 = T(X)
+  double* P = T0;
+  double* Q = T1;
   for (int it = 0; it < s; ++it) {
-    mat_mul(X, X, Y, n);
-    double* t = X; X = Y; Y = t;
+    mat_mul(P, P, Q, n);
+    double* t = P; P = Q; Q = t;
   }
   const int col = (k >= 1) ? n - 1 : 0;
   const double beta = ks->beta;
-  for (int i = tid; i < KMAX + 4; i += PHI_T) ks->y[i] = (i < m) ? beta * X[col * n + i] : 0.0;
+  for (int i = tid; i < KMAX + 4; i += PHI_T) ks->y[i] = (i < m) ? beta * P[col * n + i] : 0.0;
 }
 
 __global__ __launch_bounds__(PHI_T) void hess_phi_lds(KState* ks, const double* dtp, int k) {
@@ -551,24 +493,21 @@ void k_cast(const TA* a, TB* b, size_t n, hipStream_t st) {
   hipLaunchKernelGGL((cast_kernel<TA, TB>), dim3(blocks), dim3(256), 0, st, a, b, n);
 }
 
-__global__ __launch_bounds__(RT) void sumsq_kernel(const double* __restrict__ x, size_t n, double* out, int mode,
-                                                   double* part, unsigned* counter) {
+__global__ __launch_bounds__(RT) void sumsq_kernel(const double* __restrict__ x, size_t n, double* part) {
   double acc[1] = {0.0};
   for (size_t i = (size_t)blockIdx.x * RT + threadIdx.x; i < n; i += (size_t)gridDim.x * RT) acc[0] += x[i] * x[i];
   block_partials<1>(acc, 1, part);
-  if (arrive_last(counter)) {
-    if (threadIdx.x < 64) {
-      double s = col_sum(part, 0, gridDim.x);
-      if (threadIdx.x == 0) {
-        *out = mode ? sqrt(s) : s;
-        *counter = 0u;
-      }
-    }
-  }
+}
+__global__ __launch_bounds__(64) void sumsq_finalize(const double* part, int nblk, double* out, int mode) {
+  const double s = col_sum(part, 0, nblk);
+  if (threadIdx.x == 0) *out = mode ? sqrt(s) : s;
 }
 void k_sumsq(const double* x, size_t n, double* out, int mode, double* part, unsigned* counter,
              hipStream_t st) {
-  hipLaunchKernelGGL(sumsq_kernel, dim3(gs_blocks(n)), dim3(RT), 0, st, x, n, out, mode, part, counter);
+  (void)counter;
+  const int nb = (int)gs_blocks(n);
+  hipLaunchKernelGGL(sumsq_kernel, dim3(nb), dim3(RT), 0, st, x, n, part);
+  hipLaunchKernelGGL(sumsq_finalize, dim3(1), dim3(64), 0, st, part, nb, out, mode);
 }
 
 __global__ void fd_eps_kernel(const double* unorm, const double* vnorm, double c0, double* eps) {

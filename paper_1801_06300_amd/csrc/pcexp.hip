@@ -228,7 +228,7 @@ WsLayout ws_layout(const pcexp_ctx* c, int m, int k, int prec) {
   const size_t vb = c->Kint * sizeof(double);
   L.ks1 = take(sizeof(KState));
   L.ks2 = take(sizeof(KState));
-  L.part = take((size_t)512 * (KMAX + 2) * sizeof(double));
+  L.part = take((size_t)3 * 512 * (KMAX + 2) * sizeof(double));
   const size_t nphi = (size_t)(m + (k > 0 ? k : 0));
   L.phi = take(7 * nphi * nphi * sizeof(double));
   L.scal = take(64 * sizeof(double));
@@ -307,7 +307,7 @@ pcexp_status alloc_common(pcexp_ctx* c, hipStream_t st) {
     if (!dalloc(c, &c->io[i], c->Kint)) return fail(c, PCEXP_E_HIP, "hipMalloc failed");
   for (int i = 0; i < 2; ++i)
     if (!dalloc(c, &c->io32[i], c->Kint)) return fail(c, PCEXP_E_HIP, "hipMalloc failed");
-  c->part_len = (size_t)512 * (KMAX + 2);
+  c->part_len = (size_t)3 * 512 * (KMAX + 2);
   size_t eb = (size_t)(c->nE + 255) / 256 * 6;
   if (eb > c->part_len) c->part_len = eb;
   if (!dalloc(c, &c->part, c->part_len)) return fail(c, PCEXP_E_HIP, "hipMalloc failed");
