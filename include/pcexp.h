@@ -166,9 +166,9 @@ pcexp_status pcexp_conserved_totals(pcexp_ctx* ctx, const double* u, double* out
                                     void* stream);
 
 /* out = Phi_k(dt J(u_lin)) b by the Krylov projection of dimension m (Sec. 2.2,
- * eqs. (vm)-(final)): Arnoldi with classical Gram-Schmidt and one full
+ * eqs. (vm)-(final)): Arnoldi with classical Gram-Schmidt and a delayed
  * re-orthogonalisation pass, phi_k(dt H_m) e_1 from the exponential of the
- * augmented (m+k) matrix (Pade 13, scaling and squaring, on the device).
+ * augmented (m+k) matrix (scaled Taylor polynomial and squaring, on the device).
  * No dt prefactor (k = 0 gives exp(dt J) b).  out != b.  info may be NULL; if
  * not, the call synchronises and fills it.  Breakdown is not an error. */
 pcexp_status pcexp_arnoldi_phi(pcexp_ctx* ctx, const double* u_lin, const double* b, double dt,
@@ -188,8 +188,9 @@ pcexp_status pcexp_step(pcexp_ctx* ctx, double* u, double dt, double cfl, int32_
  * op = 0: disable; op = 2: synchronise and write, for each class c in
  * [0, PCEXP_PROF_NCLASS), out[3c] = total milliseconds, out[3c+1] = launches,
  * out[3c+2] = algorithmic bytes moved (reads + writes the operation needs).
- * Classes: 0 residual, 1 JVP, 2 Gram-Schmidt dots, 3 GS update + dots,
- * 4 GS update + norm, 5 Hessenberg phi, 6 Krylov combination, 7 other. */
+ * Classes: 0 residual, 1 JVP, 2 Arnoldi orthogonalisation (reduction,
+ * one-block finalisation and update of one iteration), 3-4 unused,
+ * 5 Hessenberg phi, 6 Krylov combination, 7 other. */
 #define PCEXP_PROF_NCLASS 8
 pcexp_status pcexp_profile(pcexp_ctx* ctx, int32_t op, double* out);
 

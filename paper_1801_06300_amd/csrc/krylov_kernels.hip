@@ -105,11 +105,11 @@ __global__ __launch_bounds__(RT) void start_kernel(const double* __restrict__ b,
     V0[i] = (TV)x;
     acc[0] += x * x;
   }
-  block_partials<1>(acc, 1, pbuf(part, 2));
+  block_partials<1>(acc, 1, part);
 }
 
 __global__ __launch_bounds__(64) void start_finalize(KState* ks, const double* part, int nblk) {
-  const double s = col_sum(pbuf(part, 2), 0, nblk);
+  const double s = col_sum(part, 0, nblk);
   if (threadIdx.x == 0) {
     const double beta = sqrt(s);
     ks->beta = beta;
@@ -130,175 +130,262 @@ void k_start(const double* b, TV* V0, size_t n, KState* ks, double* part, hipStr
 }
 
 // Vector loads of the Gram-Schmidt kernels are unconditional: slots beyond
-// the live vectors re-read the last live vector (an L1/L2 hit) and get a zero
-// coefficient, so the compiler can keep all NV loads of an element in flight.
-__device__ __forceinline__ int clampv(int i, int nvec) { return i < nvec ? i : nvec - 1; }
+// the live vectors re-read the last live vector (an L1/L2 hit) and their
+// results are discarded, so the compiler can keep all loads of an element in
+// flight.
+__device__ __forceinline__ int clampv(int i, int nq) { return i < nq ? i : (nq > 0 ? nq - 1 : 0); }
 
-// Iteration j (vectors V_0..V_j live, w stored in slot V_{j+1}):
-//   dots:         raw1_i = V_i . w, |w|^2                         -> partials 0
-//   coeff:        hcol_i = sigma_i^2 raw1_i                          (one block)
-//   update_dots:  w -= sum hcol_i V_i;  raw2_i = V_i . w             -> partials 1
-//   coeff:        hcol_i = sigma_i^2 raw2_i                          (one block)
-//   update_norm:  w -= sum hcol_i V_i;  |w|^2                        -> partials 2
-//   finalize:     H[i][j] = sigma_i (raw1_i + raw2_i), h_{j+1,j} = |w|,
-//                 breakdown test, sigma_{j+1} = 1/h_{j+1,j}          (one block)
-template <typename TV, int NV>
-__global__ __launch_bounds__(RT) void dots_kernel(const TV* __restrict__ V, size_t ld, int j, size_t n,
+// Iteration j.  Final vectors q_i = sigma_i V_i (i < j) are orthonormal; slot j
+// holds U, the once-orthogonalised next vector with tentative scale sigma_j
+// (u = sigma_j U, |u| ~ 1); slot j+1 holds W = J u.
+//   reduce:    V_i.U, V_i.W (i < j), U.U, U.W, W.W             (one pass)
+//   finalize:  s = Q^T u, rho^2 = |u|^2 - |s|^2, q_j = (u - Q s)/rho;
+//              column j-1 of H corrected by nu s and nu rho (nu = |U|
+//              estimate of the previous iteration); J q_j = (W - J Q s)/rho
+//              with J Q s from the Arnoldi relation of the finished columns;
+//              h = [Q q_j]^T J q_j; next U' = J q_j - [Q q_j] h with
+//              |U'|^2 = |J q_j|^2 - |h|^2 (Pythagoras, tentative)   (one block)
+//   update:    V_j <- U - sum e_i V_i;  V_{j+1} <- W/rho - a U - sum b_i V_i
+//              (one pass, both vectors from the same loads)
+// Column j of H stays tentative until the next iteration (or the closing
+// pass) adds nu' s'.
+template <typename TV, int NV, bool CLOSE>
+__global__ __launch_bounds__(RT) void dcgs_reduce(const TV* __restrict__ V, size_t ld, int j, size_t n,
                                                   const KState* ks, double* part) {
   if (ks->done) return;
-  const int nvec = j + 1;
-  const TV* w = V + (size_t)(j + 1) * ld;
-  double acc[NV];
-  double aw = 0.0;
+  const int nq = j;                    // final vectors before U
+  const TV* U = V + (size_t)j * ld;
+  const TV* W = V + (size_t)(j + 1) * ld;
+  constexpr int NA = CLOSE ? NV + 1 : 2 * NV + 3;
+  double acc[NA];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NA; ++i) acc[i] = 0.0;
   for (size_t idx = (size_t)blockIdx.x * RT + threadIdx.x; idx < n; idx += (size_t)gridDim.x * RT) {
-    const double wv = (double)w[idx];
+    const double u = (double)U[idx];
+    const double w = CLOSE ? 0.0 : (double)W[idx];
     TV vr[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) vr[i] = V[(size_t)clampv(i, nvec) * ld + idx];
+    for (int i = 0; i < NV; ++i) vr[i] = V[(size_t)clampv(i, nq) * ld + idx];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += (double)vr[i] * wv;
-    aw += wv * wv;
+    for (int i = 0; i < NV; ++i) {
+      acc[i] += (double)vr[i] * u;
+      if (!CLOSE) acc[NV + i] += (double)vr[i] * w;
+    }
+    if (CLOSE) {
+      acc[NV] += u * u;
+    } else {
+      acc[2 * NV] += u * u;
+      acc[2 * NV + 1] += u * w;
+      acc[2 * NV + 2] += w * w;
+    }
   }
-  // block partials: columns 0..nvec-1 = projections, column nvec = |w|^2
-  double* out = pbuf(part, 0);
-  __shared__ double red[RW][NV + 1];
+  // columns: [0, nq) V.U; then (not CLOSE) [nq, 2nq) V.W; then U.U, U.W, W.W
+  __shared__ double red[RW][NA];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    if (i < nvec) {
+  for (int i = 0; i < NA; ++i) {
+    const bool live = (i < NV) ? (i < nq) : (CLOSE || i >= 2 * NV || (i - NV) < nq);
+    if (live) {
       double a = wave_sum(acc[i]);
       if (lane == 0) red[wid][i] = a;
     }
   }
-  double a = wave_sum(aw);
-  if (lane == 0) red[wid][NV] = a;
   __syncthreads();
-  for (int i = threadIdx.x; i <= nvec; i += RT) {
-    const int src = (i == nvec) ? NV : i;
+  const int ncol = CLOSE ? nq + 1 : 2 * nq + 3;
+  for (int c = threadIdx.x; c < ncol; c += RT) {
+    int src;
+    if (c < nq) src = c;
+    else if (!CLOSE && c < 2 * nq) src = NV + (c - nq);
+    else src = (CLOSE ? NV : 2 * NV) + (c - (CLOSE ? nq : 2 * nq));
     double s = 0.0;
 #pragma unroll
     for (int w2 = 0; w2 < RW; ++w2) s += red[w2][src];
-    out[(size_t)i * PLD + blockIdx.x] = s;
+    part[(size_t)c * PLD + blockIdx.x] = s;
   }
 }
 
-template <typename TV, int NV, int IN, int OUT, bool DOTS>
-__global__ __launch_bounds__(RT) void update_kernel(TV* __restrict__ V, size_t ld, int j, size_t n,
-                                                    const KState* ks, double* part) {
+__global__ __launch_bounds__(RT) void dcgs_finalize(KState* ks, const double* part, int j, int nblk) {
   if (ks->done) return;
-  const int nvec = j + 1;
-  __shared__ double hs[NV];
-  for (int i = threadIdx.x; i < NV; i += RT) hs[i] = (i < nvec) ? ks->hcol[i] : 0.0;
-  __syncthreads();
-  TV* w = V + (size_t)(j + 1) * ld;
-  double acc[DOTS ? NV : 1];
-#pragma unroll
-  for (int i = 0; i < (DOTS ? NV : 1); ++i) acc[i] = 0.0;
-  for (size_t idx = (size_t)blockIdx.x * RT + threadIdx.x; idx < n; idx += (size_t)gridDim.x * RT) {
-    TV vr[NV];
-    double wv = (double)w[idx];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) vr[i] = V[(size_t)clampv(i, nvec) * ld + idx];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) wv -= hs[i] * (double)vr[i];
-    const TV ws = (TV)wv;
-    w[idx] = ws;
-    const double wq = (double)ws;
-    if constexpr (DOTS) {
-#pragma unroll
-      for (int i = 0; i < NV; ++i) acc[i] += (double)vr[i] * wq;
-    } else {
-      acc[0] += wq * wq;
-    }
-  }
-  if constexpr (DOTS) block_partials<NV>(acc, nvec, pbuf(part, OUT));
-  else block_partials<1>(acc, 1, pbuf(part, OUT));
-}
-
-__global__ __launch_bounds__(RT) void finalize_kernel(KState* ks, const double* part, int j, int nblk) {
-  if (ks->done) return;
-  const int nvec = j + 1;
-  __shared__ double r1[KMAX + 1], r2[KMAX + 1];
-  __shared__ double nrm;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int c = wid; c <= nvec; c += RW) {
-    const double s = col_sum(pbuf(part, 0), c, nblk);
-    if (lane == 0) r1[c] = s;
-  }
-  for (int c = wid; c <= nvec; c += RW) {
-    const double s = (c < nvec) ? col_sum(pbuf(part, 1), c, nblk) : col_sum(pbuf(part, 2), 0, nblk);
-    if (lane == 0) {
-      if (c < nvec) r2[c] = s;
-      else nrm = s;
-    }
+  const int nq = j;
+  __shared__ double col[2 * KMAX + 3];
+  __shared__ double s[KMAX], z[KMAX], g[KMAX];
+  __shared__ double rho_s;
+  __shared__ int stop;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int c = wid; c < 2 * nq + 3; c += RW) {
+    const double v = col_sum(part, c, nblk);
+    if (lane == 0) col[c] = v;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int c = 0; c < nvec; ++c) ks->H[(size_t)j * KLD + c] = ks->sigma[c] * (r1[c] + r2[c]);
-    ks->wnorm = sqrt(r1[nvec]);
-    const double h = sqrt(nrm);
-    ks->H[(size_t)j * KLD + j + 1] = h;
-    ks->hlast = h;
+  if (wid != 0) return;                 // the O(j^2) algebra runs on one wave, lane l <-> row l
+  double* H = ks->H;
+  const double eta = ks->eta;
+  const double sj = ks->sigma[j];
+  const bool live = lane < nq;
+  const double sl = live ? ks->sigma[lane] * sj * col[lane] : 0.0;
+  const double zl = live ? ks->sigma[lane] * col[nq + lane] : 0.0;
+  if (live) { s[lane] = sl; z[lane] = zl; }
+  const double ss = wave_sum(sl * sl);
+  const double alpha = sj * sj * col[2 * nq];
+  const double zeta = sj * col[2 * nq + 1];
+  const double omega = col[2 * nq + 2];
+  if (lane == 0) {
+    stop = 0;
+    double rho = 1.0;
+    if (j > 0) {
+      const double r2 = alpha - ss;
+      rho = r2 > 0.0 ? sqrt(r2) : 0.0;
+      const double hjj1 = ks->nu * rho;
+      H[(size_t)(j - 1) * KLD + j] = hjj1;
+      ks->hlast = hjj1;
+      if (!(hjj1 > eta * ks->wnorm)) {  // v_j lies in the span: stop with m_eff = j
+        ks->breakdown = 1;
+        ks->done = 1;
+        ks->m_eff = j;
+        stop = 1;
+      }
+    }
+    rho_s = rho;
+  }
+  // finish column j-1 (each lane keeps its own corrected entry: no global read-after-write)
+  double hcol_new = 0.0;
+  if (j > 0 && live) {
+    hcol_new = H[(size_t)(j - 1) * KLD + lane] + ks->nu * sl;
+    H[(size_t)(j - 1) * KLD + lane] = hcol_new;
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (stop) return;
+  const double rho = rho_s;
+  // J Q s from the finished columns: g_l = sum_i H[l][i] s_i, c = h_{j,j-1} s_{j-1}
+  double gl = 0.0;
+  if (live) {
+    for (int i = (lane > 0 ? lane - 1 : 0); i < nq - 1; ++i) gl += H[(size_t)i * KLD + lane] * s[i];
+    gl += hcol_new * s[nq - 1];
+  }
+  const double gz = wave_sum(gl * zl), gg = wave_sum(gl * gl), sz = wave_sum(sl * zl);
+  const double c = (j > 0) ? ks->nu * rho * s[j - 1] : 0.0;
+  const double ir = 1.0 / rho;
+  const double qW = (zeta - sz) * ir;
+  const double hl = live ? (zl - gl) * ir : 0.0;
+  const double hj = (qW - c) * ir;
+  const double hh = wave_sum(hl * hl) + hj * hj;
+  const double jq2 = (omega - 2.0 * (gz + c * qW) + gg + c * c) * ir * ir;
+  const double wn = sqrt(jq2 > 0.0 ? jq2 : 0.0);
+  const double t = c * ir + hj;
+  if (live) {
+    H[(size_t)j * KLD + lane] = hl;
+    ks->hcol[lane] = sl * ks->sigma[lane] / sj;
+    ks->coefb[lane] = ks->sigma[lane] * (gl * ir + hl - t * sl * ir);
+  }
+  if (lane == 0) {
+    H[(size_t)j * KLD + j] = hj;
+    ks->wnorm = wn;
     ks->m_eff = j + 1;
-    if (!(h > ks->eta * ks->wnorm)) {
+    ks->acoef = t * sj * ir;
+    ks->rinv = ir;
+    ks->sigma[j] = sj * ir;
+    const double nu2 = jq2 - hh;
+    if (!(nu2 > (eta * wn) * (eta * wn))) {   // J q_j lies in the span: m_eff = j + 1
       ks->breakdown = 1;
       ks->done = 1;
+      ks->hlast = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+      H[(size_t)j * KLD + j + 1] = ks->hlast;
     } else {
-      ks->sigma[j + 1] = 1.0 / h;
+      const double nup = sqrt(nu2);
+      ks->nu = nup;
+      ks->sigma[j + 1] = 1.0 / nup;
+      H[(size_t)j * KLD + j + 1] = nup;   // tentative; corrected by the next iteration
     }
   }
 }
 
-// Launch with the smallest vector-count bucket that holds j + 1 vectors.
-#define PCEXP_GS_DISPATCH(KERNEL, ...)                                                          \
-  do {                                                                                          \
-    const int nv_ = j + 1;                                                                      \
-    dim3 g_(gs_blocks(n)), b_(RT);                                                              \
-    if (nv_ <= 4) hipLaunchKernelGGL((KERNEL(4)), g_, b_, 0, st, __VA_ARGS__);                  \
-    else if (nv_ <= 8) hipLaunchKernelGGL((KERNEL(8)), g_, b_, 0, st, __VA_ARGS__);             \
-    else if (nv_ <= 12) hipLaunchKernelGGL((KERNEL(12)), g_, b_, 0, st, __VA_ARGS__);           \
-    else if (nv_ <= 16) hipLaunchKernelGGL((KERNEL(16)), g_, b_, 0, st, __VA_ARGS__);           \
-    else if (nv_ <= 20) hipLaunchKernelGGL((KERNEL(20)), g_, b_, 0, st, __VA_ARGS__);           \
-    else if (nv_ <= 24) hipLaunchKernelGGL((KERNEL(24)), g_, b_, 0, st, __VA_ARGS__);           \
-    else if (nv_ <= 28) hipLaunchKernelGGL((KERNEL(28)), g_, b_, 0, st, __VA_ARGS__);           \
-    else if (nv_ <= 32) hipLaunchKernelGGL((KERNEL(32)), g_, b_, 0, st, __VA_ARGS__);           \
-    else if (nv_ <= 40) hipLaunchKernelGGL((KERNEL(40)), g_, b_, 0, st, __VA_ARGS__);           \
-    else if (nv_ <= 48) hipLaunchKernelGGL((KERNEL(48)), g_, b_, 0, st, __VA_ARGS__);           \
-    else if (nv_ <= 56) hipLaunchKernelGGL((KERNEL(56)), g_, b_, 0, st, __VA_ARGS__);           \
-    else hipLaunchKernelGGL((KERNEL(64)), g_, b_, 0, st, __VA_ARGS__);                          \
-  } while (0)
-
-#define PCEXP_K_DOTS(NV) dots_kernel<TV, NV>
-#define PCEXP_K_UPD(NV) update_kernel<TV, NV, 0, 1, true>
-#define PCEXP_K_NRM(NV) update_kernel<TV, NV, 1, 2, false>
-
-// One block: the coefficients on the stored vectors for the next update,
-// hcol[c] = sigma_c^2 * (V_c . w), from the partials of buffer `which`.
-__global__ __launch_bounds__(RT) void coeff_kernel(KState* ks, const double* part, int which, int nvec, int nblk) {
-  if (ks->done) return;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int c = wid; c < nvec; c += RW) {
-    const double s = col_sum(pbuf(part, which), c, nblk);
-    if (lane == 0) ks->hcol[c] = s * ks->sigma[c] * ks->sigma[c];
+template <typename TV, int NV>
+__global__ __launch_bounds__(RT) void dcgs_update(TV* __restrict__ V, size_t ld, int j, size_t n, const KState* ks) {
+  if (ks->m_eff <= j) return;          // q_j is not part of the basis
+  const int nq = j;
+  __shared__ double e[NV], b[NV];
+  for (int i = threadIdx.x; i < NV; i += RT) {
+    e[i] = i < nq ? ks->hcol[i] : 0.0;
+    b[i] = i < nq ? ks->coefb[i] : 0.0;
+  }
+  __syncthreads();
+  const double a = ks->acoef, ir = ks->rinv;
+  TV* U = V + (size_t)j * ld;
+  TV* W = V + (size_t)(j + 1) * ld;
+  for (size_t idx = (size_t)blockIdx.x * RT + threadIdx.x; idx < n; idx += (size_t)gridDim.x * RT) {
+    TV vr[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) vr[i] = V[(size_t)clampv(i, nq) * ld + idx];
+    const double u = (double)U[idx];
+    const double w = (double)W[idx];
+    double un = u, wn = w * ir - a * u;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      un -= e[i] * (double)vr[i];
+      wn -= b[i] * (double)vr[i];
+    }
+    U[idx] = (TV)un;
+    W[idx] = (TV)wn;
   }
 }
 
-template <typename TV>
-void k_dots(const TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st) {
-  PCEXP_GS_DISPATCH(PCEXP_K_DOTS, V, ld, j, n, ks, part);
-  hipLaunchKernelGGL(coeff_kernel, dim3(1), dim3(RT), 0, st, ks, part, 0, j + 1, (int)gs_blocks(n));
+__global__ __launch_bounds__(RT) void dcgs_close_finalize(KState* ks, const double* part, int m, int nblk) {
+  if (ks->done) return;
+  __shared__ double col[KMAX + 1];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int c = wid; c <= m; c += RW) {
+    const double v = col_sum(part, c, nblk);
+    if (lane == 0) col[c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double sm = ks->sigma[m], nu = ks->nu;
+  double ss = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const double si = ks->sigma[i] * sm * col[i];
+    ks->H[(size_t)(m - 1) * KLD + i] += nu * si;
+    ss += si * si;
+  }
+  const double r2 = sm * sm * col[m] - ss;
+  const double h = nu * (r2 > 0.0 ? sqrt(r2) : 0.0);
+  ks->H[(size_t)(m - 1) * KLD + m] = h;
+  ks->hlast = h;
 }
+
+// Launch with the smallest vector-count bucket that holds nq (>= 1) vectors.
+#define PCEXP_NV_DISPATCH(KERNEL, NQ, ...)                                                     \
+  do {                                                                                         \
+    const int nv_ = (NQ) > 0 ? (NQ) : 1;                                                       \
+    dim3 g_(gs_blocks(n)), b_(RT);                                                             \
+    if (nv_ <= 4) hipLaunchKernelGGL((KERNEL(4)), g_, b_, 0, st, __VA_ARGS__);                 \
+    else if (nv_ <= 8) hipLaunchKernelGGL((KERNEL(8)), g_, b_, 0, st, __VA_ARGS__);            \
+    else if (nv_ <= 12) hipLaunchKernelGGL((KERNEL(12)), g_, b_, 0, st, __VA_ARGS__);          \
+    else if (nv_ <= 16) hipLaunchKernelGGL((KERNEL(16)), g_, b_, 0, st, __VA_ARGS__);          \
+    else if (nv_ <= 20) hipLaunchKernelGGL((KERNEL(20)), g_, b_, 0, st, __VA_ARGS__);          \
+    else if (nv_ <= 24) hipLaunchKernelGGL((KERNEL(24)), g_, b_, 0, st, __VA_ARGS__);          \
+    else if (nv_ <= 28) hipLaunchKernelGGL((KERNEL(28)), g_, b_, 0, st, __VA_ARGS__);          \
+    else if (nv_ <= 32) hipLaunchKernelGGL((KERNEL(32)), g_, b_, 0, st, __VA_ARGS__);          \
+    else if (nv_ <= 40) hipLaunchKernelGGL((KERNEL(40)), g_, b_, 0, st, __VA_ARGS__);          \
+    else if (nv_ <= 48) hipLaunchKernelGGL((KERNEL(48)), g_, b_, 0, st, __VA_ARGS__);          \
+    else if (nv_ <= 56) hipLaunchKernelGGL((KERNEL(56)), g_, b_, 0, st, __VA_ARGS__);          \
+    else hipLaunchKernelGGL((KERNEL(64)), g_, b_, 0, st, __VA_ARGS__);                         \
+  } while (0)
+
+#define PCEXP_K_RED(NV) dcgs_reduce<TV, NV, false>
+#define PCEXP_K_CLOSE(NV) dcgs_reduce<TV, NV, true>
+#define PCEXP_K_UPD(NV) dcgs_update<TV, NV>
+
 template <typename TV>
-void k_update_dots(TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st) {
-  PCEXP_GS_DISPATCH(PCEXP_K_UPD, V, ld, j, n, ks, part);
-  hipLaunchKernelGGL(coeff_kernel, dim3(1), dim3(RT), 0, st, ks, part, 1, j + 1, (int)gs_blocks(n));
+void k_arnoldi_iter(TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st) {
+  PCEXP_NV_DISPATCH(PCEXP_K_RED, j, V, ld, j, n, ks, part);
+  hipLaunchKernelGGL(dcgs_finalize, dim3(1), dim3(RT), 0, st, ks, part, j, (int)gs_blocks(n));
+  PCEXP_NV_DISPATCH(PCEXP_K_UPD, j, V, ld, j, n, ks);
 }
+
 template <typename TV>
-void k_update_norm(TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st) {
-  PCEXP_GS_DISPATCH(PCEXP_K_NRM, V, ld, j, n, ks, part);
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(RT), 0, st, ks, part, j, (int)gs_blocks(n));
+void k_arnoldi_close(TV* V, size_t ld, int m, size_t n, KState* ks, double* part, hipStream_t st) {
+  PCEXP_NV_DISPATCH(PCEXP_K_CLOSE, m, V, ld, m, n, ks, part);
+  hipLaunchKernelGGL(dcgs_close_finalize, dim3(1), dim3(RT), 0, st, ks, part, m, (int)gs_blocks(n));
 }
 
 // ------------------------------------------------------------ Hessenberg phi
@@ -555,12 +642,10 @@ void k_gemv(const T* A, const T* v, T* out, int n, const double* vscale, const i
 // explicit instantiations
 template void k_start<double>(const double*, double*, size_t, KState*, double*, hipStream_t);
 template void k_start<float>(const double*, float*, size_t, KState*, double*, hipStream_t);
-template void k_dots<double>(const double*, size_t, int, size_t, KState*, double*, hipStream_t);
-template void k_dots<float>(const float*, size_t, int, size_t, KState*, double*, hipStream_t);
-template void k_update_dots<double>(double*, size_t, int, size_t, KState*, double*, hipStream_t);
-template void k_update_dots<float>(float*, size_t, int, size_t, KState*, double*, hipStream_t);
-template void k_update_norm<double>(double*, size_t, int, size_t, KState*, double*, hipStream_t);
-template void k_update_norm<float>(float*, size_t, int, size_t, KState*, double*, hipStream_t);
+template void k_arnoldi_iter<double>(double*, size_t, int, size_t, KState*, double*, hipStream_t);
+template void k_arnoldi_iter<float>(float*, size_t, int, size_t, KState*, double*, hipStream_t);
+template void k_arnoldi_close<double>(double*, size_t, int, size_t, KState*, double*, hipStream_t);
+template void k_arnoldi_close<float>(float*, size_t, int, size_t, KState*, double*, hipStream_t);
 template void k_combine<double, double>(const double*, size_t, const KState*, const double*, double*, double*,
                                         double, const double*, size_t, hipStream_t);
 template void k_combine<float, float>(const float*, size_t, const KState*, const double*, double*, float*,

@@ -1,16 +1,18 @@
 // Krylov / Arnoldi kernels for gfx950 (paper Sec. 2.2, eqs. (vm), (vm1),
 // (vm2), (final1), (final)) and small utility kernels.
 //
-// Arnoldi with classical Gram-Schmidt and one full re-orthogonalisation pass
-// (CGS2).  The Krylov basis lives in the caller's workspace as m+1 vectors
-// V_0..V_m of stride ld; V_j is stored unnormalised and used as sigma_j V_j
-// (sigma_j = 1/h_{j,j-1}), which removes a normalisation pass: the JVP writes
-// w = J (sigma_j V_j) straight into the slot V_{j+1} and the Gram-Schmidt
-// kernels update it in place.  Dot products accumulate in FP64 whatever the
-// storage type of V; every grid reduction is a per-block partial followed by
-// a fixed-order reduction in the last block to finish (no float atomics, so
-// results are bitwise reproducible).  After a breakdown every later launch of
-// the iteration is a no-op (device flag `done`).
+// Arnoldi with classical Gram-Schmidt and delayed re-orthogonalisation
+// (CGS with the second pass of vector j folded into iteration j+1, as in the
+// low-synchronisation DCGS2 schemes): per iteration one fused reduction pass
+// and one fused update pass over the basis.  The Krylov basis lives in the
+// caller's workspace as m+1 vectors V_0..V_m of stride ld; V_j is stored
+// unnormalised and used as sigma_j V_j, which removes normalisation passes:
+// the JVP writes w = J (sigma_j V_j) straight into the slot V_{j+1}.  Dot
+// products accumulate in FP64 whatever the storage type of V; every grid
+// reduction is a per-block partial followed by a fixed-order reduction in a
+// one-block kernel (no float atomics, so results are bitwise reproducible).
+// After a breakdown every later launch of the iteration is a no-op (device
+// flag `done`).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,7 +26,10 @@ constexpr int GS_THREADS = 256;
 struct KState {
   double H[KLD * KMAX];    // column-major Hessenberg, H[j*KLD + i]
   double sigma[KMAX + 2];  // scale of each stored basis vector
-  double hcol[KMAX + 2];   // projection coefficients of the current pass
+  double hcol[KMAX + 2];   // re-orthogonalisation coefficients of the current vector
+  double coefb[KMAX + 2];  // coefficients of the next vector's update
+  double acoef, rinv;      // next vector = rinv * W - acoef * U - sum coefb_i V_i
+  double nu;               // tentative norm of the stored next vector
   double y[KMAX + 4];      // beta * phi_k(dt H) e_1
   double beta;
   double wnorm;            // |J v_j| before orthogonalisation
@@ -44,12 +49,12 @@ size_t gs_blocks(size_t n);
 void k_init_state(KState* ks, double eta, hipStream_t st);
 template <typename TV>
 void k_start(const double* b, TV* V0, size_t n, KState* ks, double* part, hipStream_t st);
+// Iteration j after the JVP has written W = J(sigma_j V_j) into slot j+1.
 template <typename TV>
-void k_dots(const TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st);
+void k_arnoldi_iter(TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st);
+// After the last iteration: completes column m-1 of H.
 template <typename TV>
-void k_update_dots(TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st);
-template <typename TV>
-void k_update_norm(TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st);
+void k_arnoldi_close(TV* V, size_t ld, int m, size_t n, KState* ks, double* part, hipStream_t st);
 void k_hess_phi(KState* ks, const double* dt, int k, int m, double* scratch, hipStream_t st);
 template <typename TV, typename TX>
 void k_combine(const TV* V, size_t ld, const KState* ks, const double* base, double* out,

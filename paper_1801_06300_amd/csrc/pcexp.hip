@@ -137,7 +137,7 @@ ElemArgs elem_args(const pcexp_ctx* c) {
 
 const double kSqrtEps = 1.4901161193847656e-08;  // sqrt(2^-52)
 
-enum { PC_RES = 0, PC_JVP = 1, PC_DOTS = 2, PC_UPD = 3, PC_NRM = 4, PC_PHI = 5, PC_COMB = 6, PC_OTHER = 7 };
+enum { PC_RES = 0, PC_JVP = 1, PC_GS = 2, PC_PHI = 5, PC_COMB = 6, PC_OTHER = 7 };
 
 // Brackets one launch with events when profiling is on (no-op otherwise).
 struct Prof {
@@ -261,9 +261,13 @@ void arnoldi_run(pcexp_ctx* c, int jvp, int prec, const double* u_lin, const flo
     jvp_int(c, jvp, prec, u_lin, u32, V + (size_t)j * ld, V + (size_t)(j + 1) * ld, &ks->sigma[j], &ks->done,
             Rlin, &ks->fd_eps, st);
     const double vb = (double)c->K * sizeof(TV);
-    { Prof pr(c, st, PC_DOTS, (j + 2) * vb); k_dots<TV>(V, ld, j, n, ks, part, st); }
-    { Prof pr(c, st, PC_UPD, (j + 3) * vb); k_update_dots<TV>(V, ld, j, n, ks, part, st); }
-    { Prof pr(c, st, PC_NRM, (j + 3) * vb); k_update_norm<TV>(V, ld, j, n, ks, part, st); }
+    // reduction pass reads j + 2 vectors; update pass reads j + 2 and writes 2
+    Prof pr(c, st, PC_GS, (2.0 * (j + 2) + 2.0) * vb);
+    k_arnoldi_iter<TV>(V, ld, j, n, ks, part, st);
+  }
+  {
+    Prof pr(c, st, PC_GS, (m + 1.0) * (double)c->K * sizeof(TV));
+    k_arnoldi_close<TV>(V, ld, m, n, ks, part, st);
   }
   { Prof pr(c, st, PC_PHI, 0.0); k_hess_phi(ks, dtp, k, m, phi, st); }
 }
