@@ -9,14 +9,43 @@ namespace pcexp {
 
 constexpr int RT = 512;          // threads per reduction block
 constexpr int RW = RT / 64;      // waves per reduction block
-constexpr int MAXB = 512;        // max reduction blocks (partials per column)
-constexpr int PLD = MAXB;        // partials are column-major: part[col * PLD + block]
+constexpr int PLD = 512;         // partials are column-major: part[col * PLD + block]
+#ifndef PCEXP_RED_BLOCKS
+#define PCEXP_RED_BLOCKS 256
+#endif
+// One 8-wave block per compute unit: the fused Gram-Schmidt passes hold
+// 2 NV + 3 FP64 accumulators per lane, so a second resident block per CU
+// would only add a tail round.
+constexpr int MAXB = PCEXP_RED_BLOCKS;
+static_assert(MAXB <= PLD, "partials per column exceed the partial stride");
 
 size_t gs_blocks(size_t n) {
-  size_t b = (n + RT - 1) / RT;
-  if (b > MAXB) b = MAXB;
+  size_t b = (n + 2 * RT - 1) / (2 * RT);   // the Gram-Schmidt passes take two entries per lane
+  if (b > (size_t)MAXB) b = MAXB;
   if (b < 1) b = 1;
   return b;
+}
+
+// Two consecutive entries per lane: one 16-byte (FP64) or 8-byte (FP32) load.
+template <typename T> struct Pair;
+template <> struct Pair<double> { using type = double2; };
+template <> struct Pair<float> { using type = float2; };
+template <typename T>
+__device__ __forceinline__ void load_pair(const T* base, size_t p, size_t n, double& a, double& b) {
+  const typename Pair<T>::type v = reinterpret_cast<const typename Pair<T>::type*>(base)[p];
+  a = (double)v.x;
+  b = (2 * p + 1 < n) ? (double)v.y : 0.0;   // the slot stride is even, so the load stays in the slot
+}
+template <typename T>
+__device__ __forceinline__ void store_pair(T* base, size_t p, size_t n, double a, double b) {
+  if (2 * p + 1 < n) {
+    typename Pair<T>::type v;
+    v.x = (T)a;
+    v.y = (T)b;
+    reinterpret_cast<typename Pair<T>::type*>(base)[p] = v;
+  } else {
+    base[2 * p] = (T)a;
+  }
 }
 
 __device__ __forceinline__ double wave_sum(double a) {
@@ -43,6 +72,22 @@ __device__ __forceinline__ double col_sum(const double* part, int c, int nblk) {
   double a = 0.0;
   for (int b = lane; b < nblk; b += 64) a += part[(size_t)c * PLD + b];
   return wave_sum(a);
+}
+
+// Fixed-order sums of columns [0, ncol) into col[] by a whole RT-thread
+// block: 8 lanes per column, all loads of a lane independent.
+__device__ __forceinline__ void block_col_sums(const double* part, int ncol, int nblk, double* col) {
+  const int g = threadIdx.x >> 3, sub = threadIdx.x & 7;
+  for (int c0 = 0; c0 < ncol; c0 += RT / 8) {
+    const int c = c0 + g;
+    double a = 0.0;
+    if (c < ncol)
+      for (int b = sub; b < nblk; b += 8) a += part[(size_t)c * PLD + b];
+    a += __shfl_xor(a, 4, 64);
+    a += __shfl_xor(a, 2, 64);
+    a += __shfl_xor(a, 1, 64);
+    if (c < ncol && sub == 0) col[c] = a;
+  }
 }
 
 // Block-reduce NV per-thread accumulators into part[c * PLD + blockIdx.x].
@@ -160,23 +205,25 @@ __global__ __launch_bounds__(RT) void dcgs_reduce(const TV* __restrict__ V, size
   double acc[NA];
 #pragma unroll
   for (int i = 0; i < NA; ++i) acc[i] = 0.0;
-  for (size_t idx = (size_t)blockIdx.x * RT + threadIdx.x; idx < n; idx += (size_t)gridDim.x * RT) {
-    const double u = (double)U[idx];
-    const double w = CLOSE ? 0.0 : (double)W[idx];
-    TV vr[NV];
+  const size_t np = (n + 1) / 2;
+  for (size_t p = (size_t)blockIdx.x * RT + threadIdx.x; p < np; p += (size_t)gridDim.x * RT) {
+    double u0, u1, w0 = 0.0, w1 = 0.0;
+    load_pair(U, p, n, u0, u1);
+    if (!CLOSE) load_pair(W, p, n, w0, w1);
+    double v0[NV], v1[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) vr[i] = V[(size_t)clampv(i, nq) * ld + idx];
+    for (int i = 0; i < NV; ++i) load_pair(V + (size_t)clampv(i, nq) * ld, p, n, v0[i], v1[i]);
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      acc[i] += (double)vr[i] * u;
-      if (!CLOSE) acc[NV + i] += (double)vr[i] * w;
+      acc[i] += v0[i] * u0 + v1[i] * u1;
+      if (!CLOSE) acc[NV + i] += v0[i] * w0 + v1[i] * w1;
     }
     if (CLOSE) {
-      acc[NV] += u * u;
+      acc[NV] += u0 * u0 + u1 * u1;
     } else {
-      acc[2 * NV] += u * u;
-      acc[2 * NV + 1] += u * w;
-      acc[2 * NV + 2] += w * w;
+      acc[2 * NV] += u0 * u0 + u1 * u1;
+      acc[2 * NV + 1] += u0 * w0 + u1 * w1;
+      acc[2 * NV + 2] += w0 * w0 + w1 * w1;
     }
   }
   // columns: [0, nq) V.U; then (not CLOSE) [nq, 2nq) V.W; then U.U, U.W, W.W
@@ -209,12 +256,14 @@ __global__ __launch_bounds__(RT) void dcgs_finalize(KState* ks, const double* pa
   const int nq = j;
   __shared__ double col[2 * KMAX + 3];
   __shared__ double s[KMAX], z[KMAX], g[KMAX];
+  __shared__ double Hs[KMAX * KMAX];   // H[l][i], l < nq, i < nq, row-major (staged once)
   __shared__ double rho_s;
   __shared__ int stop;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int c = wid; c < 2 * nq + 3; c += RW) {
-    const double v = col_sum(part, c, nblk);
-    if (lane == 0) col[c] = v;
+  block_col_sums(part, 2 * nq + 3, nblk, col);
+  for (int t = tid; t < nq * nq; t += RT) {
+    const int i = t / nq, l = t % nq;            // column i, row l (coalesced over l)
+    Hs[l * KMAX + i] = ks->H[(size_t)i * KLD + l];
   }
   __syncthreads();
   if (wid != 0) return;                 // the O(j^2) algebra runs on one wave, lane l <-> row l
@@ -250,7 +299,7 @@ __global__ __launch_bounds__(RT) void dcgs_finalize(KState* ks, const double* pa
   // finish column j-1 (each lane keeps its own corrected entry: no global read-after-write)
   double hcol_new = 0.0;
   if (j > 0 && live) {
-    hcol_new = H[(size_t)(j - 1) * KLD + lane] + ks->nu * sl;
+    hcol_new = Hs[lane * KMAX + (j - 1)] + ks->nu * sl;
     H[(size_t)(j - 1) * KLD + lane] = hcol_new;
   }
   __builtin_amdgcn_wave_barrier();
@@ -259,7 +308,7 @@ __global__ __launch_bounds__(RT) void dcgs_finalize(KState* ks, const double* pa
   // J Q s from the finished columns: g_l = sum_i H[l][i] s_i, c = h_{j,j-1} s_{j-1}
   double gl = 0.0;
   if (live) {
-    for (int i = (lane > 0 ? lane - 1 : 0); i < nq - 1; ++i) gl += H[(size_t)i * KLD + lane] * s[i];
+    for (int i = (lane > 0 ? lane - 1 : 0); i < nq - 1; ++i) gl += Hs[lane * KMAX + i] * s[i];
     gl += hcol_new * s[nq - 1];
   }
   const double gz = wave_sum(gl * zl), gg = wave_sum(gl * gl), sz = wave_sum(sl * zl);
@@ -312,31 +361,30 @@ __global__ __launch_bounds__(RT) void dcgs_update(TV* __restrict__ V, size_t ld,
   const double a = ks->acoef, ir = ks->rinv;
   TV* U = V + (size_t)j * ld;
   TV* W = V + (size_t)(j + 1) * ld;
-  for (size_t idx = (size_t)blockIdx.x * RT + threadIdx.x; idx < n; idx += (size_t)gridDim.x * RT) {
-    TV vr[NV];
+  const size_t np = (n + 1) / 2;
+  for (size_t p = (size_t)blockIdx.x * RT + threadIdx.x; p < np; p += (size_t)gridDim.x * RT) {
+    double v0[NV], v1[NV], u0, u1, w0, w1;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) vr[i] = V[(size_t)clampv(i, nq) * ld + idx];
-    const double u = (double)U[idx];
-    const double w = (double)W[idx];
-    double un = u, wn = w * ir - a * u;
+    for (int i = 0; i < NV; ++i) load_pair(V + (size_t)clampv(i, nq) * ld, p, n, v0[i], v1[i]);
+    load_pair(U, p, n, u0, u1);
+    load_pair(W, p, n, w0, w1);
+    double un0 = u0, un1 = u1, wn0 = w0 * ir - a * u0, wn1 = w1 * ir - a * u1;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      un -= e[i] * (double)vr[i];
-      wn -= b[i] * (double)vr[i];
+      un0 -= e[i] * v0[i];
+      un1 -= e[i] * v1[i];
+      wn0 -= b[i] * v0[i];
+      wn1 -= b[i] * v1[i];
     }
-    U[idx] = (TV)un;
-    W[idx] = (TV)wn;
+    store_pair(U, p, n, un0, un1);
+    store_pair(W, p, n, wn0, wn1);
   }
 }
 
 __global__ __launch_bounds__(RT) void dcgs_close_finalize(KState* ks, const double* part, int m, int nblk) {
   if (ks->done) return;
   __shared__ double col[KMAX + 1];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int c = wid; c <= m; c += RW) {
-    const double v = col_sum(part, c, nblk);
-    if (lane == 0) col[c] = v;
-  }
+  block_col_sums(part, m + 1, nblk, col);
   __syncthreads();
   if (threadIdx.x != 0) return;
   const double sm = ks->sigma[m], nu = ks->nu;
