@@ -134,11 +134,9 @@ void k_init_state(KState* ks, double eta, hipStream_t st) {
   hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(256), 0, st, ks, eta);
 }
 
-// Partial buffers of one Arnoldi run: three column blocks of (KMAX+2) columns.
-__device__ __forceinline__ double* pbuf(double* part, int which) { return part + (size_t)which * (KMAX + 2) * PLD; }
-__device__ __forceinline__ const double* pbuf(const double* part, int which) {
-  return part + (size_t)which * (KMAX + 2) * PLD;
-}
+// The partial buffer of an Arnoldi run holds 3 (KMAX + 2) columns of PLD:
+// the fused pass writes at most 2 (KMAX - 1) + 3 of them.
+static_assert(2 * (KMAX - 1) + 3 <= 3 * (KMAX + 2), "partial columns exceed the buffer");
 
 // ------------------------------------------------- start: V_0 = b, beta = |b|
 template <typename TV>
@@ -194,60 +192,116 @@ __device__ __forceinline__ int clampv(int i, int nq) { return i < nq ? i : (nq >
 //              (one pass, both vectors from the same loads)
 // Column j of H stays tentative until the next iteration (or the closing
 // pass) adds nu' s'.
-template <typename TV, int NV, bool CLOSE>
+// Reduce-scatter butterfly over one wave: step (H, O) halves the values a
+// lane holds, sending H of them to lane ^ O and adding the H it receives.
+// After log2(N) steps (N <= 64) a lane holds one column sum; N - 1 shuffles
+// in all instead of 6 per column.  All indices are compile-time constants.
+template <int H, int O>
+struct Bfly {
+  static __device__ __forceinline__ void run(double* a, int lane, int& col) {
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double send = up ? a[i] : a[i + H];
+      const double keep = up ? a[i + H] : a[i];
+      a[i] = keep + __shfl_xor(send, O, 64);
+    }
+    if (up) col += H;
+    Bfly<H / 2, O / 2>::run(a, lane, col);
+  }
+};
+template <int O> struct Bfly<0, O> {          // fewer columns than lanes: finish with plain shuffles
+  static __device__ __forceinline__ void run(double* a, int, int&) {
+#pragma unroll
+    for (int o = O; o >= 1; o /= 2) a[0] += __shfl_xor(a[0], o, 64);
+  }
+};
+template <int H> struct Bfly<H, 0> {
+  static __device__ __forceinline__ void run(double*, int, int&) {}
+};
+template <> struct Bfly<0, 0> {
+  static __device__ __forceinline__ void run(double*, int, int&) {}
+};
+
+constexpr int pow2_ceil(int x) { return x <= 4 ? 4 : 2 * pow2_ceil((x + 1) / 2); }
+
+// Largest number of basis vectors one reduction block handles; more live
+// vectors are split over blockIdx.y (each chunk re-reads U and W).
+constexpr int CHUNK = 32;
+
+template <typename TV, int PW>
+__device__ __forceinline__ void load_pw(const TV* base, size_t p, size_t n, double* x) {
+  if (PW == 2) load_pair(base, p, n, x[0], x[1]);
+  else x[0] = (double)base[p];
+}
+
+template <typename TV, int NV, int PW, bool CLOSE>
 __global__ __launch_bounds__(RT) void dcgs_reduce(const TV* __restrict__ V, size_t ld, int j, size_t n,
                                                   const KState* ks, double* part) {
   if (ks->done) return;
   const int nq = j;                    // final vectors before U
+  const int i0 = blockIdx.y * NV;      // this block's chunk of them
   const TV* U = V + (size_t)j * ld;
   const TV* W = V + (size_t)(j + 1) * ld;
-  constexpr int NA = CLOSE ? NV + 1 : 2 * NV + 3;
-  double acc[NA];
+  constexpr int NB = CLOSE ? NV : 2 * NV;   // V.U (and V.W) columns of the chunk
+  constexpr int NP = pow2_ceil(NB);
+  constexpr int NX = CLOSE ? 1 : 3;         // U.U (, U.W, W.W)
+  static_assert(NP <= 64, "one butterfly column per lane at most");
+  double acc[NP], ext[NX];
 #pragma unroll
-  for (int i = 0; i < NA; ++i) acc[i] = 0.0;
-  const size_t np = (n + 1) / 2;
+  for (int i = 0; i < NP; ++i) acc[i] = 0.0;
+#pragma unroll
+  for (int i = 0; i < NX; ++i) ext[i] = 0.0;
+  const size_t np = PW == 2 ? (n + 1) / 2 : n;
   for (size_t p = (size_t)blockIdx.x * RT + threadIdx.x; p < np; p += (size_t)gridDim.x * RT) {
-    double u0, u1, w0 = 0.0, w1 = 0.0;
-    load_pair(U, p, n, u0, u1);
-    if (!CLOSE) load_pair(W, p, n, w0, w1);
-    double v0[NV], v1[NV];
+    double u[PW], w[PW], v[NV][PW];
+    load_pw<TV, PW>(U, p, n, u);
+    if (!CLOSE) load_pw<TV, PW>(W, p, n, w);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) load_pair(V + (size_t)clampv(i, nq) * ld, p, n, v0[i], v1[i]);
+    for (int i = 0; i < NV; ++i) load_pw<TV, PW>(V + (size_t)clampv(i0 + i, nq) * ld, p, n, v[i]);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      acc[i] += v0[i] * u0 + v1[i] * u1;
-      if (!CLOSE) acc[NV + i] += v0[i] * w0 + v1[i] * w1;
-    }
-    if (CLOSE) {
-      acc[NV] += u0 * u0 + u1 * u1;
-    } else {
-      acc[2 * NV] += u0 * u0 + u1 * u1;
-      acc[2 * NV + 1] += u0 * w0 + u1 * w1;
-      acc[2 * NV + 2] += w0 * w0 + w1 * w1;
+    for (int k = 0; k < PW; ++k) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        acc[i] += v[i][k] * u[k];
+        if (!CLOSE) acc[NV + i] += v[i][k] * w[k];
+      }
+      ext[0] += u[k] * u[k];
+      if (!CLOSE) {
+        ext[1] += u[k] * w[k];
+        ext[2] += w[k] * w[k];
+      }
     }
   }
-  // columns: [0, nq) V.U; then (not CLOSE) [nq, 2nq) V.W; then U.U, U.W, W.W
-  __shared__ double red[RW][NA];
+  __shared__ double red[RW][NP + NX];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int col = 0;
+  Bfly<NP / 2, 32>::run(acc, lane, col);
 #pragma unroll
-  for (int i = 0; i < NA; ++i) {
-    const bool live = (i < NV) ? (i < nq) : (CLOSE || i >= 2 * NV || (i - NV) < nq);
-    if (live) {
-      double a = wave_sum(acc[i]);
-      if (lane == 0) red[wid][i] = a;
-    }
+  for (int i = 0; i < NX; ++i) ext[i] = wave_sum(ext[i]);
+  if ((lane & (64 / NP - 1)) == 0) red[wid][col] = acc[0];
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NX; ++i) red[wid][NP + i] = ext[i];
   }
   __syncthreads();
-  const int ncol = CLOSE ? nq + 1 : 2 * nq + 3;
-  for (int c = threadIdx.x; c < ncol; c += RT) {
-    int src;
-    if (c < nq) src = c;
-    else if (!CLOSE && c < 2 * nq) src = NV + (c - nq);
-    else src = (CLOSE ? NV : 2 * NV) + (c - (CLOSE ? nq : 2 * nq));
-    double s = 0.0;
+  // partial columns: [0, nq) V.U, then (not CLOSE) [nq, 2nq) V.W, then the extras
+  for (int c = threadIdx.x; c < NB + NX; c += RT) {
+    int g, src;
+    bool live;
+    if (c < NV) {
+      g = i0 + c; live = g < nq; src = c;
+    } else if (c < NB) {
+      g = nq + i0 + (c - NV); live = i0 + (c - NV) < nq; src = c;
+    } else {
+      g = (CLOSE ? nq : 2 * nq) + (c - NB); live = blockIdx.y == 0; src = NP + (c - NB);
+    }
+    if (live) {
+      double t = 0.0;
 #pragma unroll
-    for (int w2 = 0; w2 < RW; ++w2) s += red[w2][src];
-    part[(size_t)c * PLD + blockIdx.x] = s;
+      for (int w2 = 0; w2 < RW; ++w2) t += red[w2][src];
+      part[(size_t)g * PLD + blockIdx.x] = t;
+    }
   }
 }
 
@@ -348,7 +402,9 @@ __global__ __launch_bounds__(RT) void dcgs_finalize(KState* ks, const double* pa
   }
 }
 
-template <typename TV, int NV>
+// CV vectors per inner step: CV == NV unrolls everything (loads of one entry
+// all in flight); CV < NV bounds the registers of the long-basis buckets.
+template <typename TV, int NV, int PW, int CV>
 __global__ __launch_bounds__(RT) void dcgs_update(TV* __restrict__ V, size_t ld, int j, size_t n, const KState* ks) {
   if (ks->m_eff <= j) return;          // q_j is not part of the basis
   const int nq = j;
@@ -361,23 +417,39 @@ __global__ __launch_bounds__(RT) void dcgs_update(TV* __restrict__ V, size_t ld,
   const double a = ks->acoef, ir = ks->rinv;
   TV* U = V + (size_t)j * ld;
   TV* W = V + (size_t)(j + 1) * ld;
-  const size_t np = (n + 1) / 2;
+  const size_t np = PW == 2 ? (n + 1) / 2 : n;
   for (size_t p = (size_t)blockIdx.x * RT + threadIdx.x; p < np; p += (size_t)gridDim.x * RT) {
-    double v0[NV], v1[NV], u0, u1, w0, w1;
+    double u[PW], w[PW], un[PW], wn[PW];
+    load_pw<TV, PW>(U, p, n, u);
+    load_pw<TV, PW>(W, p, n, w);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) load_pair(V + (size_t)clampv(i, nq) * ld, p, n, v0[i], v1[i]);
-    load_pair(U, p, n, u0, u1);
-    load_pair(W, p, n, w0, w1);
-    double un0 = u0, un1 = u1, wn0 = w0 * ir - a * u0, wn1 = w1 * ir - a * u1;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      un0 -= e[i] * v0[i];
-      un1 -= e[i] * v1[i];
-      wn0 -= b[i] * v0[i];
-      wn1 -= b[i] * v1[i];
+    for (int k = 0; k < PW; ++k) {
+      un[k] = u[k];
+      wn[k] = w[k] * ir - a * u[k];
     }
-    store_pair(U, p, n, un0, un1);
-    store_pair(W, p, n, wn0, wn1);
+#pragma unroll 1
+    for (int c0 = 0; c0 < NV; c0 += CV) {
+      if (CV < NV && c0 >= nq) break;
+      double v[CV][PW];
+#pragma unroll
+      for (int i = 0; i < CV; ++i) load_pw<TV, PW>(V + (size_t)clampv(c0 + i, nq) * ld, p, n, v[i]);
+#pragma unroll
+      for (int i = 0; i < CV; ++i) {
+        const double ei = e[c0 + i], bi = b[c0 + i];
+#pragma unroll
+        for (int k = 0; k < PW; ++k) {
+          un[k] -= ei * v[i][k];
+          wn[k] -= bi * v[i][k];
+        }
+      }
+    }
+    if (PW == 2) {
+      store_pair(U, p, n, un[0], un[1]);
+      store_pair(W, p, n, wn[0], wn[1]);
+    } else {
+      U[p] = (TV)un[0];
+      W[p] = (TV)wn[0];
+    }
   }
 }
 
@@ -400,40 +472,62 @@ __global__ __launch_bounds__(RT) void dcgs_close_finalize(KState* ks, const doub
   ks->hlast = h;
 }
 
-// Launch with the smallest vector-count bucket that holds nq (>= 1) vectors.
-#define PCEXP_NV_DISPATCH(KERNEL, NQ, ...)                                                     \
-  do {                                                                                         \
-    const int nv_ = (NQ) > 0 ? (NQ) : 1;                                                       \
-    dim3 g_(gs_blocks(n)), b_(RT);                                                             \
-    if (nv_ <= 4) hipLaunchKernelGGL((KERNEL(4)), g_, b_, 0, st, __VA_ARGS__);                 \
-    else if (nv_ <= 8) hipLaunchKernelGGL((KERNEL(8)), g_, b_, 0, st, __VA_ARGS__);            \
-    else if (nv_ <= 12) hipLaunchKernelGGL((KERNEL(12)), g_, b_, 0, st, __VA_ARGS__);          \
-    else if (nv_ <= 16) hipLaunchKernelGGL((KERNEL(16)), g_, b_, 0, st, __VA_ARGS__);          \
-    else if (nv_ <= 20) hipLaunchKernelGGL((KERNEL(20)), g_, b_, 0, st, __VA_ARGS__);          \
-    else if (nv_ <= 24) hipLaunchKernelGGL((KERNEL(24)), g_, b_, 0, st, __VA_ARGS__);          \
-    else if (nv_ <= 28) hipLaunchKernelGGL((KERNEL(28)), g_, b_, 0, st, __VA_ARGS__);          \
-    else if (nv_ <= 32) hipLaunchKernelGGL((KERNEL(32)), g_, b_, 0, st, __VA_ARGS__);          \
-    else if (nv_ <= 40) hipLaunchKernelGGL((KERNEL(40)), g_, b_, 0, st, __VA_ARGS__);          \
-    else if (nv_ <= 48) hipLaunchKernelGGL((KERNEL(48)), g_, b_, 0, st, __VA_ARGS__);          \
-    else if (nv_ <= 56) hipLaunchKernelGGL((KERNEL(56)), g_, b_, 0, st, __VA_ARGS__);          \
-    else hipLaunchKernelGGL((KERNEL(64)), g_, b_, 0, st, __VA_ARGS__);                         \
-  } while (0)
+// Blocks per vector chunk of the reduction (the partials per column).
+static int red_blocks(size_t n, int nq) {
+  const int nc = nq > CHUNK ? (nq + CHUNK - 1) / CHUNK : 1;
+  const int b = (int)gs_blocks(n) / nc;
+  return b > 0 ? b : 1;
+}
 
-#define PCEXP_K_RED(NV) dcgs_reduce<TV, NV, false>
-#define PCEXP_K_CLOSE(NV) dcgs_reduce<TV, NV, true>
-#define PCEXP_K_UPD(NV) dcgs_update<TV, NV>
+// Smallest vector-count bucket that holds nq (>= 1) vectors; two entries per
+// lane while the registers allow it.
+template <typename TV, bool CLOSE>
+static void launch_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st) {
+  const int nq = j > 0 ? j : 1;
+  const dim3 b(RT);
+  const unsigned nb = (unsigned)red_blocks(n, nq);
+  if (nq <= 4) hipLaunchKernelGGL((dcgs_reduce<TV, 4, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 8) hipLaunchKernelGGL((dcgs_reduce<TV, 8, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 12) hipLaunchKernelGGL((dcgs_reduce<TV, 12, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 16) hipLaunchKernelGGL((dcgs_reduce<TV, 16, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 20) hipLaunchKernelGGL((dcgs_reduce<TV, 20, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 24) hipLaunchKernelGGL((dcgs_reduce<TV, 24, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 28) hipLaunchKernelGGL((dcgs_reduce<TV, 28, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else {
+    const unsigned nc = (unsigned)((nq + CHUNK - 1) / CHUNK);
+    hipLaunchKernelGGL((dcgs_reduce<TV, CHUNK, 1, CLOSE>), dim3(nb, nc), b, 0, st, V, ld, j, n, ks, part);
+  }
+}
+
+template <typename TV>
+static void launch_update(TV* V, size_t ld, int j, size_t n, const KState* ks, hipStream_t st) {
+  const int nq = j > 0 ? j : 1;
+  const dim3 g((unsigned)gs_blocks(n)), b(RT);
+  if (nq <= 4) hipLaunchKernelGGL((dcgs_update<TV, 4, 2, 4>), g, b, 0, st, V, ld, j, n, ks);
+  else if (nq <= 8) hipLaunchKernelGGL((dcgs_update<TV, 8, 2, 8>), g, b, 0, st, V, ld, j, n, ks);
+  else if (nq <= 12) hipLaunchKernelGGL((dcgs_update<TV, 12, 2, 12>), g, b, 0, st, V, ld, j, n, ks);
+  else if (nq <= 16) hipLaunchKernelGGL((dcgs_update<TV, 16, 2, 16>), g, b, 0, st, V, ld, j, n, ks);
+  else if (nq <= 20) hipLaunchKernelGGL((dcgs_update<TV, 20, 2, 20>), g, b, 0, st, V, ld, j, n, ks);
+  else if (nq <= 24) hipLaunchKernelGGL((dcgs_update<TV, 24, 2, 24>), g, b, 0, st, V, ld, j, n, ks);
+  else if (nq <= 28) {
+    constexpr int PW = sizeof(TV) == 8 ? 2 : 1;   // FP32 pairs would spill here
+    hipLaunchKernelGGL((dcgs_update<TV, 28, PW, 28>), g, b, 0, st, V, ld, j, n, ks);
+  }
+  else if (nq <= 32) hipLaunchKernelGGL((dcgs_update<TV, 32, 1, 32>), g, b, 0, st, V, ld, j, n, ks);
+  else hipLaunchKernelGGL((dcgs_update<TV, KMAX, 1, 16>), g, b, 0, st, V, ld, j, n, ks);
+}
 
 template <typename TV>
 void k_arnoldi_iter(TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st) {
-  PCEXP_NV_DISPATCH(PCEXP_K_RED, j, V, ld, j, n, ks, part);
-  hipLaunchKernelGGL(dcgs_finalize, dim3(1), dim3(RT), 0, st, ks, part, j, (int)gs_blocks(n));
-  PCEXP_NV_DISPATCH(PCEXP_K_UPD, j, V, ld, j, n, ks);
+  launch_reduce<TV, false>(V, ld, j, n, ks, part, st);
+  hipLaunchKernelGGL(dcgs_finalize, dim3(1), dim3(RT), 0, st, ks, part, j, red_blocks(n, j > 0 ? j : 1));
+  launch_update<TV>(V, ld, j, n, ks, st);
 }
 
 template <typename TV>
 void k_arnoldi_close(TV* V, size_t ld, int m, size_t n, KState* ks, double* part, hipStream_t st) {
-  PCEXP_NV_DISPATCH(PCEXP_K_CLOSE, m, V, ld, m, n, ks, part);
-  hipLaunchKernelGGL(dcgs_close_finalize, dim3(1), dim3(RT), 0, st, ks, part, m, (int)gs_blocks(n));
+  launch_reduce<TV, true>(V, ld, m, n, ks, part, st);
+  hipLaunchKernelGGL(dcgs_close_finalize, dim3(1), dim3(RT), 0, st, ks, part, m, red_blocks(n, m > 0 ? m : 1));
 }
 
 // ------------------------------------------------------------ Hessenberg phi

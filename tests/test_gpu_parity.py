@@ -149,6 +149,19 @@ def test_arnoldi_phi_vs_dense_dg():
     assert rel(out, want) < 1e-11
 
 
+@pytest.mark.parametrize("m,prec", [(64, "f64"), (48, "mixed"), (33, "f64")])
+def test_arnoldi_phi_long_basis(m, prec):
+    """Bases beyond one 32-vector chunk of the fused Gram-Schmidt pass."""
+    g, ctx, u = _pair("sq4j", 2, "roe")
+    b = g.residual(u)
+    dt = stable_dt(g, u, 5.0)
+    out, info = ctx.arnoldi_phi(_t(u), _t(b), dt, k=1, m=m, prec=prec, info=True)
+    want, oinfo = krylov.arnoldi_phi(lambda x: jvp_cs(g, u, x.reshape(u.shape)), b, dt, 1, m,
+                                     return_info=True)
+    assert info["m_eff"] == oinfo["m_eff"] == m
+    assert rel(_n(out), want) < (1e-10 if prec == "f64" else 1e-5)
+
+
 def test_arnoldi_phi_zero_vector_and_mixed():
     g, ctx, u = _pair("sq4j", 2, "roe")
     out, info = ctx.arnoldi_phi(_t(u), _t(np.zeros_like(u)), 0.1, k=1, m=5, info=True)
@@ -176,11 +189,13 @@ def test_dense_split_model_growth():
             assert abs(u.item() - (a * (np.exp(b) - 1) + b * np.exp(b)) / b) < 1e-12 * max(1, abs(u.item()))
 
 
-def test_dense_linear_exactness_and_breakdown():
+@pytest.mark.parametrize("n", [20, 21])
+def test_dense_linear_exactness_and_breakdown(n):
+    """n = 21: an odd vector length exercises the unpaired last entry of the
+    two-entries-per-lane Gram-Schmidt passes."""
     from scipy.linalg import expm
     PCEXP = _dev()
     rng = np.random.default_rng(4)
-    n = 20
     A = rng.standard_normal((n, n)) - 4 * np.eye(n)
     u0 = rng.standard_normal(n)
     ctx = PCEXP.dense(A, A)
