@@ -73,6 +73,10 @@ struct DGIO {
 // LDS budget per workgroup (bytes) used to choose the tile size.
 constexpr int kLdsBudget = 40 * 1024;
 
+// Tile policy.  The two pointwise phases have NQ * TE (volume) and
+// NF * NFQ * TE (faces) work items over NT threads; a partial last round
+// leaves most lanes idle, so TE is chosen to minimise rounds per element
+// (largest TE among equals) under the LDS budget.
 template <int D, int P, typename T, bool DUAL>
 struct Tile {
   using Sh = Shape<D, P>;
@@ -80,9 +84,24 @@ struct Tile {
   static constexpr int NFL = Sh::NF * Sh::NFQ * Sh::NV;
   static constexpr int NW = NG > NFL ? NG : NFL;
   static constexpr int per_elem = (int)sizeof(T) * (Sh::NVB * (DUAL ? 2 : 1) + NW) + Sh::NF;
-  static constexpr int TE = (64 * per_elem <= kLdsBudget) ? 64
-                            : (32 * per_elem <= kLdsBudget) ? 32
-                            : (16 * per_elem <= kLdsBudget) ? 16 : 8;
+  // reference tables B, Dg, Bf, wq, wf, nref; staged in LDS when small
+  static constexpr int NTAB = Sh::NQ * Sh::NB * (D + 1) + Sh::NF * Sh::NORI * Sh::NFQ * Sh::NB + Sh::NQ +
+                              Sh::NFQ + Sh::NF * D;
+  static constexpr bool STAGE_TAB = NTAB * (int)sizeof(T) <= 8192;
+  static constexpr int fixed_lds = STAGE_TAB ? NTAB * (int)sizeof(T) : 0;
+  static constexpr int NT = 256;
+  static constexpr int rounds(int te) {
+    return (Sh::NQ * te + NT - 1) / NT + (Sh::NF * Sh::NFQ * te + NT - 1) / NT;
+  }
+  static constexpr int pick() {
+    int best = 1;
+    for (int te = 2; te <= 64; ++te) {
+      if (te * per_elem + fixed_lds > kLdsBudget) break;
+      if (rounds(te) * best <= rounds(best) * te) best = te;   // rounds/te no larger
+    }
+    return best;
+  }
+  static constexpr int TE = pick();
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
@@ -104,16 +123,14 @@ __device__ __forceinline__ void num_flux(const S* UL, const S* UR, const T* n, T
   else flux_roe<D>(UL, UR, n, gamma, F);
 }
 
-template <int D, int P, int FLUX, typename T, int MODE>
-__global__ __launch_bounds__(256) void dg_apply(DGParams<T> prm, DGIO<T> io) {
+template <int D, int P, int FLUX, typename T, int MODE, int TE, int NT>
+__global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   using Sh = Shape<D, P>;
   constexpr int NV = Sh::NV, NB = Sh::NB, NVB = Sh::NVB, NQ = Sh::NQ, NFQ = Sh::NFQ;
   constexpr int NF = Sh::NF, NORI = Sh::NORI;
   constexpr bool DUAL = (MODE == MODE_TAN);
   using Tl = Tile<D, P, T, DUAL>;
-  constexpr int TE = Tl::TE;
   using S = typename std::conditional<DUAL, Dual<T, 1>, T>::type;
-  constexpr int NT = 256;
   constexpr int NOUT = (NVB * TE + NT - 1) / NT;
 
   if (io.skip && *io.skip) return;
@@ -121,6 +138,27 @@ __global__ __launch_bounds__(256) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   __shared__ T sv[DUAL ? NVB * TE : 1];
   __shared__ T sw[Tl::NW * TE];
   __shared__ unsigned char sori[NF * TE];
+  __shared__ T stab[Tl::STAGE_TAB ? Tl::NTAB : 1];
+
+  // reference tables: every lane reads them, so keep them in LDS when small
+  constexpr int oDg = NQ * NB, oBf = oDg + NQ * NB * D, owq = oBf + NF * NORI * NFQ * NB, owf = owq + NQ,
+                onr = owf + NFQ;
+  const T *tB, *tDg, *tBf, *twq, *twf, *tnref;
+  if constexpr (Tl::STAGE_TAB) {
+    for (int t = threadIdx.x; t < Tl::NTAB; t += NT) {
+      T x;
+      if (t < oDg) x = prm.B[t];
+      else if (t < oBf) x = prm.Dg[t - oDg];
+      else if (t < owq) x = prm.Bf[t - oBf];
+      else if (t < owf) x = prm.wq[t - owq];
+      else if (t < onr) x = prm.wf[t - owf];
+      else x = prm.nref[t - onr];
+      stab[t] = x;
+    }
+    tB = stab; tDg = stab + oDg; tBf = stab + oBf; twq = stab + owq; twf = stab + owf; tnref = stab + onr;
+  } else {
+    tB = prm.B; tDg = prm.Dg; tBf = prm.Bf; twq = prm.wq; twf = prm.wf; tnref = prm.nref;
+  }
 
   const int Epad = prm.Epad, nE = prm.nE;
   const int e0 = xcd_tile(blockIdx.x, gridDim.x) * TE;
@@ -162,7 +200,7 @@ __global__ __launch_bounds__(256) void dg_apply(DGParams<T> prm, DGIO<T> io) {
       T a = T(0), b = T(0);
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
-        const T bq = prm.B[q * NB + i];
+        const T bq = tB[q * NB + i];
         a += su[(k * NB + i) * TE + e] * bq;
         if (DUAL) b += sv[(k * NB + i) * TE + e] * bq;
       }
@@ -183,7 +221,7 @@ __global__ __launch_bounds__(256) void dg_apply(DGParams<T> prm, DGIO<T> io) {
       else if (!(rho > T(0)) || !(p > T(0))) fl |= 2u;
       if (fl) atomicOr(io.flags, fl);
     }
-    const T wgt = sd * prm.wq[q];
+    const T wgt = sd * twq[q];
 #pragma unroll
     for (int r = 0; r < D; ++r) {
       T a[D];
@@ -205,7 +243,7 @@ __global__ __launch_bounds__(256) void dg_apply(DGParams<T> prm, DGIO<T> io) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
 #pragma unroll
-        for (int r = 0; r < D; ++r) s += sw[((q * NV + k) * D + r) * TE + e] * prm.Dg[(q * NB + i) * D + r];
+        for (int r = 0; r < D; ++r) s += sw[((q * NV + k) * D + r) * TE + e] * tDg[(q * NB + i) * D + r];
       acc[o] += s;
     }
   }
@@ -221,7 +259,7 @@ __global__ __launch_bounds__(256) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     if (r == 0) sori[f * TE + e] = (unsigned char)oE;
     const T sd = prm.sdet[ge];
     const T rs = T(1) / sd;
-    const T* bl = prm.Bf + ((f * NORI + oE) * NFQ + r) * NB;
+    const T* bl = tBf + ((f * NORI + oE) * NFQ + r) * NB;
     S UL[NV], UR[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -245,7 +283,7 @@ __global__ __launch_bounds__(256) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     for (int c = 0; c < D; ++c) {
       T s = T(0);
 #pragma unroll
-      for (int rr = 0; rr < D; ++rr) s += prm.ainv[(size_t)(rr * D + c) * Epad + ge] * prm.nref[f * D + rr];
+      for (int rr = 0; rr < D; ++rr) s += prm.ainv[(size_t)(rr * D + c) * Epad + ge] * tnref[f * D + rr];
       nl[c] = s * sd * sd;
       len2 += nl[c] * nl[c];
     }
@@ -255,7 +293,7 @@ __global__ __launch_bounds__(256) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     for (int c = 0; c < D; ++c) n[c] = nl[c] / len;
     if (nb >= 0) {
       const int fN = info & 3, oN = (info >> 2) & 7;
-      const T* br = prm.Bf + ((fN * NORI + oN) * NFQ + r) * NB;
+      const T* br = tBf + ((fN * NORI + oN) * NFQ + r) * NB;
       const T rsn = T(1) / prm.sdet[nb];
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
@@ -283,7 +321,7 @@ __global__ __launch_bounds__(256) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     }
     S F[NV];
     num_flux<D, FLUX>(UL, UR, n, prm.gamma, F);
-    const T wgt = prm.wf[r] * len * rs;
+    const T wgt = twf[r] * len * rs;
 #pragma unroll
     for (int k = 0; k < NV; ++k) sw[((f * NFQ + r) * NV + k) * TE + e] = wgt * Part<S>::get(F[k]);
   }
@@ -297,7 +335,7 @@ __global__ __launch_bounds__(256) void dg_apply(DGParams<T> prm, DGIO<T> io) {
         T s = T(0);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-          const T* bl = prm.Bf + (f * NORI + sori[f * TE + e]) * NFQ * NB;
+          const T* bl = tBf + (f * NORI + sori[f * TE + e]) * NFQ * NB;
 #pragma unroll
           for (int r = 0; r < NFQ; ++r) s += sw[((f * NFQ + r) * NV + k) * TE + e] * bl[r * NB + i];
         }
@@ -552,21 +590,16 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
 template <int D, int P, int FLUX>
 void launch_vjp(const DGParams<double>& prm, const double* u, const double* w, double* out, hipStream_t st) {
   constexpr int TE = VjpTile<D, P, FLUX>::TE;
-  hipLaunchKernelGGL((dg_vjp_kernel<D, P, FLUX>), dim3(prm.Epad / TE), dim3(256), 0, st, prm, u, w, out);
+  hipLaunchKernelGGL((dg_vjp_kernel<D, P, FLUX>), dim3((prm.Epad + TE - 1) / TE), dim3(256), 0, st, prm, u, w, out);
 }
 
 // Host launchers (defined in the per-dimension translation units).
 template <int D, int P, int FLUX, typename T, int MODE>
 void launch_dg(const DGParams<T>& prm, const DGIO<T>& io, hipStream_t st) {
-  constexpr bool DUAL = (MODE == MODE_TAN);
-  constexpr int TE = Tile<D, P, T, DUAL>::TE;
-  const int nblk = prm.Epad / TE;
-  hipLaunchKernelGGL((dg_apply<D, P, FLUX, T, MODE>), dim3(nblk), dim3(256), 0, st, prm, io);
-}
-
-template <int D, int P>
-constexpr int tile_elems_max() {
-  return 64;
+  using Tl = Tile<D, P, T, MODE == MODE_TAN>;
+  constexpr int TE = Tl::TE, NT = Tl::NT;
+  const int nblk = (prm.Epad + TE - 1) / TE;   // the last tile may run past Epad: guarded in the kernel
+  hipLaunchKernelGGL((dg_apply<D, P, FLUX, T, MODE, TE, NT>), dim3(nblk), dim3(NT), 0, st, prm, io);
 }
 
 }  // namespace pcexp
