@@ -182,14 +182,16 @@ pcexp_status pcexp_step(pcexp_ctx* ctx, double* u, double dt, double cfl, int32_
                         int32_t scheme, int32_t prec, int32_t jvp, void* ws, size_t ws_bytes,
                         pcexp_step_info* info, void* stream);
 
-/* Kernel-class timing with HIP events recorded on the caller's stream around
- * the launches made by pcexp_step / pcexp_arnoldi_phi (for roofline reports).
+/* Kernel-class timing with HIP events for the launches made by pcexp_step /
+ * pcexp_arnoldi_phi (for roofline reports).  Each timed operation is one
+ * kernel; its event pair is passed to that kernel's dispatch on the caller's
+ * stream, so the interval is the kernel's own execution time.
  * op = 1: enable and reset (pre-creates the events; call outside timed code);
  * op = 0: disable; op = 2: synchronise and write, for each class c in
  * [0, PCEXP_PROF_NCLASS), out[3c] = total milliseconds, out[3c+1] = launches,
  * out[3c+2] = algorithmic bytes moved (reads + writes the operation needs).
- * Classes: 0 residual, 1 JVP, 2 Arnoldi orthogonalisation (reduction,
- * one-block finalisation and update of one iteration), 3-4 unused,
+ * Classes: 0 residual, 1 JVP, 2 Gram-Schmidt reduction pass (V^T [U W]),
+ * 3 its one-block finalisation (no HBM bytes), 4 Gram-Schmidt update pass,
  * 5 Hessenberg phi, 6 Krylov combination, 7 other. */
 #define PCEXP_PROF_NCLASS 8
 pcexp_status pcexp_profile(pcexp_ctx* ctx, int32_t op, double* out);

@@ -23,6 +23,7 @@
 #include <type_traits>
 
 #include "dg_physics.hpp"
+#include "launch.hpp"
 
 namespace pcexp {
 
@@ -590,7 +591,7 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
 template <int D, int P, int FLUX>
 void launch_vjp(const DGParams<double>& prm, const double* u, const double* w, double* out, hipStream_t st) {
   constexpr int TE = VjpTile<D, P, FLUX>::TE;
-  hipLaunchKernelGGL((dg_vjp_kernel<D, P, FLUX>), dim3((prm.Epad + TE - 1) / TE), dim3(256), 0, st, prm, u, w, out);
+  launch((dg_vjp_kernel<D, P, FLUX>), dim3((prm.Epad + TE - 1) / TE), dim3(256), 0, st, prm, u, w, out);
 }
 
 // Host launchers (defined in the per-dimension translation units).
@@ -599,7 +600,7 @@ void launch_dg(const DGParams<T>& prm, const DGIO<T>& io, hipStream_t st) {
   using Tl = Tile<D, P, T, MODE == MODE_TAN>;
   constexpr int TE = Tl::TE, NT = Tl::NT;
   const int nblk = (prm.Epad + TE - 1) / TE;   // the last tile may run past Epad: guarded in the kernel
-  hipLaunchKernelGGL((dg_apply<D, P, FLUX, T, MODE, TE, NT>), dim3(nblk), dim3(NT), 0, st, prm, io);
+  launch((dg_apply<D, P, FLUX, T, MODE, TE, NT>), dim3(nblk), dim3(NT), 0, st, prm, io);
 }
 
 }  // namespace pcexp

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dg_dispatch.hpp"
+#include "launch.hpp"
 
 namespace pcexp {
 
@@ -187,33 +188,33 @@ __global__ void totals_finalize(const double* part, int nblk, int nv, double* ou
 }
 
 void ek_to_internal(const ElemArgs& a, const double* u_abi, double* u_int, hipStream_t st) {
-  hipLaunchKernelGGL(to_internal_kernel, grid_for((size_t)a.Epad * a.nv), dim3(EK_T), 0, st, a, u_abi, u_int);
+  launch(to_internal_kernel, grid_for((size_t)a.Epad * a.nv), dim3(EK_T), 0, st, a, u_abi, u_int);
 }
 void ek_to_abi(const ElemArgs& a, const double* u_int, double* u_abi, hipStream_t st) {
-  hipLaunchKernelGGL(to_abi_kernel, grid_for((size_t)a.nE * a.nv), dim3(EK_T), 0, st, a, u_int, u_abi);
+  launch(to_abi_kernel, grid_for((size_t)a.nE * a.nv), dim3(EK_T), 0, st, a, u_int, u_abi);
 }
 void ek_quad_points(const ElemArgs& a, double* xyz, hipStream_t st) {
-  hipLaunchKernelGGL(quad_points_kernel, grid_for((size_t)a.nE * a.nq), dim3(EK_T), 0, st, a, xyz);
+  launch(quad_points_kernel, grid_for((size_t)a.nE * a.nq), dim3(EK_T), 0, st, a, xyz);
 }
 void ek_project(const ElemArgs& a, const double* Uqp, double* u_abi, hipStream_t st) {
-  hipLaunchKernelGGL(project_kernel, grid_for((size_t)a.nE * a.nv), dim3(EK_T), 0, st, a, Uqp, u_abi);
+  launch(project_kernel, grid_for((size_t)a.nE * a.nv), dim3(EK_T), 0, st, a, Uqp, u_abi);
 }
 void ek_evaluate(const ElemArgs& a, const double* u_abi, double* Uqp, hipStream_t st) {
-  hipLaunchKernelGGL(evaluate_kernel, grid_for((size_t)a.nE * a.nv), dim3(EK_T), 0, st, a, u_abi, Uqp);
+  launch(evaluate_kernel, grid_for((size_t)a.nE * a.nv), dim3(EK_T), 0, st, a, u_abi, Uqp);
 }
 void ek_stable_dt(const ElemArgs& a, const double* u_int, const double* cfl_dev, double cfl, double* dt,
                   double* part, unsigned* counter, hipStream_t st) {
   (void)counter;
   const dim3 g = grid_for((size_t)a.nE);
-  hipLaunchKernelGGL(stable_dt_kernel, g, dim3(EK_T), 0, st, a, u_int, part);
-  hipLaunchKernelGGL(stable_dt_finalize, dim3(1), dim3(64), 0, st, part, (int)g.x, cfl_dev, cfl, dt);
+  launch(stable_dt_kernel, g, dim3(EK_T), 0, st, a, u_int, part);
+  launch(stable_dt_finalize, dim3(1), dim3(64), 0, st, part, (int)g.x, cfl_dev, cfl, dt);
 }
 void ek_totals(const ElemArgs& a, const double* u_int, double* out, double* part, unsigned* counter,
                hipStream_t st) {
   (void)counter;
   const dim3 g = grid_for((size_t)a.nE);
-  hipLaunchKernelGGL(totals_kernel, g, dim3(EK_T), 0, st, a, u_int, part);
-  hipLaunchKernelGGL(totals_finalize, dim3(1), dim3(EK_T), 0, st, part, (int)g.x, a.nv, out);
+  launch(totals_kernel, g, dim3(EK_T), 0, st, a, u_int, part);
+  launch(totals_finalize, dim3(1), dim3(EK_T), 0, st, part, (int)g.x, a.nv, out);
 }
 
 }  // namespace pcexp

@@ -1,5 +1,6 @@
 // Krylov / Arnoldi and utility kernels (see krylov_kernels.hpp).
 #include "krylov_kernels.hpp"
+#include "launch.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -131,7 +132,7 @@ __global__ void init_state_kernel(KState* ks, double eta) {
 }
 
 void k_init_state(KState* ks, double eta, hipStream_t st) {
-  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(256), 0, st, ks, eta);
+  launch(init_state_kernel, dim3(1), dim3(256), 0, st, ks, eta);
 }
 
 // The partial buffer of an Arnoldi run holds 3 (KMAX + 2) columns of PLD:
@@ -168,8 +169,8 @@ __global__ __launch_bounds__(64) void start_finalize(KState* ks, const double* p
 template <typename TV>
 void k_start(const double* b, TV* V0, size_t n, KState* ks, double* part, hipStream_t st) {
   const int nb = (int)gs_blocks(n);
-  hipLaunchKernelGGL(start_kernel<TV>, dim3(nb), dim3(RT), 0, st, b, V0, n, part);
-  hipLaunchKernelGGL(start_finalize, dim3(1), dim3(64), 0, st, ks, part, nb);
+  launch(start_kernel<TV>, dim3(nb), dim3(RT), 0, st, b, V0, n, part);
+  launch(start_finalize, dim3(1), dim3(64), 0, st, ks, part, nb);
 }
 
 // Vector loads of the Gram-Schmidt kernels are unconditional: slots beyond
@@ -486,16 +487,16 @@ static void launch_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, d
   const int nq = j > 0 ? j : 1;
   const dim3 b(RT);
   const unsigned nb = (unsigned)red_blocks(n, nq);
-  if (nq <= 4) hipLaunchKernelGGL((dcgs_reduce<TV, 4, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
-  else if (nq <= 8) hipLaunchKernelGGL((dcgs_reduce<TV, 8, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
-  else if (nq <= 12) hipLaunchKernelGGL((dcgs_reduce<TV, 12, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
-  else if (nq <= 16) hipLaunchKernelGGL((dcgs_reduce<TV, 16, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
-  else if (nq <= 20) hipLaunchKernelGGL((dcgs_reduce<TV, 20, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
-  else if (nq <= 24) hipLaunchKernelGGL((dcgs_reduce<TV, 24, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
-  else if (nq <= 28) hipLaunchKernelGGL((dcgs_reduce<TV, 28, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  if (nq <= 4) launch((dcgs_reduce<TV, 4, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 8) launch((dcgs_reduce<TV, 8, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 12) launch((dcgs_reduce<TV, 12, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 16) launch((dcgs_reduce<TV, 16, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 20) launch((dcgs_reduce<TV, 20, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 24) launch((dcgs_reduce<TV, 24, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 28) launch((dcgs_reduce<TV, 28, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
   else {
     const unsigned nc = (unsigned)((nq + CHUNK - 1) / CHUNK);
-    hipLaunchKernelGGL((dcgs_reduce<TV, CHUNK, 1, CLOSE>), dim3(nb, nc), b, 0, st, V, ld, j, n, ks, part);
+    launch((dcgs_reduce<TV, CHUNK, 1, CLOSE>), dim3(nb, nc), b, 0, st, V, ld, j, n, ks, part);
   }
 }
 
@@ -503,31 +504,35 @@ template <typename TV>
 static void launch_update(TV* V, size_t ld, int j, size_t n, const KState* ks, hipStream_t st) {
   const int nq = j > 0 ? j : 1;
   const dim3 g((unsigned)gs_blocks(n)), b(RT);
-  if (nq <= 4) hipLaunchKernelGGL((dcgs_update<TV, 4, 2, 4>), g, b, 0, st, V, ld, j, n, ks);
-  else if (nq <= 8) hipLaunchKernelGGL((dcgs_update<TV, 8, 2, 8>), g, b, 0, st, V, ld, j, n, ks);
-  else if (nq <= 12) hipLaunchKernelGGL((dcgs_update<TV, 12, 2, 12>), g, b, 0, st, V, ld, j, n, ks);
-  else if (nq <= 16) hipLaunchKernelGGL((dcgs_update<TV, 16, 2, 16>), g, b, 0, st, V, ld, j, n, ks);
-  else if (nq <= 20) hipLaunchKernelGGL((dcgs_update<TV, 20, 2, 20>), g, b, 0, st, V, ld, j, n, ks);
-  else if (nq <= 24) hipLaunchKernelGGL((dcgs_update<TV, 24, 2, 24>), g, b, 0, st, V, ld, j, n, ks);
+  if (nq <= 4) launch((dcgs_update<TV, 4, 2, 4>), g, b, 0, st, V, ld, j, n, ks);
+  else if (nq <= 8) launch((dcgs_update<TV, 8, 2, 8>), g, b, 0, st, V, ld, j, n, ks);
+  else if (nq <= 12) launch((dcgs_update<TV, 12, 2, 12>), g, b, 0, st, V, ld, j, n, ks);
+  else if (nq <= 16) launch((dcgs_update<TV, 16, 2, 16>), g, b, 0, st, V, ld, j, n, ks);
+  else if (nq <= 20) launch((dcgs_update<TV, 20, 2, 20>), g, b, 0, st, V, ld, j, n, ks);
+  else if (nq <= 24) launch((dcgs_update<TV, 24, 2, 24>), g, b, 0, st, V, ld, j, n, ks);
   else if (nq <= 28) {
     constexpr int PW = sizeof(TV) == 8 ? 2 : 1;   // FP32 pairs would spill here
-    hipLaunchKernelGGL((dcgs_update<TV, 28, PW, 28>), g, b, 0, st, V, ld, j, n, ks);
+    launch((dcgs_update<TV, 28, PW, 28>), g, b, 0, st, V, ld, j, n, ks);
   }
-  else if (nq <= 32) hipLaunchKernelGGL((dcgs_update<TV, 32, 1, 32>), g, b, 0, st, V, ld, j, n, ks);
-  else hipLaunchKernelGGL((dcgs_update<TV, KMAX, 1, 16>), g, b, 0, st, V, ld, j, n, ks);
+  else if (nq <= 32) launch((dcgs_update<TV, 32, 1, 32>), g, b, 0, st, V, ld, j, n, ks);
+  else launch((dcgs_update<TV, KMAX, 1, 16>), g, b, 0, st, V, ld, j, n, ks);
 }
 
 template <typename TV>
-void k_arnoldi_iter(TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st) {
-  launch_reduce<TV, false>(V, ld, j, n, ks, part, st);
-  hipLaunchKernelGGL(dcgs_finalize, dim3(1), dim3(RT), 0, st, ks, part, j, red_blocks(n, j > 0 ? j : 1));
+void k_gs_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, double* part, bool close, hipStream_t st) {
+  if (close) launch_reduce<TV, true>(V, ld, j, n, ks, part, st);
+  else launch_reduce<TV, false>(V, ld, j, n, ks, part, st);
+}
+
+void k_gs_finalize(KState* ks, const double* part, int j, size_t n, bool close, hipStream_t st) {
+  const int nblk = red_blocks(n, j > 0 ? j : 1);
+  if (close) launch(dcgs_close_finalize, dim3(1), dim3(RT), 0, st, ks, part, j, nblk);
+  else launch(dcgs_finalize, dim3(1), dim3(RT), 0, st, ks, part, j, nblk);
+}
+
+template <typename TV>
+void k_gs_update(TV* V, size_t ld, int j, size_t n, const KState* ks, hipStream_t st) {
   launch_update<TV>(V, ld, j, n, ks, st);
-}
-
-template <typename TV>
-void k_arnoldi_close(TV* V, size_t ld, int m, size_t n, KState* ks, double* part, hipStream_t st) {
-  launch_reduce<TV, true>(V, ld, m, n, ks, part, st);
-  hipLaunchKernelGGL(dcgs_close_finalize, dim3(1), dim3(RT), 0, st, ks, part, m, red_blocks(n, m > 0 ? m : 1));
 }
 
 // ------------------------------------------------------------ Hessenberg phi
@@ -661,9 +666,9 @@ void k_hess_phi(KState* ks, const double* dt, int k, int m, double* scratch, hip
   const int n = m + (k >= 1 ? k : 0);
   const size_t bytes = (size_t)7 * n * n * sizeof(double);
   if (bytes <= 60 * 1024) {
-    hipLaunchKernelGGL(hess_phi_lds, dim3(1), dim3(PHI_T), bytes, st, ks, dt, k);
+    launch(hess_phi_lds, dim3(1), dim3(PHI_T), bytes, st, ks, dt, k);
   } else {
-    hipLaunchKernelGGL(hess_phi_glb, dim3(1), dim3(PHI_T), 0, st, ks, dt, k, scratch);
+    launch(hess_phi_glb, dim3(1), dim3(PHI_T), 0, st, ks, dt, k, scratch);
   }
 }
 
@@ -692,7 +697,7 @@ void k_combine(const TV* V, size_t ld, const KState* ks, const double* base, dou
                double fac, const double* dtp, size_t n, hipStream_t st) {
   size_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL((combine_kernel<TV, TX>), dim3(blocks), dim3(256), 0, st, V, ld, ks, base, out, xout,
+  launch((combine_kernel<TV, TX>), dim3(blocks), dim3(256), 0, st, V, ld, ks, base, out, xout,
                      fac, dtp, n);
 }
 
@@ -707,7 +712,7 @@ void k_fill(T* p, T v, size_t n, const int* skip, hipStream_t st) {
   size_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((fill_kernel<T>), dim3(blocks), dim3(256), 0, st, p, v, n, skip);
+  launch((fill_kernel<T>), dim3(blocks), dim3(256), 0, st, p, v, n, skip);
 }
 
 template <typename TA, typename TB>
@@ -719,7 +724,7 @@ void k_cast(const TA* a, TB* b, size_t n, hipStream_t st) {
   size_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((cast_kernel<TA, TB>), dim3(blocks), dim3(256), 0, st, a, b, n);
+  launch((cast_kernel<TA, TB>), dim3(blocks), dim3(256), 0, st, a, b, n);
 }
 
 __global__ __launch_bounds__(RT) void sumsq_kernel(const double* __restrict__ x, size_t n, double* part) {
@@ -735,8 +740,8 @@ void k_sumsq(const double* x, size_t n, double* out, int mode, double* part, uns
              hipStream_t st) {
   (void)counter;
   const int nb = (int)gs_blocks(n);
-  hipLaunchKernelGGL(sumsq_kernel, dim3(nb), dim3(RT), 0, st, x, n, part);
-  hipLaunchKernelGGL(sumsq_finalize, dim3(1), dim3(64), 0, st, part, nb, out, mode);
+  launch(sumsq_kernel, dim3(nb), dim3(RT), 0, st, x, n, part);
+  launch(sumsq_finalize, dim3(1), dim3(64), 0, st, part, nb, out, mode);
 }
 
 __global__ void fd_eps_kernel(const double* unorm, const double* vnorm, double c0, double* eps) {
@@ -745,7 +750,7 @@ __global__ void fd_eps_kernel(const double* unorm, const double* vnorm, double c
   *eps = e;
 }
 void k_fd_eps(const double* unorm, const double* vnorm, double c0, double* eps, hipStream_t st) {
-  hipLaunchKernelGGL(fd_eps_kernel, dim3(1), dim3(1), 0, st, unorm, vnorm, c0, eps);
+  launch(fd_eps_kernel, dim3(1), dim3(1), 0, st, unorm, vnorm, c0, eps);
 }
 
 template <typename TC>
@@ -757,12 +762,12 @@ template <typename TC>
 void k_glue_d(const double* a, const double* b, const TC* c, double* out, size_t n, hipStream_t st) {
   size_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL((glue_kernel<TC>), dim3(blocks), dim3(256), 0, st, a, b, c, out, n);
+  launch((glue_kernel<TC>), dim3(blocks), dim3(256), 0, st, a, b, c, out, n);
 }
 
 __global__ void set_scalar_kernel(double* p, double v) { *p = v; }
 void k_set_scalar(double* p, double v, hipStream_t st) {
-  hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, st, p, v);
+  launch(set_scalar_kernel, dim3(1), dim3(1), 0, st, p, v);
 }
 
 template <typename T>
@@ -778,16 +783,16 @@ __global__ void gemv_kernel(const T* A, const T* v, T* out, int n, const double*
 }
 template <typename T>
 void k_gemv(const T* A, const T* v, T* out, int n, const double* vscale, const int* skip, hipStream_t st) {
-  hipLaunchKernelGGL((gemv_kernel<T>), dim3((n + 3) / 4), dim3(256), 0, st, A, v, out, n, vscale, skip);
+  launch((gemv_kernel<T>), dim3((n + 3) / 4), dim3(256), 0, st, A, v, out, n, vscale, skip);
 }
 
 // explicit instantiations
 template void k_start<double>(const double*, double*, size_t, KState*, double*, hipStream_t);
 template void k_start<float>(const double*, float*, size_t, KState*, double*, hipStream_t);
-template void k_arnoldi_iter<double>(double*, size_t, int, size_t, KState*, double*, hipStream_t);
-template void k_arnoldi_iter<float>(float*, size_t, int, size_t, KState*, double*, hipStream_t);
-template void k_arnoldi_close<double>(double*, size_t, int, size_t, KState*, double*, hipStream_t);
-template void k_arnoldi_close<float>(float*, size_t, int, size_t, KState*, double*, hipStream_t);
+template void k_gs_reduce<double>(const double*, size_t, int, size_t, KState*, double*, bool, hipStream_t);
+template void k_gs_reduce<float>(const float*, size_t, int, size_t, KState*, double*, bool, hipStream_t);
+template void k_gs_update<double>(double*, size_t, int, size_t, const KState*, hipStream_t);
+template void k_gs_update<float>(float*, size_t, int, size_t, const KState*, hipStream_t);
 template void k_combine<double, double>(const double*, size_t, const KState*, const double*, double*, double*,
                                         double, const double*, size_t, hipStream_t);
 template void k_combine<float, float>(const float*, size_t, const KState*, const double*, double*, float*,

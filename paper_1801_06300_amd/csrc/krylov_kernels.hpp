@@ -49,12 +49,15 @@ size_t gs_blocks(size_t n);
 void k_init_state(KState* ks, double eta, hipStream_t st);
 template <typename TV>
 void k_start(const double* b, TV* V0, size_t n, KState* ks, double* part, hipStream_t st);
-// Iteration j after the JVP has written W = J(sigma_j V_j) into slot j+1.
+// Iteration j, after the JVP has written W = J(sigma_j V_j) into slot j+1:
+// reduce (one pass over V_0..V_{j+1}), finalize (one block), update (one pass
+// rewriting V_j and V_{j+1}).  With close = true and j = m (after the last
+// iteration) reduce + finalize complete column m-1 of H.
 template <typename TV>
-void k_arnoldi_iter(TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st);
-// After the last iteration: completes column m-1 of H.
+void k_gs_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, double* part, bool close, hipStream_t st);
+void k_gs_finalize(KState* ks, const double* part, int j, size_t n, bool close, hipStream_t st);
 template <typename TV>
-void k_arnoldi_close(TV* V, size_t ld, int m, size_t n, KState* ks, double* part, hipStream_t st);
+void k_gs_update(TV* V, size_t ld, int j, size_t n, const KState* ks, hipStream_t st);
 void k_hess_phi(KState* ks, const double* dt, int k, int m, double* scratch, hipStream_t st);
 template <typename TV, typename TX>
 void k_combine(const TV* V, size_t ld, const KState* ks, const double* base, double* out,

@@ -15,7 +15,12 @@
 #include "../../include/pcexp.h"
 #include "dg_dispatch.hpp"
 #include "krylov_kernels.hpp"
+#include "launch.hpp"
 #include "setup.hpp"
+
+namespace pcexp {
+thread_local LaunchTiming g_launch_timing;
+}  // namespace pcexp
 
 using namespace pcexp;
 
@@ -137,9 +142,12 @@ ElemArgs elem_args(const pcexp_ctx* c) {
 
 const double kSqrtEps = 1.4901161193847656e-08;  // sqrt(2^-52)
 
-enum { PC_RES = 0, PC_JVP = 1, PC_GS = 2, PC_PHI = 5, PC_COMB = 6, PC_OTHER = 7 };
+enum { PC_RES = 0, PC_JVP = 1, PC_GSR = 2, PC_GSF = 3, PC_GSU = 4, PC_PHI = 5, PC_COMB = 6, PC_OTHER = 7 };
 
-// Brackets one launch with events when profiling is on (no-op otherwise).
+// Times the one kernel launched in its scope when profiling is on (no-op
+// otherwise): the event pair is handed to that launch, so it measures the
+// kernel's own execution.  If no launch consumed the pair (the operation was
+// skipped on the host), both events are recorded here and the interval is ~0.
 struct Prof {
   pcexp_ctx* c;
   hipStream_t st;
@@ -150,10 +158,14 @@ struct Prof {
     if (2 * k + 1 >= c->ev.size()) return;
     idx = (int)k;
     c->recs.push_back({cls, bytes, (int)(2 * k)});
-    (void)hipEventRecord(c->ev[2 * k], st);
+    g_launch_timing.start = c->ev[2 * k];
+    g_launch_timing.stop = c->ev[2 * k + 1];
   }
   ~Prof() {
-    if (idx >= 0) (void)hipEventRecord(c->ev[2 * idx + 1], st);
+    if (idx < 0 || !g_launch_timing.start) return;
+    g_launch_timing.start = g_launch_timing.stop = nullptr;
+    (void)hipEventRecord(c->ev[2 * idx], st);
+    (void)hipEventRecord(c->ev[2 * idx + 1], st);
   }
 };
 
@@ -261,14 +273,16 @@ void arnoldi_run(pcexp_ctx* c, int jvp, int prec, const double* u_lin, const flo
     jvp_int(c, jvp, prec, u_lin, u32, V + (size_t)j * ld, V + (size_t)(j + 1) * ld, &ks->sigma[j], &ks->done,
             Rlin, &ks->fd_eps, st);
     const double vb = (double)c->K * sizeof(TV);
-    // reduction pass reads j + 2 vectors; update pass reads j + 2 and writes 2
-    Prof pr(c, st, PC_GS, (2.0 * (j + 2) + 2.0) * vb);
-    k_arnoldi_iter<TV>(V, ld, j, n, ks, part, st);
+    // the reduction pass reads j + 2 vectors; the update pass reads j + 2 and writes 2
+    { Prof pr(c, st, PC_GSR, (j + 2.0) * vb); k_gs_reduce<TV>(V, ld, j, n, ks, part, false, st); }
+    { Prof pr(c, st, PC_GSF, 0.0); k_gs_finalize(ks, part, j, n, false, st); }
+    { Prof pr(c, st, PC_GSU, (j + 4.0) * vb); k_gs_update<TV>(V, ld, j, n, ks, st); }
   }
   {
-    Prof pr(c, st, PC_GS, (m + 1.0) * (double)c->K * sizeof(TV));
-    k_arnoldi_close<TV>(V, ld, m, n, ks, part, st);
+    Prof pr(c, st, PC_GSR, (m + 1.0) * (double)c->K * sizeof(TV));
+    k_gs_reduce<TV>(V, ld, m, n, ks, part, true, st);
   }
+  { Prof pr(c, st, PC_GSF, 0.0); k_gs_finalize(ks, part, m, n, true, st); }
   { Prof pr(c, st, PC_PHI, 0.0); k_hess_phi(ks, dtp, k, m, phi, st); }
 }
 
