@@ -152,9 +152,18 @@ pcexp_status pcexp_residual(pcexp_ctx* ctx, const double* u, double* R, void* st
 pcexp_status pcexp_jvp(pcexp_ctx* ctx, const double* u, const double* v, double* Jv,
                        int32_t jvp, int32_t prec, void* stream);
 
-/* JTw = J(u)^T w, the transpose of the exact Jacobian of Sec. 4.4 (FP64). */
+/* JTw = J(u)^T w, the transpose of the exact Jacobian of Sec. 4.4 (FP64).
+ * Dense contexts: A_jac^T w. */
 pcexp_status pcexp_vjp(pcexp_ctx* ctx, const double* u, const double* w, double* JTw,
                        void* stream);
+
+/* Second-order adjoint term (reverse mode through an operator that depends on
+ * u; not part of the paper, which has no adjoint): in one pass
+ * JTw = J(u)^T w and dJTw = d/deps [J(u + eps v)^T w] = (d_u [J(u) v])^T w,
+ * by nested forward-mode differentiation of the VJP.  All arrays device FP64,
+ * ABI layout, distinct from w and from each other.  Dense contexts: dJTw = 0. */
+pcexp_status pcexp_vjp2(pcexp_ctx* ctx, const double* u, const double* v, const double* w,
+                        double* JTw, double* dJTw, void* stream);
 
 /* dt of eq. (x3d): CFL min_E h_E / ((2p+1)(|v| + c)), h_E = 2d|E|/|dE|, with v and c
  * at the element centroid.  Synchronises; result on the host. */
@@ -181,6 +190,31 @@ pcexp_status pcexp_arnoldi_phi(pcexp_ctx* ctx, const double* u_lin, const double
 pcexp_status pcexp_step(pcexp_ctx* ctx, double* u, double dt, double cfl, int32_t m,
                         int32_t scheme, int32_t prec, int32_t jvp, void* ws, size_t ws_bytes,
                         pcexp_step_info* info, void* stream);
+
+/* Objective for reverse-mode tests: value_host = int_Omega (p_h - p_ref)^2 dx
+ * by the volume quadrature rule, p = (gamma-1)(rho E - |rho v|^2 / (2 rho))
+ * (Sec. 4.1); grad (optional, device, ABI layout, != u) = d value / d u.
+ * Synchronises. */
+pcexp_status pcexp_pressure_functional(pcexp_ctx* ctx, const double* u, double p_ref,
+                                       double* value_host, double* grad, void* stream);
+
+/* Reverse mode of one step (the discrete adjoint of pcexp_step in FP64 with
+ * the tangent JVP; not part of the paper): ubar_n = (d u_{n+1} / d u_n)^T
+ * ubar_np1 for the step u_n -> u_{n+1} of eqs. (s9)-(s10) (scheme PCEXP) or
+ * (s8) (EXP1) with the fixed time step dt > 0 and Krylov dimension m.  The
+ * step is recomputed from u_n with both Krylov bases kept in the workspace,
+ * then swept backwards: reverse Arnoldi (Gram-Schmidt relations, the adjoint
+ * of the Frechet derivative of the Hessenberg exponential, J^T and the
+ * second-order term of pcexp_vjp2 per basis vector) and the reverse glue.
+ * The result is the exact derivative of the Krylov approximation (not of the
+ * exact exponential).  Arrays device FP64, ABI layout; ubar_n != ubar_np1.
+ * Workspace: pcexp_step_vjp_workspace_bytes (3(m+1) + 14 vectors of K plus
+ * small state), 256-byte aligned, caller-owned.  Synchronises once (to read
+ * the Krylov dimensions reached). */
+size_t pcexp_step_vjp_workspace_bytes(const pcexp_ctx* ctx, int32_t m);
+pcexp_status pcexp_step_vjp(pcexp_ctx* ctx, const double* u_n, double dt, int32_t m,
+                            int32_t scheme, const double* ubar_np1, double* ubar_n, void* ws,
+                            size_t ws_bytes, void* stream);
 
 /* Kernel-class timing with HIP events for the launches made by pcexp_step /
  * pcexp_arnoldi_phi (for roofline reports).  Each timed operation is one

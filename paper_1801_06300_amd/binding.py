@@ -68,6 +68,11 @@ _SIGS = {
     "pcexp_residual": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "pcexp_jvp": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, _VP]),
     "pcexp_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "pcexp_vjp2": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "pcexp_step_vjp_workspace_bytes": (ctypes.c_size_t, [_VP, ctypes.c_int32]),
+    "pcexp_pressure_functional": (ctypes.c_int, [_VP, _VP, ctypes.c_double, c_double_p, _VP, _VP]),
+    "pcexp_step_vjp": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP,
+                                      ctypes.c_size_t, _VP]),
     "pcexp_stable_dt": (ctypes.c_int, [_VP, _VP, ctypes.c_double, c_double_p, _VP]),
     "pcexp_conserved_totals": (ctypes.c_int, [_VP, _VP, c_double_p, _VP]),
     "pcexp_arnoldi_phi": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
@@ -241,6 +246,41 @@ class PCEXP:
         w = self._vec(w, self.shape)
         out = self.empty() if out is None else out
         self._check(self.lib.pcexp_vjp(self.ctx, _ptr(u), _ptr(w), _ptr(out), self._stream()), "vjp")
+        return out
+
+    def vjp2(self, u, v, w):
+        """(J(u)^T w, d/deps [J(u + eps v)^T w]) in one pass."""
+        u = self._vec(u, self.shape)
+        v = self._vec(v, self.shape)
+        w = self._vec(w, self.shape)
+        out, out_d = self.empty(), self.empty()
+        self._check(self.lib.pcexp_vjp2(self.ctx, _ptr(u), _ptr(v), _ptr(w), _ptr(out), _ptr(out_d),
+                                        self._stream()), "vjp2")
+        return out, out_d
+
+    def pressure_functional(self, u, p_ref=1.0, grad=False):
+        """int (p_h - p_ref)^2 dx, and its gradient with respect to u if grad."""
+        u = self._vec(u, self.shape)
+        val = ctypes.c_double()
+        g = self.empty() if grad else None
+        self._check(self.lib.pcexp_pressure_functional(self.ctx, _ptr(u), float(p_ref), ctypes.byref(val),
+                                                       _ptr(g) if grad else None, self._stream()),
+                    "pressure_functional")
+        return (val.value, g) if grad else val.value
+
+    def step_vjp(self, u, ubar, dt, m=30, scheme="pcexp"):
+        """(d u_{n+1} / d u_n)^T ubar for the step from u with fixed dt (FP64, tangent JVP)."""
+        u = self._vec(u, self.shape)
+        ubar = self._vec(ubar, self.shape)
+        nbytes = self.lib.pcexp_step_vjp_workspace_bytes(self.ctx, m)
+        key = ("rev", m)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
+            self._ws[key] = ws
+        out = self.empty()
+        self._check(self.lib.pcexp_step_vjp(self.ctx, _ptr(u), float(dt), m, SCHEME[scheme], _ptr(ubar), _ptr(out),
+                                            _ptr(ws), nbytes, self._stream()), "step_vjp")
         return out
 
     def stable_dt(self, u, cfl):

@@ -39,13 +39,26 @@ bool dg_run2_f(int p, int flux, int mode, const DGParams<float>& prm, const DGIO
   return run<float>(p, flux, mode, prm, io, st);
 }
 
-bool dg_vjp2(int p, int flux, const DGParams<double>& prm, const double* u, const double* w, double* out,
-             hipStream_t st) {
+template <int P>
+static bool vjp_p(int flux, const DGParams<double>& prm, const double* u, const double* v, const double* w,
+                  double* out, double* out_d, hipStream_t st) {
+  if (out_d) {
+    if (flux == FLUX_LF) launch_vjp2<2, P, FLUX_LF>(prm, u, v, w, out, out_d, st);
+    else launch_vjp2<2, P, FLUX_ROE>(prm, u, v, w, out, out_d, st);
+  } else {
+    if (flux == FLUX_LF) launch_vjp<2, P, FLUX_LF>(prm, u, w, out, st);
+    else launch_vjp<2, P, FLUX_ROE>(prm, u, w, out, st);
+  }
+  return true;
+}
+
+bool dg_vjp2(int p, int flux, const DGParams<double>& prm, const double* u, const double* v, const double* w,
+             double* out, double* out_d, hipStream_t st) {
   switch (p) {
-    case 0: if (flux == FLUX_LF) launch_vjp<2, 0, FLUX_LF>(prm, u, w, out, st); else launch_vjp<2, 0, FLUX_ROE>(prm, u, w, out, st); return true;
-    case 1: if (flux == FLUX_LF) launch_vjp<2, 1, FLUX_LF>(prm, u, w, out, st); else launch_vjp<2, 1, FLUX_ROE>(prm, u, w, out, st); return true;
-    case 2: if (flux == FLUX_LF) launch_vjp<2, 2, FLUX_LF>(prm, u, w, out, st); else launch_vjp<2, 2, FLUX_ROE>(prm, u, w, out, st); return true;
-    case 3: if (flux == FLUX_LF) launch_vjp<2, 3, FLUX_LF>(prm, u, w, out, st); else launch_vjp<2, 3, FLUX_ROE>(prm, u, w, out, st); return true;
+    case 0: return vjp_p<0>(flux, prm, u, v, w, out, out_d, st);
+    case 1: return vjp_p<1>(flux, prm, u, v, w, out, out_d, st);
+    case 2: return vjp_p<2>(flux, prm, u, v, w, out, out_d, st);
+    case 3: return vjp_p<3>(flux, prm, u, v, w, out, out_d, st);
   }
   return false;
 }

@@ -18,10 +18,11 @@ bool dg_run2_f(int p, int flux, int mode, const DGParams<float>& prm, const DGIO
 bool dg_run3_f(int p, int flux, int mode, const DGParams<float>& prm, const DGIO<float>& io, hipStream_t st);
 
 // Transpose J(u)^T w (FP64).
-bool dg_vjp2(int p, int flux, const DGParams<double>& prm, const double* u, const double* w, double* out,
-             hipStream_t st);
-bool dg_vjp3(int p, int flux, const DGParams<double>& prm, const double* u, const double* w, double* out,
-             hipStream_t st);
+// out = J(u)^T w; if out_d is not null also out_d = d/deps [J(u + eps v)^T w].
+bool dg_vjp2(int p, int flux, const DGParams<double>& prm, const double* u, const double* v, const double* w,
+             double* out, double* out_d, hipStream_t st);
+bool dg_vjp3(int p, int flux, const DGParams<double>& prm, const double* u, const double* v, const double* w,
+             double* out, double* out_d, hipStream_t st);
 
 // Element-level helpers (elem_kernels.hip); runtime sizes, not on the hot path.
 struct ElemArgs {
@@ -40,6 +41,10 @@ struct ElemArgs {
   double gamma;
 };
 void ek_to_internal(const ElemArgs& a, const double* u_abi, double* u_int, hipStream_t st);
+// value = int (p_h - p_ref)^2 dx (device scalar); grad_int (optional) its
+// gradient with respect to the internal coefficients; part >= Epad/256 doubles.
+void ek_pressure_functional(const ElemArgs& a, const double* u_int, double p_ref, double* value, double* grad_int,
+                            double* part, hipStream_t st);
 void ek_to_abi(const ElemArgs& a, const double* u_int, double* u_abi, hipStream_t st);
 void ek_quad_points(const ElemArgs& a, double* xyz, hipStream_t st);
 void ek_project(const ElemArgs& a, const double* Uqp, double* u_abi, hipStream_t st);

@@ -367,33 +367,61 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
 // (c) for each interior face, the adjoint of the neighbour N's face term
 // F~(U_N, U_E, n_N) with respect to its second argument, evaluated with N's
 // own geometry exactly as N's forward residual does.  Flux Jacobians come from
-// forward-mode Dual<T, NV> numbers seeded on the state being differentiated.
-template <int D, int P, int FLUX>
+// forward-mode Dual<ST, NV> numbers seeded on the state being differentiated.
+//
+// ST = double gives J(u)^T w.  ST = Dual<double, 1> runs the same code on the
+// state u + eps v: the value part is J(u)^T w and the eps part is
+// d/deps [J(u + eps v)^T w] = (d_u [J(u) v])^T w, the second-order term of the
+// reverse sweep through an Arnoldi process whose operator depends on u.
+template <typename ST> struct StateScalar;
+template <> struct StateScalar<double> {
+  static constexpr bool SECOND = false;
+  __device__ static double make(double u, double) { return u; }
+  __device__ static double value(double x) { return x; }
+  __device__ static double deriv(double) { return 0.0; }
+};
+template <> struct StateScalar<Dual<double, 1>> {
+  static constexpr bool SECOND = true;
+  __device__ static Dual<double, 1> make(double u, double v) {
+    Dual<double, 1> r;
+    r.v = u;
+    r.d[0] = v;
+    return r;
+  }
+  __device__ static double value(const Dual<double, 1>& x) { return x.v; }
+  __device__ static double deriv(const Dual<double, 1>& x) { return x.d[0]; }
+};
+
+template <int D, int P, int FLUX, typename ST>
 struct VjpTile {
   using Sh = Shape<D, P>;
   static constexpr int NX = (Sh::NQ > Sh::NF * Sh::NFQ ? Sh::NQ : Sh::NF * Sh::NFQ) * Sh::NV;
-  static constexpr int per_elem = 8 * (2 * Sh::NVB + NX) + Sh::NF;
+  static constexpr int per_elem = (int)sizeof(ST) * (Sh::NVB + NX) + 8 * Sh::NVB + Sh::NF;
   static constexpr int TE = (64 * per_elem <= kLdsBudget) ? 64
                             : (32 * per_elem <= kLdsBudget) ? 32
-                            : (16 * per_elem <= kLdsBudget) ? 16 : 8;
+                            : (16 * per_elem <= kLdsBudget) ? 16
+                            : (8 * per_elem <= kLdsBudget) ? 8 : 4;
 };
 
-template <int D, int P, int FLUX>
+template <int D, int P, int FLUX, typename ST>
 __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const double* __restrict__ u,
-                                                     const double* __restrict__ w, double* __restrict__ out) {
+                                                     const double* __restrict__ vdir,
+                                                     const double* __restrict__ w, double* __restrict__ out,
+                                                     double* __restrict__ out_d) {
   using T = double;
+  using SS = StateScalar<ST>;
   using Sh = Shape<D, P>;
   constexpr int NV = Sh::NV, NB = Sh::NB, NVB = Sh::NVB, NQ = Sh::NQ, NFQ = Sh::NFQ;
   constexpr int NF = Sh::NF, NORI = Sh::NORI;
-  constexpr int TE = VjpTile<D, P, FLUX>::TE;
-  constexpr int NX = VjpTile<D, P, FLUX>::NX;
+  constexpr int TE = VjpTile<D, P, FLUX, ST>::TE;
+  constexpr int NX = VjpTile<D, P, FLUX, ST>::NX;
   constexpr int NT = 256;
   constexpr int NOUT = (NVB * TE + NT - 1) / NT;
-  using SD = Dual<T, NV>;
+  using SD = Dual<ST, NV>;
 
-  __shared__ T su[NVB * TE];
+  __shared__ ST su[NVB * TE];
   __shared__ T sw[NVB * TE];
-  __shared__ T sx[NX * TE];
+  __shared__ ST sx[NX * TE];
   __shared__ unsigned char sori[NF * TE];
 
   const int Epad = prm.Epad, nE = prm.nE;
@@ -403,13 +431,14 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
 
   for (int t = tid; t < NVB * TE; t += NT) {
     const int ki = t / TE, e = t % TE, ge = e0 + e;
-    su[t] = ge < nE ? u[(size_t)ki * Epad + ge] : T(0);
-    sw[t] = ge < nE ? w[(size_t)ki * Epad + ge] : T(0);
+    const bool in = ge < nE;
+    su[t] = SS::make(in ? u[(size_t)ki * Epad + ge] : T(0), (SS::SECOND && in) ? vdir[(size_t)ki * Epad + ge] : T(0));
+    sw[t] = in ? w[(size_t)ki * Epad + ge] : T(0);
   }
   __syncthreads();
-  T acc[NOUT];
+  ST acc[NOUT];
 #pragma unroll
-  for (int o = 0; o < NOUT; ++o) acc[o] = T(0);
+  for (int o = 0; o < NOUT; ++o) acc[o] = ST(0);
 
   // ---- (a) volume adjoint
   for (int t = tid; t < NQ * TE; t += NT) {
@@ -419,16 +448,16 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
     SD U[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      T a = T(0);
+      ST a = ST(0);
 #pragma unroll
-      for (int i = 0; i < NB; ++i) a += su[(k * NB + i) * TE + e] * prm.B[q * NB + i];
+      for (int i = 0; i < NB; ++i) a = a + su[(k * NB + i) * TE + e] * prm.B[q * NB + i];
       U[k].v = a * rs;
 #pragma unroll
-      for (int j = 0; j < NV; ++j) U[k].d[j] = (j == k) ? T(1) : T(0);
+      for (int j = 0; j < NV; ++j) U[k].d[j] = ST((j == k) ? 1.0 : 0.0);
     }
-    T Ub[NV];
+    ST Ub[NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) Ub[j] = T(0);
+    for (int j = 0; j < NV; ++j) Ub[j] = ST(0);
 #pragma unroll
     for (int r = 0; r < D; ++r) {
       T a[D];
@@ -443,7 +472,7 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
         for (int i = 0; i < NB; ++i) gb += sw[(k * NB + i) * TE + e] * prm.Dg[(q * NB + i) * D + r];
         gb *= sd * prm.wq[q];
 #pragma unroll
-        for (int j = 0; j < NV; ++j) Ub[j] += gb * F[k].d[j];
+        for (int j = 0; j < NV; ++j) Ub[j] = Ub[j] + F[k].d[j] * gb;
       }
     }
 #pragma unroll
@@ -455,10 +484,10 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
     const int t = tid + o * NT;
     if (t < NVB * TE) {
       const int ki = t / TE, e = t % TE, k = ki / NB, i = ki % NB;
-      T s = T(0);
+      ST s = ST(0);
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) s += sx[(q * NV + k) * TE + e] * prm.B[q * NB + i];
-      acc[o] += s;
+      for (int q = 0; q < NQ; ++q) s = s + sx[(q * NV + k) * TE + e] * prm.B[q * NB + i];
+      acc[o] = acc[o] + s;
     }
   }
   __syncthreads();
@@ -477,15 +506,16 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
     T wl[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      T a = T(0), b = T(0);
+      ST a = ST(0);
+      T b = T(0);
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
-        a += su[(k * NB + i) * TE + e] * bl[i];
+        a = a + su[(k * NB + i) * TE + e] * bl[i];
         b += sw[(k * NB + i) * TE + e] * bl[i];
       }
       UE[k].v = a * rs;
 #pragma unroll
-      for (int j = 0; j < NV; ++j) UE[k].d[j] = (j == k) ? T(1) : T(0);
+      for (int j = 0; j < NV; ++j) UE[k].d[j] = ST((j == k) ? 1.0 : 0.0);
       wl[k] = b;
     }
     T nl[D], len2 = T(0);
@@ -501,7 +531,7 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
     T n[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) n[c] = nl[c] / len;
-    T Ub[NV];
+    ST Ub[NV];
     const T cs = -prm.wf[r] * len * rs;   // seed scale of the own face term
     if (nb >= 0) {
       const int fN = info & 3, oN = (info >> 2) & 7;
@@ -511,22 +541,24 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
       T wn[NV];
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
-        T a = T(0), b = T(0);
+        ST a = ST(0);
+        T b = T(0);
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-          a += u[(size_t)(k * NB + i) * Epad + nb] * br[i];
-          b += w[(size_t)(k * NB + i) * Epad + nb] * br[i];
+          const size_t g = (size_t)(k * NB + i) * Epad + nb;
+          a = a + SS::make(u[g], SS::SECOND ? vdir[g] : T(0)) * br[i];
+          b += w[g] * br[i];
         }
-        UN[k] = mkconst<T, NV>(a * rsN);
+        UN[k] = mkconst<ST, NV>(a * rsN);
         wn[k] = b;
       }
       SD F[NV];
       num_flux<D, FLUX>(UE, UN, n, prm.gamma, F);
 #pragma unroll
       for (int j = 0; j < NV; ++j) {
-        T s = T(0);
+        ST s = ST(0);
 #pragma unroll
-        for (int k = 0; k < NV; ++k) s += cs * wl[k] * F[k].d[j];
+        for (int k = 0; k < NV; ++k) s = s + F[k].d[j] * (cs * wl[k]);
         Ub[j] = s;
       }
       // neighbour's own geometry: |f|_N n_N = det(A_N) A_N^{-T} nref_{fN}
@@ -546,10 +578,10 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
       const T cn = -prm.wf[r] * lenN * rsN;
 #pragma unroll
       for (int j = 0; j < NV; ++j) {
-        T s = T(0);
+        ST s = ST(0);
 #pragma unroll
-        for (int k = 0; k < NV; ++k) s += cn * wn[k] * F[k].d[j];
-        Ub[j] += s;
+        for (int k = 0; k < NV; ++k) s = s + F[k].d[j] * (cn * wn[k]);
+        Ub[j] = Ub[j] + s;
       }
     } else {
       SD G[NV], F[NV];
@@ -558,9 +590,9 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
       num_flux<D, FLUX>(UE, G, n, prm.gamma, F);
 #pragma unroll
       for (int j = 0; j < NV; ++j) {
-        T s = T(0);
+        ST s = ST(0);
 #pragma unroll
-        for (int k = 0; k < NV; ++k) s += cs * wl[k] * F[k].d[j];
+        for (int k = 0; k < NV; ++k) s = s + F[k].d[j] * (cs * wl[k]);
         Ub[j] = s;
       }
     }
@@ -574,24 +606,37 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
     if (t < NVB * TE) {
       const int ki = t / TE, e = t % TE, k = ki / NB, i = ki % NB, ge = e0 + e;
       if (ge < nE) {
-        T s = T(0);
+        ST s = ST(0);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
           const T* bl = prm.Bf + (f * NORI + sori[f * TE + e]) * NFQ * NB;
 #pragma unroll
-          for (int r = 0; r < NFQ; ++r) s += sx[((f * NFQ + r) * NV + k) * TE + e] * bl[r * NB + i];
+          for (int r = 0; r < NFQ; ++r) s = s + sx[((f * NFQ + r) * NV + k) * TE + e] * bl[r * NB + i];
         }
-        acc[o] += s;
+        acc[o] = acc[o] + s;
       }
-      if (ge < Epad) out[(size_t)ki * Epad + ge] = ge < nE ? acc[o] : T(0);
+      if (ge < Epad) {
+        out[(size_t)ki * Epad + ge] = ge < nE ? SS::value(acc[o]) : T(0);
+        if (SS::SECOND) out_d[(size_t)ki * Epad + ge] = ge < nE ? SS::deriv(acc[o]) : T(0);
+      }
     }
   }
 }
 
 template <int D, int P, int FLUX>
 void launch_vjp(const DGParams<double>& prm, const double* u, const double* w, double* out, hipStream_t st) {
-  constexpr int TE = VjpTile<D, P, FLUX>::TE;
-  launch((dg_vjp_kernel<D, P, FLUX>), dim3((prm.Epad + TE - 1) / TE), dim3(256), 0, st, prm, u, w, out);
+  constexpr int TE = VjpTile<D, P, FLUX, double>::TE;
+  launch((dg_vjp_kernel<D, P, FLUX, double>), dim3((prm.Epad + TE - 1) / TE), dim3(256), 0, st, prm, u,
+         (const double*)nullptr, w, out, (double*)nullptr);
+}
+
+// out = J(u)^T w and out_d = d/deps [J(u + eps v)^T w] in one pass.
+template <int D, int P, int FLUX>
+void launch_vjp2(const DGParams<double>& prm, const double* u, const double* v, const double* w, double* out,
+                 double* out_d, hipStream_t st) {
+  constexpr int TE = VjpTile<D, P, FLUX, Dual<double, 1>>::TE;
+  launch((dg_vjp_kernel<D, P, FLUX, Dual<double, 1>>), dim3((prm.Epad + TE - 1) / TE), dim3(256), 0, st, prm, u,
+         v, w, out, out_d);
 }
 
 // Host launchers (defined in the per-dimension translation units).

@@ -12,13 +12,27 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace pcexp {
 
+// Forward-mode number: value v and N directional derivatives d[].  T may
+// itself be a Dual (nested forward mode: Dual<Dual<double, 1>, N> carries the
+// N first derivatives and their derivative along one more direction, which is
+// what the second-order adjoint term needs).
 template <typename T, int N>
 struct Dual {
   T v;
   T d[N];
+  Dual() = default;
+  // constant (all derivatives zero)
+  __host__ __device__ Dual(double c) : v(c) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) d[i] = T(0);
+  }
 };
+
+template <typename U> struct IsPlain { static constexpr bool value = std::is_arithmetic<U>::value; };
 
 template <typename T> struct ScalarOf { using type = T; };
 template <typename T, int N> struct ScalarOf<Dual<T, N>> { using type = T; };
@@ -134,6 +148,76 @@ __device__ __forceinline__ Dual<T, N> operator/(T a, const Dual<T, N>& b) {
   return r;
 }
 
+// Plain scalars (double, float, int) against a Dual whose component type is
+// a different type (a nested Dual): applied to the value and every derivative.
+#define PCEXP_DUAL_PLAIN(OP)                                                                   \
+  template <typename T, int N, typename U,                                                     \
+            typename std::enable_if<IsPlain<U>::value && !std::is_same<U, T>::value, int>::type = 0> \
+  __device__ __forceinline__ Dual<T, N> operator OP(const Dual<T, N>& a, U b) {                \
+    Dual<T, N> r;                                                                              \
+    r.v = a.v OP b;                                                                            \
+    _Pragma("unroll") for (int i = 0; i < N; ++i) r.d[i] = PCEXP_DUAL_PLAIN_D(a.d[i], b);     \
+    return r;                                                                                  \
+  }
+#define PCEXP_DUAL_PLAIN_D(x, b) (x)
+PCEXP_DUAL_PLAIN(+)
+PCEXP_DUAL_PLAIN(-)
+#undef PCEXP_DUAL_PLAIN_D
+#define PCEXP_DUAL_PLAIN_D(x, b) ((x) * (b))
+PCEXP_DUAL_PLAIN(*)
+#undef PCEXP_DUAL_PLAIN_D
+#define PCEXP_DUAL_PLAIN_D(x, b) ((x) * (1.0 / (b)))
+PCEXP_DUAL_PLAIN(/)
+#undef PCEXP_DUAL_PLAIN_D
+#undef PCEXP_DUAL_PLAIN
+
+template <typename T, int N, typename U,
+          typename std::enable_if<IsPlain<U>::value && !std::is_same<U, T>::value, int>::type = 0>
+__device__ __forceinline__ Dual<T, N> operator+(U b, const Dual<T, N>& a) { return a + b; }
+template <typename T, int N, typename U,
+          typename std::enable_if<IsPlain<U>::value && !std::is_same<U, T>::value, int>::type = 0>
+__device__ __forceinline__ Dual<T, N> operator*(U b, const Dual<T, N>& a) { return a * b; }
+template <typename T, int N, typename U,
+          typename std::enable_if<IsPlain<U>::value && !std::is_same<U, T>::value, int>::type = 0>
+__device__ __forceinline__ Dual<T, N> operator-(U b, const Dual<T, N>& a) {
+  Dual<T, N> r;
+  r.v = b - a.v;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = -a.d[i];
+  return r;
+}
+template <typename T, int N, typename U,
+          typename std::enable_if<IsPlain<U>::value && !std::is_same<U, T>::value, int>::type = 0>
+__device__ __forceinline__ Dual<T, N> operator/(U a, const Dual<T, N>& b) {
+  Dual<T, N> r;
+  T ib = T(1) / b.v;
+  r.v = a * ib;
+  T f = -r.v * ib;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = f * b.d[i];
+  return r;
+}
+
+// Comparisons look at values only.
+#define PCEXP_DUAL_CMP(OP)                                                                      \
+  template <typename T, int N>                                                                  \
+  __device__ __forceinline__ bool operator OP(const Dual<T, N>& a, const Dual<T, N>& b) {       \
+    return a.v OP b.v;                                                                          \
+  }                                                                                             \
+  template <typename T, int N, typename U, typename std::enable_if<IsPlain<U>::value, int>::type = 0> \
+  __device__ __forceinline__ bool operator OP(const Dual<T, N>& a, U b) {                       \
+    return a.v OP b;                                                                            \
+  }                                                                                             \
+  template <typename T, int N, typename U, typename std::enable_if<IsPlain<U>::value, int>::type = 0> \
+  __device__ __forceinline__ bool operator OP(U a, const Dual<T, N>& b) {                       \
+    return a OP b.v;                                                                            \
+  }
+PCEXP_DUAL_CMP(>)
+PCEXP_DUAL_CMP(<)
+PCEXP_DUAL_CMP(>=)
+PCEXP_DUAL_CMP(<=)
+#undef PCEXP_DUAL_CMP
+
 // ---- elementary functions (value and Dual)
 __device__ __forceinline__ double s_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float s_sqrt(float x) { return sqrtf(x); }
@@ -168,11 +252,11 @@ template <typename T, int N>
 __device__ __forceinline__ Dual<T, N> s_max(const Dual<T, N>& a, const Dual<T, N>& b) {
   return a.v >= b.v ? a : b;
 }
-template <typename T, int N>
-__device__ __forceinline__ Dual<T, N> s_pow(const Dual<T, N>& a, T e) {
+template <typename T, int N, typename E, typename std::enable_if<IsPlain<E>::value, int>::type = 0>
+__device__ __forceinline__ Dual<T, N> s_pow(const Dual<T, N>& a, E e) {
   Dual<T, N> r;
   r.v = s_pow(a.v, e);
-  T f = e * s_pow(a.v, e - T(1));
+  T f = e * s_pow(a.v, e - E(1));
 #pragma unroll
   for (int i = 0; i < N; ++i) r.d[i] = f * a.d[i];
   return r;

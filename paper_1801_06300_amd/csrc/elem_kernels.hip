@@ -187,6 +187,72 @@ __global__ void totals_finalize(const double* part, int nblk, int nv, double* ou
   }
 }
 
+// Pressure functional P(u) = int_Omega (p_h - p_ref)^2 dx by the volume rule,
+// and its gradient with respect to the internal coefficients:
+//   dP/du_{k,i,E} = sum_q w_q s_E 2 (p_q - p_ref) dp/dU_k(U_q) B_{q,i},
+// U_q = sum_i u_{k,i,E} B_{q,i} / s_E, dx = s_E^2 dxi (s_E = sqrt(det A_E)).
+// One thread per element; per-block partial sums of P (fixed order).
+__global__ void pfun_kernel(ElemArgs a, const double* __restrict__ u, double p_ref, double* part, double* grad) {
+  const int e = blockIdx.x * EK_T + threadIdx.x;
+  const int nb = a.nb, nv = a.nv, d = a.dim;
+  double val = 0.0;
+  if (e < a.nE) {
+    const double s = a.sdet[e], rs = 1.0 / s;
+    const double gm1 = a.gamma - 1.0;
+    double g[5 * MAXNB];
+    for (int t = 0; t < nv * nb; ++t) g[t] = 0.0;
+    for (int q = 0; q < a.nq; ++q) {
+      double U[5];
+      for (int k = 0; k < nv; ++k) {
+        double x = 0.0;
+        for (int i = 0; i < nb; ++i) x += u[(size_t)(k * nb + i) * a.Epad + e] * a.B[q * nb + i];
+        U[k] = x * rs;
+      }
+      const double rho = U[0];
+      double m2 = 0.0;
+      for (int c = 0; c < d; ++c) m2 += U[1 + c] * U[1 + c];
+      const double p = gm1 * (U[d + 1] - 0.5 * m2 / rho);
+      const double dp = p - p_ref;
+      val += a.wq[q] * s * s * dp * dp;
+      // dp/dU: (gm1 |m|^2 / (2 rho^2), -gm1 m / rho, gm1)
+      double dpdU[5];
+      dpdU[0] = 0.5 * gm1 * m2 / (rho * rho);
+      for (int c = 0; c < d; ++c) dpdU[1 + c] = -gm1 * U[1 + c] / rho;
+      dpdU[d + 1] = gm1;
+      const double f = a.wq[q] * s * 2.0 * dp;
+      for (int k = 0; k < nv; ++k)
+        for (int i = 0; i < nb; ++i) g[k * nb + i] += f * dpdU[k] * a.B[q * nb + i];
+    }
+    if (grad)
+      for (int t = 0; t < nv * nb; ++t) grad[(size_t)t * a.Epad + e] = g[t];
+  } else if (grad && e < a.Epad) {
+    for (int t = 0; t < nv * nb; ++t) grad[(size_t)t * a.Epad + e] = 0.0;
+  }
+  __shared__ double red[EK_T / 64];
+  const double wsum = ek_wave_sum(val);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = wsum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < EK_T / 64; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+__global__ void pfun_finalize(const double* part, int nblk, double* out) {
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) t += part[b];
+  t = ek_wave_sum(t);
+  if (threadIdx.x == 0) *out = t;
+}
+
+void ek_pressure_functional(const ElemArgs& a, const double* u_int, double p_ref, double* value, double* grad_int,
+                            double* part, hipStream_t st) {
+  const dim3 g = grid_for((size_t)a.Epad);
+  launch(pfun_kernel, g, dim3(EK_T), 0, st, a, u_int, p_ref, part, grad_int);
+  launch(pfun_finalize, dim3(1), dim3(64), 0, st, (const double*)part, (int)g.x, value);
+}
+
 void ek_to_internal(const ElemArgs& a, const double* u_abi, double* u_int, hipStream_t st) {
   launch(to_internal_kernel, grid_for((size_t)a.Epad * a.nv), dim3(EK_T), 0, st, a, u_abi, u_int);
 }

@@ -567,14 +567,10 @@ __device__ void mat_mul_add(const double* A, const double* B, const double* D, d
   __syncthreads();
 }
 
-__device__ void phi_body(KState* ks, const double* dtp, int k, double* mem) {
-  const int m = ks->m_eff;
+// exp(X) for the n x n matrix X = mem[0, n^2) (column-major), n <= 2 KMAX + 2;
+// mem holds 7 n^2 doubles.  Returns a pointer to the result inside mem.
+__device__ double* expm_core(double* mem, int n) {
   const int tid = threadIdx.x;
-  if (m == 0) {
-    for (int i = tid; i < KMAX + 4; i += PHI_T) ks->y[i] = 0.0;
-    return;
-  }
-  const int n = (k >= 1) ? m + k : m;
   const int nn = n * n;
   double* X = mem;          // scaled A
   double* X2 = X + nn;
@@ -583,21 +579,7 @@ __device__ void phi_body(KState* ks, const double* dtp, int k, double* mem) {
   double* Bq = X4 + nn;     // current block polynomial
   double* T0 = Bq + nn;     // ping-pong accumulators
   double* T1 = T0 + nn;
-  const double dt = *dtp;
-  for (int t = tid; t < nn; t += PHI_T) {
-    const int i = t % n, jj = t / n;
-    double v = 0.0;
-    if (i < m && jj < m) {
-      if (i <= jj + 1) v = dt * ks->H[(size_t)jj * KLD + i];
-    } else if (k >= 1 && jj == m && i == 0) {
-      v = 1.0;
-    } else if (k >= 2 && jj >= m + 1 && i == jj - 1) {
-      v = 1.0;
-    }
-    X[t] = v;
-  }
-  __syncthreads();
-  __shared__ double colsum[KMAX + 4];
+  __shared__ double colsum[2 * KMAX + 4];
   __shared__ int s_sq;
   for (int jj = tid; jj < n; jj += PHI_T) {
     double s = 0.0;
@@ -649,6 +631,34 @@ __device__ void phi_body(KState* ks, const double* dtp, int k, double* mem) {
     mat_mul(P, P, Q, n);
     double* t = P; P = Q; Q = t;
   }
+  return P;
+}
+
+__device__ void phi_body(KState* ks, const double* dtp, int k, double* mem) {
+  const int m = ks->m_eff;
+  const int tid = threadIdx.x;
+  if (m == 0) {
+    for (int i = tid; i < KMAX + 4; i += PHI_T) ks->y[i] = 0.0;
+    return;
+  }
+  const int n = (k >= 1) ? m + k : m;
+  const int nn = n * n;
+  double* X = mem;
+  const double dt = *dtp;
+  for (int t = tid; t < nn; t += PHI_T) {
+    const int i = t % n, jj = t / n;
+    double v = 0.0;
+    if (i < m && jj < m) {
+      if (i <= jj + 1) v = dt * ks->H[(size_t)jj * KLD + i];
+    } else if (k >= 1 && jj == m && i == 0) {
+      v = 1.0;
+    } else if (k >= 2 && jj >= m + 1 && i == jj - 1) {
+      v = 1.0;
+    }
+    X[t] = v;
+  }
+  __syncthreads();
+  const double* P = expm_core(mem, n);
   const int col = (k >= 1) ? n - 1 : 0;
   const double beta = ks->beta;
   for (int i = tid; i < KMAX + 4; i += PHI_T) ks->y[i] = (i < m) ? beta * P[col * n + i] : 0.0;
@@ -787,6 +797,246 @@ void k_gemv(const T* A, const T* v, T* out, int n, const double* vscale, const i
 }
 
 // explicit instantiations
+// ================================================================ reverse mode
+// Kernels of the reverse sweep through one Arnoldi run (FP64 basis).  The
+// basis vectors are v_i = sigma_i V_i; adjoint vectors are plain.
+
+// Partial dot products of x with sigma_i V_i, i in [i0, i0 + nvec): blockIdx.y
+// selects a chunk of RV_NV vectors; column c of the partials is vector i0 + c.
+constexpr int RV_NV = 16;
+
+__global__ __launch_bounds__(RT) void rv_dots_kernel(const double* __restrict__ V, size_t ld, int i0, int nvec,
+                                                     const double* __restrict__ x, size_t n, double* part) {
+  constexpr int NP = RV_NV;
+  const int c0 = blockIdx.y * RV_NV;
+  double acc[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) acc[i] = 0.0;
+  const size_t np = (n + 1) / 2;
+  for (size_t p = (size_t)blockIdx.x * RT + threadIdx.x; p < np; p += (size_t)gridDim.x * RT) {
+    double x0, x1;
+    load_pair(x, p, n, x0, x1);
+#pragma unroll
+    for (int i = 0; i < RV_NV; ++i) {
+      const int c = c0 + i < nvec ? c0 + i : nvec - 1;
+      double v0, v1;
+      load_pair(V + (size_t)(i0 + c) * ld, p, n, v0, v1);
+      acc[i] += v0 * x0 + v1 * x1;
+    }
+  }
+  __shared__ double red[RW][NP];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int col = 0;
+  Bfly<NP / 2, 32>::run(acc, lane, col);
+  if ((lane & (64 / NP - 1)) == 0) red[wid][col] = acc[0];
+  __syncthreads();
+  for (int c = threadIdx.x; c < RV_NV; c += RT) {
+    if (c0 + c < nvec) {
+      double t = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < RW; ++w2) t += red[w2][c];
+      part[(size_t)(c0 + c) * PLD + blockIdx.x] = t;
+    }
+  }
+}
+
+// out[c] = scale_c * sum of column c, scale_c = sigma[i0 + c] (or 1).
+__global__ __launch_bounds__(RT) void rv_dots_finalize(const double* part, int nvec, int nblk, const double* sigma,
+                                                       int i0, double* out) {
+  __shared__ double col[KMAX + 2];
+  block_col_sums(part, nvec, nblk, col);
+  __syncthreads();
+  for (int c = threadIdx.x; c < nvec; c += RT) out[c] = (sigma ? sigma[i0 + c] : 1.0) * col[c];
+}
+
+void k_rv_dots(const double* V, size_t ld, const double* sigma, int i0, int nvec, const double* x, size_t n,
+               double* part, double* out, hipStream_t st) {
+  if (nvec <= 0) return;
+  const unsigned nc = (unsigned)((nvec + RV_NV - 1) / RV_NV);
+  int nb = (int)gs_blocks(n) / (int)nc;
+  if (nb < 1) nb = 1;
+  launch(rv_dots_kernel, dim3((unsigned)nb, nc), dim3(RT), 0, st, V, ld, i0, nvec, x, n, part);
+  launch(rv_dots_finalize, dim3(1), dim3(RT), 0, st, (const double*)part, nvec, nb, sigma, i0, out);
+}
+
+// out = ax * x + ay * y + sum_{i < nvec} coef[i] sigma[i0 + i] V_{i0 + i}; ax, ay
+// are device scalars when the pointers are given, else the constants.
+__global__ __launch_bounds__(256) void rv_combine_kernel(RvComb a, double* out, size_t n) {
+  __shared__ double cf[KMAX + 2];
+  __shared__ double sx, sy;
+  for (int i = threadIdx.x; i < a.nvec; i += blockDim.x)
+    cf[i] = a.coef[i] * (a.sigma ? a.sigma[a.i0 + i] : 1.0);
+  if (threadIdx.x == 0) {
+    sx = a.axp ? *a.axp : a.axc;
+    sy = a.ayp ? *a.ayp : a.ayc;
+  }
+  __syncthreads();
+  const double ax = sx, ay = sy;
+  const int nv = a.nvec;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
+    double r = 0.0;
+    if (a.x) r += ax * a.x[idx];
+    if (a.y) r += ay * a.y[idx];
+    const double* Vp = a.V + (size_t)a.i0 * a.ld + idx;
+    int i = 0;
+    for (; i + 4 <= nv; i += 4) {
+      const double v0 = Vp[(size_t)i * a.ld], v1 = Vp[(size_t)(i + 1) * a.ld];
+      const double v2 = Vp[(size_t)(i + 2) * a.ld], v3 = Vp[(size_t)(i + 3) * a.ld];
+      r += cf[i] * v0 + cf[i + 1] * v1 + cf[i + 2] * v2 + cf[i + 3] * v3;
+    }
+    for (; i < nv; ++i) r += cf[i] * Vp[(size_t)i * a.ld];
+    out[idx] = r;
+  }
+}
+
+void k_rv_combine(const RvComb& a, double* out, size_t n, hipStream_t st) {
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  launch(rv_combine_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a, out, n);
+}
+
+// Vb_i (=|+=) a[i] r + b[i] w for i < nvec (r or w may be null).
+__global__ __launch_bounds__(256) void rv_rank_kernel(double* Vb, size_t ld, int nvec, const double* r,
+                                                      const double* w, const double* ca, const double* cb, int set,
+                                                      size_t n) {
+  __shared__ double sa[KMAX + 2], sb[KMAX + 2];
+  for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
+    sa[i] = ca ? ca[i] : 0.0;
+    sb[i] = cb ? cb[i] : 0.0;
+  }
+  __syncthreads();
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
+    const double rr = r ? r[idx] : 0.0, ww = w ? w[idx] : 0.0;
+    for (int i = 0; i < nvec; ++i) {
+      double* p = Vb + (size_t)i * ld + idx;
+      const double add = sa[i] * rr + sb[i] * ww;
+      *p = set ? add : *p + add;
+    }
+  }
+}
+
+void k_rv_rank(double* Vb, size_t ld, int nvec, const double* r, const double* w, const double* a, const double* b,
+               bool set, size_t n, hipStream_t st) {
+  if (nvec <= 0) return;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  launch(rv_rank_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Vb, ld, nvec, r, w, a, b, set ? 1 : 0, n);
+}
+
+// ---- one-block algebra of the reverse sweep
+// a[i] = fac dt y_i (i < M): initial adjoints of the basis, v_i_bar = a_i x_bar.
+__global__ void rv_init_kernel(const KState* ks, RState* rs, double fac, const double* dtp) {
+  const double f = fac * *dtp;
+  const int M = ks->m_eff;
+  for (int i = threadIdx.x; i < KMAX + 2; i += blockDim.x) rs->a[i] = i < M ? f * ks->y[i] : 0.0;
+}
+
+// y_bar = fac dt V^T x_bar (dots given), then the adjoint of
+// y = beta [exp(A^)]_{0:M, M}, A^ = [[dt H_M, e_1], [0, 0]]:
+//   beta_bar = y_bar . y / beta,  z_bar = beta y_bar,
+//   H_bar = dt [L(A^T, Z)]_{0:M, 0:M},  Z = [z_bar; 0] e_M^T,
+// with the Frechet derivative L(X, E) = upper-right block of exp([[X, E], [0, X]]).
+__global__ __launch_bounds__(PHI_T) void rv_phi_adjoint_kernel(const KState* ks, RState* rs, const double* dots,
+                                                               double fac, const double* dtp, double* mem) {
+  const int M = ks->m_eff;
+  const int tid = threadIdx.x;
+  const double dt = *dtp;
+  const double beta = ks->beta;
+  __shared__ double yb[KMAX + 2];
+  for (int i = tid; i < KMAX + 2; i += PHI_T) yb[i] = i < M ? fac * dt * dots[i] : 0.0;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int i = 0; i < M; ++i) t += yb[i] * ks->y[i];
+    rs->betabar = beta > 0.0 ? t / beta : 0.0;
+  }
+  for (int t = tid; t < KLD * KMAX; t += PHI_T) rs->Hbar[t] = 0.0;
+  if (M == 0) return;
+  const int n1 = M + 1, n = 2 * n1, nn = n * n;
+  double* X = mem;
+  for (int t = tid; t < nn; t += PHI_T) {
+    const int i = t % n, jj = t / n;    // row i, column jj
+    double v = 0.0;
+    const bool top = i < n1, left = jj < n1;
+    if (top == left || (top && !left)) {
+      if (top && !left) {                 // Z block: column M of the upper-right block
+        if (jj - n1 == M && i < M) v = beta * yb[i];
+      } else {                            // A^T blocks on the diagonal
+        const int r = top ? i : i - n1, cc = top ? jj : jj - n1;
+        // A^T[r][cc] = A^[cc][r]
+        if (cc < M && r < M) {
+          if (cc <= r + 1) v = dt * ks->H[(size_t)r * KLD + cc];
+        } else if (r == M && cc == 0) {
+          v = 1.0;
+        }
+      }
+    }
+    X[t] = v;
+  }
+  __syncthreads();
+  const double* P = expm_core(mem, n);
+  for (int t = tid; t < M * M; t += PHI_T) {
+    const int i = t % M, jj = t / M;
+    if (i <= jj + 1) rs->Hbar[(size_t)jj * KLD + i] = dt * P[(size_t)(n1 + jj) * n + i];
+  }
+}
+
+// r_bar coefficients for iteration j < M - 1 from t = v_{j+1}_bar . v_{j+1}:
+//   r_bar = v_{j+1}_bar / h + (H_bar_{j+1,j} - t / h) v_{j+1},  h = h_{j+1,j}.
+__global__ void rv_coef_r_kernel(const KState* ks, RState* rs, int j, const double* tdot) {
+  const double h = ks->H[(size_t)j * KLD + j + 1];
+  rs->alpha = 1.0 / h;
+  rs->gamma = rs->Hbar[(size_t)j * KLD + j + 1] - *tdot / h;
+}
+
+// Iteration j: with c_i = v_i . r_bar (or 0), h_bar_i = H_bar_{i,j} - c_i;
+//   b[i] = h_bar_i, a[i] = -h_{i,j} (i <= j); c[i] = h_{i,j} (i <= j + 1).
+__global__ void rv_coef_w_kernel(const KState* ks, RState* rs, int j, const double* cdots) {
+  for (int i = threadIdx.x; i < KMAX + 2; i += blockDim.x) {
+    const bool in = i <= j;
+    const double hij = (i <= j + 1 && i < KLD) ? ks->H[(size_t)j * KLD + i] : 0.0;
+    rs->b[i] = in ? rs->Hbar[(size_t)j * KLD + i] - (cdots ? cdots[i] : 0.0) : 0.0;
+    rs->a[i] = in ? -hij : 0.0;
+    rs->c[i] = (i <= j + 1) ? hij : 0.0;
+  }
+}
+
+// b_bar = v_0_bar / beta + (beta_bar - t / beta) v_0, t = v_0_bar . v_0.
+__global__ void rv_coef_b_kernel(const KState* ks, RState* rs, const double* tdot) {
+  const double beta = ks->beta;
+  rs->alpha = 1.0 / beta;
+  rs->gamma = rs->betabar - *tdot / beta;
+}
+
+void k_rv_init(const KState* ks, RState* rs, double fac, const double* dtp, hipStream_t st) {
+  launch(rv_init_kernel, dim3(1), dim3(64), 0, st, ks, rs, fac, dtp);
+}
+void k_rv_phi_adjoint(const KState* ks, RState* rs, const double* dots, double fac, const double* dtp, double* mem,
+                      hipStream_t st) {
+  launch(rv_phi_adjoint_kernel, dim3(1), dim3(PHI_T), 0, st, ks, rs, dots, fac, dtp, mem);
+}
+void k_rv_coef_r(const KState* ks, RState* rs, int j, const double* tdot, hipStream_t st) {
+  launch(rv_coef_r_kernel, dim3(1), dim3(1), 0, st, ks, rs, j, tdot);
+}
+void k_rv_coef_w(const KState* ks, RState* rs, int j, const double* cdots, hipStream_t st) {
+  launch(rv_coef_w_kernel, dim3(1), dim3(64), 0, st, ks, rs, j, cdots);
+}
+void k_rv_coef_b(const KState* ks, RState* rs, const double* tdot, hipStream_t st) {
+  launch(rv_coef_b_kernel, dim3(1), dim3(1), 0, st, ks, rs, tdot);
+}
+
+// Dense test operator: out = A^T v (row-major A).
+__global__ void gemv_t_kernel(const double* A, const double* v, double* out, int n) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += A[(size_t)i * n + j] * v[i];
+    out[j] = s;
+  }
+}
+void k_gemv_t(const double* A, const double* v, double* out, int n, hipStream_t st) {
+  launch(gemv_t_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, v, out, n);
+}
+
 template void k_start<double>(const double*, double*, size_t, KState*, double*, hipStream_t);
 template void k_start<float>(const double*, float*, size_t, KState*, double*, hipStream_t);
 template void k_gs_reduce<double>(const double*, size_t, int, size_t, KState*, double*, bool, hipStream_t);

@@ -44,6 +44,16 @@ struct KState {
   unsigned counter[8];
 };
 
+// State of the reverse sweep through one Arnoldi run.
+struct RState {
+  double Hbar[KLD * KMAX];   // adjoint of H (same layout), entries i <= j + 1 of column j
+  double a[KMAX + 2], b[KMAX + 2], c[KMAX + 2];   // per-iteration coefficients
+  double dots[KMAX + 2];     // dot-product results
+  double t[4];               // scalar dot results
+  double alpha, gamma;       // two-term combination coefficients
+  double betabar;            // adjoint of beta = |b|
+};
+
 // --- host-side launchers (krylov_kernels.hip) -------------------------------
 size_t gs_blocks(size_t n);
 void k_init_state(KState* ks, double eta, hipStream_t st);
@@ -62,6 +72,34 @@ void k_hess_phi(KState* ks, const double* dt, int k, int m, double* scratch, hip
 template <typename TV, typename TX>
 void k_combine(const TV* V, size_t ld, const KState* ks, const double* base, double* out,
                TX* xout, double fac, const double* dtp, size_t n, hipStream_t st);
+
+// reverse sweep (FP64 basis V, v_i = sigma_i V_i)
+struct RvComb {
+  const double* x;
+  const double* axp;
+  double axc;
+  const double* y;
+  const double* ayp;
+  double ayc;
+  const double* V;
+  size_t ld;
+  const double* sigma;
+  const double* coef;
+  int i0, nvec;
+};
+// out[c] = (sigma_{i0+c} V_{i0+c}) . x (sigma may be null: 1), c < nvec
+void k_rv_dots(const double* V, size_t ld, const double* sigma, int i0, int nvec, const double* x, size_t n,
+               double* part, double* out, hipStream_t st);
+void k_rv_combine(const RvComb& a, double* out, size_t n, hipStream_t st);
+void k_rv_rank(double* Vb, size_t ld, int nvec, const double* r, const double* w, const double* a, const double* b,
+               bool set, size_t n, hipStream_t st);
+void k_rv_init(const KState* ks, RState* rs, double fac, const double* dtp, hipStream_t st);
+void k_rv_phi_adjoint(const KState* ks, RState* rs, const double* dots, double fac, const double* dtp, double* mem,
+                      hipStream_t st);
+void k_rv_coef_r(const KState* ks, RState* rs, int j, const double* tdot, hipStream_t st);
+void k_rv_coef_w(const KState* ks, RState* rs, int j, const double* cdots, hipStream_t st);
+void k_rv_coef_b(const KState* ks, RState* rs, const double* tdot, hipStream_t st);
+void k_gemv_t(const double* A, const double* v, double* out, int n, hipStream_t st);
 
 // utilities
 template <typename T> void k_fill(T* p, T v, size_t n, const int* skip, hipStream_t st);

@@ -5,6 +5,7 @@
 // residual and exact Jacobian); Sec. 5 eq. (x3d) (time step).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -59,7 +60,7 @@ struct pcexp_ctx {
   double *Ajac = nullptr, *Ares = nullptr;
   float* Ajac32 = nullptr;
   // context-owned scratch for single-shot calls
-  double* io[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* io[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   float* io32[2] = {nullptr, nullptr};
   double* part = nullptr;
   size_t part_len = 0;
@@ -286,6 +287,130 @@ void arnoldi_run(pcexp_ctx* c, int jvp, int prec, const double* u_lin, const flo
   { Prof pr(c, st, PC_PHI, 0.0); k_hess_phi(ks, dtp, k, m, phi, st); }
 }
 
+// ---- reverse mode ----------------------------------------------------------
+// J^T w on internal vectors (with res_jac on a dense context: the residual
+// matrix); if out_d is given also out_d = d/deps [J(u + eps v)^T w] (zero for
+// the constant dense operators).
+bool vjp_int(pcexp_ctx* c, const double* u, const double* v, const double* w, double* out, double* out_d,
+             bool res_jac, hipStream_t st) {
+  if (c->dense) {
+    k_gemv_t(res_jac ? c->Ares : c->Ajac, w, out, (int)c->Kint, st);
+    if (out_d) k_fill<double>(out_d, 0.0, c->Kint, nullptr, st);
+    return true;
+  }
+  return c->dim == 2 ? dg_vjp2(c->p, c->flux, params_d(c), u, v, w, out, out_d, st)
+                     : dg_vjp3(c->p, c->flux, params_d(c), u, v, w, out, out_d, st);
+}
+
+struct RevBufs {
+  double *r, *wb, *wj, *t1, *t2;   // K-vectors
+  double* Vb;                       // m adjoint basis vectors, stride Kld
+  RState* rs;
+  double* part;
+  double* mem;                      // expm scratch, 7 (2 KMAX + 2)^2 doubles
+};
+
+// Reverse sweep through one Arnoldi run of J = J(u_lin) with b, producing
+// x = fac dt V_M y, y = beta phi_1(dt H_M) e_1 (the forward left its basis in
+// V, its state in ks; M = m_eff).  Given x_bar: b_bar = (dx/db)^T x_bar, and
+// ubar += the part of (dx/du_lin)^T x_bar that comes through J(u_lin).
+// Differentiates the Arnoldi relations themselves (one classical Gram-Schmidt
+// pass with exact orthogonality, which the re-orthogonalised forward
+// realises to rounding): for j = M-1 .. 0,
+//   r_bar = (v_{j+1}_bar - (v_{j+1}_bar . v_{j+1}) v_{j+1}) / h_{j+1,j} + H_bar_{j+1,j} v_{j+1}  (j < M-1)
+//   h_bar_{ij} = H_bar_{ij} - v_i . r_bar,  w_bar = r_bar + sum_i h_bar_{ij} v_i
+//   v_i_bar += -h_{ij} r_bar + h_bar_{ij} J v_j   (i <= j)
+//   v_j_bar += J^T w_bar,  ubar += (d_u [J(u) v_j])^T w_bar
+// and finally b = beta v_0: b_bar = (v_0_bar - (v_0_bar . v_0) v_0) / beta + beta_bar v_0.
+void arnoldi_reverse(pcexp_ctx* c, const double* u_lin, const KState* ks, int M, const double* V, double fac,
+                     const double* dtp, const double* xbar, double* bbar, double* ubar, const RevBufs& B,
+                     hipStream_t st) {
+  const size_t n = c->Kint, ld = c->Kld;
+  const double* sig = ks->sigma;
+  RState* rs = B.rs;
+  if (M == 0) {
+    k_fill<double>(bbar, 0.0, n, nullptr, st);
+    return;
+  }
+  k_rv_init(ks, rs, fac, dtp, st);
+  k_rv_rank(B.Vb, ld, M, xbar, nullptr, rs->a, nullptr, true, n, st);
+  k_rv_dots(V, ld, sig, 0, M, xbar, n, B.part, rs->dots, st);
+  k_rv_phi_adjoint(ks, rs, rs->dots, fac, dtp, B.mem, st);
+  for (int j = M - 1; j >= 0; --j) {
+    const double* rptr = nullptr;
+    if (j < M - 1) {
+      double* vb1 = B.Vb + (size_t)(j + 1) * ld;
+      k_rv_dots(V, ld, sig, j + 1, 1, vb1, n, B.part, &rs->t[0], st);
+      k_rv_coef_r(ks, rs, j, &rs->t[0], st);
+      RvComb a{};
+      a.x = vb1; a.axp = &rs->alpha; a.V = V; a.ld = ld; a.sigma = sig; a.coef = &rs->gamma; a.i0 = j + 1; a.nvec = 1;
+      k_rv_combine(a, B.r, n, st);
+      k_rv_dots(V, ld, sig, 0, j + 1, B.r, n, B.part, rs->dots, st);
+      k_rv_coef_w(ks, rs, j, rs->dots, st);
+      rptr = B.r;
+    } else {
+      k_rv_coef_w(ks, rs, j, nullptr, st);
+    }
+    {  // w_bar = r_bar + sum_{i <= j} h_bar_i v_i
+      RvComb a{};
+      a.x = rptr; a.axc = 1.0; a.V = V; a.ld = ld; a.sigma = sig; a.coef = rs->b; a.i0 = 0; a.nvec = j + 1;
+      k_rv_combine(a, B.wb, n, st);
+    }
+    if (j < M - 1) {  // J v_j from the Arnoldi relation
+      RvComb a{};
+      a.V = V; a.ld = ld; a.sigma = sig; a.coef = rs->c; a.i0 = 0; a.nvec = j + 2;
+      k_rv_combine(a, B.wj, n, st);
+    } else {
+      jvp_int(c, PCEXP_JVP_TANGENT, PCEXP_PREC_F64, u_lin, nullptr, V + (size_t)j * ld, B.wj, &sig[j], nullptr,
+              nullptr, nullptr, st);
+    }
+    k_rv_rank(B.Vb, ld, j + 1, rptr, B.wj, rs->a, rs->b, false, n, st);
+    vjp_int(c, u_lin, V + (size_t)j * ld, B.wb, B.t1, B.t2, false, st);
+    double* vbj = B.Vb + (size_t)j * ld;
+    {
+      RvComb a{};
+      a.x = vbj; a.axc = 1.0; a.y = B.t1; a.ayc = 1.0;
+      k_rv_combine(a, vbj, n, st);
+    }
+    {
+      RvComb a{};
+      a.x = ubar; a.axc = 1.0; a.y = B.t2; a.ayp = &sig[j];
+      k_rv_combine(a, ubar, n, st);
+    }
+  }
+  k_rv_dots(V, ld, sig, 0, 1, B.Vb, n, B.part, &rs->t[0], st);
+  k_rv_coef_b(ks, rs, &rs->t[0], st);
+  RvComb a{};
+  a.x = B.Vb; a.axp = &rs->alpha; a.V = V; a.ld = ld; a.sigma = sig; a.coef = &rs->gamma; a.i0 = 0; a.nvec = 1;
+  k_rv_combine(a, bbar, n, st);
+}
+
+struct RevLayout {
+  size_t ks1, ks2, rs, part, mem, scal, un, Rn, us, Rs, x1, ub, acc, xb, db, r, wb, wj, t1, t2, V1, V2, Vb, total;
+};
+
+RevLayout rev_layout(const pcexp_ctx* c, int m) {
+  RevLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+  const size_t vb = c->Kint * sizeof(double), sb = c->Kld * sizeof(double);
+  L.ks1 = take(sizeof(KState));
+  L.ks2 = take(sizeof(KState));
+  L.rs = take(sizeof(RState));
+  L.part = take((size_t)3 * 512 * (KMAX + 2) * sizeof(double));
+  const size_t nphi = (size_t)std::max(m + 1, 2 * (m + 1));
+  L.mem = take(7 * nphi * nphi * sizeof(double));
+  L.scal = take(64 * sizeof(double));
+  L.un = take(vb); L.Rn = take(vb); L.us = take(vb); L.Rs = take(vb); L.x1 = take(vb);
+  L.ub = take(vb); L.acc = take(vb); L.xb = take(vb); L.db = take(vb);
+  L.r = take(vb); L.wb = take(vb); L.wj = take(vb); L.t1 = take(vb); L.t2 = take(vb);
+  L.V1 = take((size_t)(m + 1) * sb);
+  L.V2 = take((size_t)(m + 1) * sb);
+  L.Vb = take((size_t)m * sb);
+  L.total = off;
+  return L;
+}
+
 void fill_info(pcexp_krylov_info* out, const KState& h) {
   out->beta = h.beta;
   out->h_last = h.hlast;
@@ -321,7 +446,7 @@ pcexp_status report_flags(pcexp_ctx* c, uint32_t* out_flags) {
 }
 
 pcexp_status alloc_common(pcexp_ctx* c, hipStream_t st) {
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 5; ++i)
     if (!dalloc(c, &c->io[i], c->Kint)) return fail(c, PCEXP_E_HIP, "hipMalloc failed");
   for (int i = 0; i < 2; ++i)
     if (!dalloc(c, &c->io32[i], c->Kint)) return fail(c, PCEXP_E_HIP, "hipMalloc failed");
@@ -542,11 +667,9 @@ pcexp_status pcexp_jvp(pcexp_ctx* c, const double* u, const double* v, double* J
 pcexp_status pcexp_vjp(pcexp_ctx* c, const double* u, const double* w, double* JTw, void* stream) {
   if (!c || !u || !w || !JTw || w == JTw) return c ? fail(c, PCEXP_E_ARG, "bad pointers") : PCEXP_E_ARG;
   hipStream_t st = (hipStream_t)stream;
-  if (c->dense) return fail(c, PCEXP_E_UNSUPPORTED, "vjp not provided for dense contexts");
   to_int(c, u, c->io[0], st);
   to_int(c, w, c->io[1], st);
-  bool ok = c->dim == 2 ? dg_vjp2(c->p, c->flux, params_d(c), c->io[0], c->io[1], c->io[2], st)
-                        : dg_vjp3(c->p, c->flux, params_d(c), c->io[0], c->io[1], c->io[2], st);
+  bool ok = vjp_int(c, c->io[0], nullptr, c->io[1], c->io[2], nullptr, false, st);
   to_abi(c, c->io[2], JTw, st);
   return ok ? hip_check(c, "vjp") : fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
 }
@@ -723,6 +846,128 @@ pcexp_status pcexp_step(pcexp_ctx* c, double* u, double dt, double cfl, int32_t 
     return report_flags(c, &info->flags);
   }
   return PCEXP_OK;
+}
+
+pcexp_status pcexp_pressure_functional(pcexp_ctx* c, const double* u, double p_ref, double* value_host,
+                                       double* grad, void* stream) {
+  if (!c || !u || !value_host) return c ? fail(c, PCEXP_E_ARG, "bad pointers") : PCEXP_E_ARG;
+  if (c->dense) return fail(c, PCEXP_E_UNSUPPORTED, "dense context has no mesh");
+  if (grad == u) return fail(c, PCEXP_E_ARG, "grad must not alias u");
+  hipStream_t st = (hipStream_t)stream;
+  to_int(c, u, c->io[0], st);
+  ek_pressure_functional(elem_args(c), c->io[0], p_ref, &c->scal[24], grad ? c->io[1] : nullptr, c->part, st);
+  if (grad) to_abi(c, c->io[1], grad, st);
+  if (hipMemcpyAsync(value_host, &c->scal[24], sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(c, PCEXP_E_HIP, "pressure functional sync failed");
+  return hip_check(c, "pressure_functional");
+}
+
+size_t pcexp_step_vjp_workspace_bytes(const pcexp_ctx* c, int32_t m) {
+  if (!c || m < 1 || m > KMAX) return 0;
+  return rev_layout(c, m).total;
+}
+
+pcexp_status pcexp_vjp2(pcexp_ctx* c, const double* u, const double* v, const double* w, double* JTw,
+                        double* dJTw, void* stream) {
+  if (!c || !u || !v || !w || !JTw || !dJTw || w == JTw || w == dJTw || JTw == dJTw)
+    return c ? fail(c, PCEXP_E_ARG, "bad pointers") : PCEXP_E_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  to_int(c, u, c->io[0], st);
+  to_int(c, v, c->io[1], st);
+  to_int(c, w, c->io[2], st);
+  if (!vjp_int(c, c->io[0], c->io[1], c->io[2], c->io[3], c->io[4], false, st))
+    return fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
+  to_abi(c, c->io[3], JTw, st);
+  to_abi(c, c->io[4], dJTw, st);
+  return hip_check(c, "vjp2");
+}
+
+pcexp_status pcexp_step_vjp(pcexp_ctx* c, const double* u_n, double dt, int32_t m, int32_t scheme,
+                            const double* ubar_np1, double* ubar_n, void* ws, size_t ws_bytes, void* stream) {
+  if (!c) return PCEXP_E_ARG;
+  if (!u_n || !ubar_np1 || !ubar_n || ubar_np1 == ubar_n) return fail(c, PCEXP_E_ARG, "bad pointers");
+  if (m < 1 || m > KMAX) return fail(c, PCEXP_E_ARG, "m must be in [1, 64]");
+  if (scheme != PCEXP_SCHEME_PCEXP && scheme != PCEXP_SCHEME_EXP1) return fail(c, PCEXP_E_ARG, "bad scheme");
+  if (!std::isfinite(dt) || !(dt > 0.0)) return fail(c, PCEXP_E_ARG, "step_vjp needs a fixed dt > 0");
+  const RevLayout L = rev_layout(c, m);
+  if (!ws || ws_bytes < L.total) return fail(c, PCEXP_E_WORKSPACE, "workspace missing or too small");
+  if (((uintptr_t)ws) % ALIGN != 0) return fail(c, PCEXP_E_WORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)ws;
+  auto vec = [&](size_t off) { return (double*)(w + off); };
+  KState* ks1 = (KState*)(w + L.ks1);
+  KState* ks2 = (KState*)(w + L.ks2);
+  double* part = vec(L.part);
+  double* mem = vec(L.mem);
+  double* scal = vec(L.scal);
+  double *un = vec(L.un), *Rn = vec(L.Rn), *us = vec(L.us), *Rs = vec(L.Rs), *x1 = vec(L.x1);
+  double *ub = vec(L.ub), *acc = vec(L.acc), *xb = vec(L.xb), *db = vec(L.db);
+  double *V1 = vec(L.V1), *V2 = vec(L.V2);
+  RevBufs B{vec(L.r), vec(L.wb), vec(L.wj), vec(L.t1), vec(L.t2), vec(L.Vb), (RState*)(w + L.rs), part, mem};
+  const size_t n = c->Kint;
+  double* dtp = &scal[0];
+  const bool pc = scheme == PCEXP_SCHEME_PCEXP;
+
+  // ---- forward step, keeping both Krylov bases
+  to_int(c, u_n, un, st);
+  k_set_scalar(dtp, dt, st);
+  if (!residual_int(c, un, Rn, st)) return fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
+  arnoldi_run<double>(c, PCEXP_JVP_TANGENT, PCEXP_PREC_F64, un, nullptr, Rn, Rn, dtp, 1, m, ks1, part, mem, V1, st);
+  k_combine<double, double>(V1, c->Kld, ks1, un, us, x1, 1.0, dtp, n, st);
+  if (pc) {
+    if (!residual_int(c, us, Rs, st)) return fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
+    jvp_int(c, PCEXP_JVP_TANGENT, PCEXP_PREC_F64, un, nullptr, x1, B.wj, nullptr, nullptr, nullptr, nullptr, st);
+    k_glue_d<double>(Rs, Rn, B.wj, Rs, n, st);   // Rs <- d = R(u*) - R_n - J_n x1
+    arnoldi_run<double>(c, PCEXP_JVP_TANGENT, PCEXP_PREC_F64, un, nullptr, Rs, Rn, dtp, 1, m, ks2, part, mem, V2,
+                        st);
+  }
+  int M1 = 0, M2 = 0;
+  if (hipMemcpyAsync(&M1, &ks1->m_eff, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      (pc && hipMemcpyAsync(&M2, &ks2->m_eff, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(c, PCEXP_E_HIP, "step_vjp sync failed");
+
+  // ---- reverse sweep; acc accumulates u_n_bar
+  to_int(c, ubar_np1, ub, st);
+  k_fill<double>(acc, 0.0, n, nullptr, st);
+  if (pc) {
+    // u_{n+1} = u* + x2 (x2 = 1/2 dt V2 y2): x2_bar = u*_bar = ub
+    arnoldi_reverse(c, un, ks2, M2, V2, 0.5, dtp, ub, db, acc, B, st);   // db = d_bar
+    // d = R(u*) - R_n - J(u_n) x1
+    vjp_int(c, us, nullptr, db, B.t1, nullptr, true, st);                  // J(u*)^T d_bar
+    RvComb a{};
+    a.x = ub; a.axc = 1.0; a.y = B.t1; a.ayc = 1.0;
+    k_rv_combine(a, xb, n, st);                                            // xb = u*_bar
+    vjp_int(c, un, x1, db, B.t1, B.t2, false, st);                         // J^T d_bar, (d_u[J x1])^T d_bar
+    a = RvComb{};
+    a.x = xb; a.axc = 1.0; a.y = B.t1; a.ayc = -1.0;
+    k_rv_combine(a, B.r, n, st);                                           // x1_bar = u*_bar - J^T d_bar
+    a = RvComb{};
+    a.x = acc; a.axc = 1.0; a.y = B.t2; a.ayc = -1.0;
+    k_rv_combine(a, acc, n, st);
+    a = RvComb{};
+    a.x = acc; a.axc = 1.0; a.y = xb; a.ayc = 1.0;
+    k_rv_combine(a, acc, n, st);                                           // u* = u_n + x1
+    a = RvComb{};
+    a.x = B.r; a.axc = 1.0;
+    k_rv_combine(a, xb, n, st);                                            // xb = x1_bar
+    arnoldi_reverse(c, un, ks1, M1, V1, 1.0, dtp, xb, Rs, acc, B, st);     // Rs = b1_bar
+    a = RvComb{};
+    a.x = Rs; a.axc = 1.0; a.y = db; a.ayc = -1.0;
+    k_rv_combine(a, Rs, n, st);                                            // R_n_bar = b1_bar - d_bar
+  } else {
+    arnoldi_reverse(c, un, ks1, M1, V1, 1.0, dtp, ub, Rs, acc, B, st);     // Rs = R_n_bar
+    RvComb a{};
+    a.x = acc; a.axc = 1.0; a.y = ub; a.ayc = 1.0;
+    k_rv_combine(a, acc, n, st);                                           // u_{n+1} = u_n + x1
+  }
+  vjp_int(c, un, nullptr, Rs, B.t1, nullptr, true, st);                    // R_n = R(u_n)
+  RvComb a{};
+  a.x = acc; a.axc = 1.0; a.y = B.t1; a.ayc = 1.0;
+  k_rv_combine(a, acc, n, st);
+  to_abi(c, acc, ubar_n, st);
+  return hip_check(c, "step_vjp");
 }
 
 pcexp_status pcexp_profile(pcexp_ctx* c, int32_t op, double* out) {
