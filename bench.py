@@ -74,10 +74,12 @@ def parse():
 
 
 def cpu_baseline(mesh, cfg, u0_np, K):
-    """Time the FP64 oracle on a bounded sample of the same workload: one
-    residual, three complex-step JVPs and the MGS work of one Arnoldi
-    iteration at full size; a PCEXP step costs 2 residuals + (2m+1) JVPs +
-    two MGS Arnoldi runs, from which seconds per step are extrapolated."""
+    """Time the FP64 oracle on a bounded sample of the same workload (about
+    10 s on 16 cores): two residuals, 24 complex-step JVPs and the 30
+    modified Gram-Schmidt projections of one late Arnoldi iteration, all at
+    full size.  A PCEXP step costs 2 residuals + (2m+1) JVPs + two MGS
+    Arnoldi runs (sum_{j<m} (j+1) projections each), from which seconds per
+    step are extrapolated."""
     import numpy as np
     from oracle.dg import DG
     from oracle.derivatives import jvp_cs
@@ -87,28 +89,32 @@ def cpu_baseline(mesh, cfg, u0_np, K):
     g = DG(mesh, cfg["p"], cfg["flux"])
     u = u0_np
     t0 = time.perf_counter()
-    R = g.residual(u)
-    t_res = time.perf_counter() - t0
+    for _ in range(2):
+        R = g.residual(u)
+    t_res = (time.perf_counter() - t0) / 2
     v = W.random_unit_vector(u.shape, 1)
+    njvp = 24
     t0 = time.perf_counter()
-    for _ in range(3):
+    for _ in range(njvp):
         jvp_cs(g, u, v)
-    t_jvp = (time.perf_counter() - t0) / 3
+    t_jvp = (time.perf_counter() - t0) / njvp
     m = cfg["m"]
-    Vb = np.random.default_rng(0).standard_normal((K, 8))
+    nproj = m
+    Vb = np.random.default_rng(0).standard_normal((K, nproj))
     w = R.ravel().copy()
     t0 = time.perf_counter()
-    for i in range(8):          # MGS projections against 8 basis vectors
+    for i in range(nproj):
         h = Vb[:, i] @ w
         w = w - h * Vb[:, i]
-    t_gs8 = time.perf_counter() - t0
-    # MGS of one Arnoldi run touches sum_{j<m} (j+1) vectors
-    t_gs = t_gs8 / 8 * (m * (m + 1) / 2)
+    t_proj = (time.perf_counter() - t0) / nproj
+    t_gs = t_proj * (m * (m + 1) / 2)     # MGS of one Arnoldi run
     s_step = 2 * t_res + (2 * m + 1) * t_jvp + 2 * t_gs
+    sample_s = 2 * t_res + njvp * t_jvp + nproj * t_proj
     return dict(value=K / s_step, unit="DOF-updates/s", cores=threads, kind="oracle",
-                sample=(f"config-2 size, FP64 NumPy oracle: 1 residual ({t_res:.2f} s), 3 complex-step JVPs "
-                        f"({t_jvp:.2f} s each), 8 MGS projections; per step = 2 R + {2 * m + 1} JVP + "
-                        f"2 Arnoldi MGS = {s_step:.1f} s"),
+                sample=(f"config-2 size, FP64 NumPy oracle, {sample_s:.1f} s measured: 2 residuals "
+                        f"({t_res:.2f} s each), {njvp} complex-step JVPs ({t_jvp:.2f} s each), {nproj} MGS "
+                        f"projections ({1e3 * t_proj:.1f} ms each); per step = 2 R + {2 * m + 1} JVP + "
+                        f"2 Arnoldi MGS = {s_step:.1f} s extrapolated"),
                 seconds_per_step=s_step)
 
 
@@ -184,6 +190,22 @@ def main():
                                   rel_diff_vs_t64=float((torch.linalg.norm(u - u_t64) /
                                                          torch.linalg.norm(u_t64)).item()))
 
+    # reverse mode (discrete adjoint of one step, fixed dt): time per step_vjp vs forward step
+    reverse = None
+    if not args.no_variants:
+        ub = torch.as_tensor(W.random_unit_vector(tuple(u0.shape), 501), device=dev)
+        ctx.step_vjp(u0, ub, dt, m=m)
+        torch.cuda.synchronize()
+        nrev = 3
+        t0 = time.perf_counter()
+        for _ in range(nrev):
+            ctx.step_vjp(u0, ub, dt, m=m)
+        torch.cuda.synchronize()
+        rev_s = (time.perf_counter() - t0) / nrev
+        reverse = dict(ms_per_step_vjp=1e3 * rev_s, ratio_to_forward=rev_s / (wall / steps),
+                       workspace_bytes=int(ctx.lib.pcexp_step_vjp_workspace_bytes(ctx.ctx, m)),
+                       note="recomputes the forward step with both Krylov bases, then the reverse sweep")
+
     # live per-kernel timing (HIP events on the step's stream) over a second timed region
     _, _, _, prof = run("f64", "tangent", steps, profile=True)
     kern = {k: dict(ms_total=v[0], launches=v[1], avg_us=(1e3 * v[0] / v[1]) if v[1] else 0.0,
@@ -219,6 +241,7 @@ def main():
         "jvp_gbs": round(jvp_gbs, 1),
         "roofline": roofline,
         "variants": variants,
+        "reverse": reverse,
         "kernels": kern,
         "gpu_event_seconds": gpu_s,
     }
