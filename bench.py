@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--workload", default="vortex2d", choices=["vortex2d", "channel", "vortex3d"],
+                    help="vortex2d: the headline PCEXP step benchmark; channel: steady bump channel to "
+                         "||R(rho)|| <= 1e-10 with the CFL ramp; vortex3d: 3D P2 vortex, mixed precision")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counter calibration)")
     return ap.parse_args()
@@ -118,6 +121,102 @@ def cpu_baseline(mesh, cfg, u0_np, K):
                 seconds_per_step=s_step)
 
 
+def bench_channel(args, dev):
+    """Steady subsonic channel over a Gaussian bump (384x128x2 jittered
+    triangles, P2 Roe, Mach 0.5): pseudo-time PCEXP with the CFL ramp of
+    eq. (cfl) (CFL_max 1000, m = 30) from the uniform free stream, in FP64
+    and in mixed precision, for at most `--steps` pseudo-time steps or until
+    ||R(rho)|| <= 1e-10.  With a fixed Krylov dimension this P2 case does not
+    converge at the ramp's CFL (it does on small P1 channels); the line then
+    reports the throughput and the residual reached."""
+    import torch
+    import workloads as W
+    from paper_1801_06300_amd import PCEXP, PcexpError
+
+    cfg = W.get_config(3)
+    mesh = W.build_mesh(cfg)
+    prim = W.freestream_prim(2, mach=cfg["mach"], angle_deg=cfg["angle_deg"])
+    ctx = PCEXP(mesh, cfg["p"], cfg["flux"], farfield_prim=prim, device=dev)
+    xq = ctx.quad_points().cpu().numpy()
+    Uq = W.uniform_state(xq.reshape(-1, 2), prim).reshape(ctx.nE, ctx.nq, ctx.nv)
+    u0 = ctx.project(torch.as_tensor(Uq, device=dev)).contiguous()
+    res = {}
+    for prec in ("f64", "mixed"):
+        u = u0.clone()
+        ctx.steady(u.clone(), cfl_max=cfg["cfl_max"], tol=1.0, max_iter=1, m=cfg["m"], prec=prec)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            info = ctx.steady(u, cfl_max=cfg["cfl_max"], tol=cfg["target_residual"], max_iter=args.steps,
+                              check_every=10, m=cfg["m"], prec=prec)
+        except PcexpError as e:
+            res[prec] = dict(error=str(e))
+            continue
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[prec] = dict(info, seconds=wall, ms_per_iteration=1e3 * wall / info["iterations"],
+                         dofs_per_s=ctx.K * info["iterations"] / wall)
+    main = res.get("mixed", {})
+    out = {
+        "metric": "PCEXP DOF-updates/s (steady channel, CFL ramp)",
+        "value": round(main.get("dofs_per_s", 0.0), 1), "unit": "DOF-updates/s", "n_gpus": 1,
+        "steps": main.get("iterations", 0), "warmup": 1,
+        "ms_per_step": round(main.get("ms_per_iteration", 0.0), 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64 (mixed)", "data": "synthetic",
+        "config": {"workload": "steady bump channel, 384x128x2 jittered triangles (98304), DG P2, Roe, "
+                               "Mach 0.5, m=30, CFL ramp to 1000, mixed precision", "K": ctx.K},
+        "runs": res,
+    }
+    print(json.dumps(out))
+
+
+def bench_vortex3d(args, dev):
+    """3D vortex column (48^3 cubes x 6 tetrahedra, P2, LF), mixed precision,
+    m = 30, CFL 10 (dt from eq. (x3d) at u_0), `steps` PCEXP steps."""
+    import torch
+    import workloads as W
+    from paper_1801_06300_amd import PCEXP
+
+    cfg = W.get_config(4)
+    mesh = W.build_mesh(cfg)
+    ctx = PCEXP(mesh, cfg["p"], cfg["flux"], device=dev)
+    xq = ctx.quad_points().cpu().numpy()
+    c = cfg["vortex_center"]
+    Uq = W.isentropic_vortex(xq.reshape(-1, 3), center=c, period=mesh.period).reshape(ctx.nE, ctx.nq, ctx.nv)
+    u0 = ctx.project(torch.as_tensor(Uq, device=dev))
+    u0 = (u0 + torch.as_tensor(W.perturbation(tuple(u0.shape), cfg["pert_seed"]), device=dev)).contiguous()
+    dt = ctx.stable_dt(u0, cfg["cfl"])
+    steps = min(args.steps, cfg["steps"])
+    u = u0.clone()
+    for _ in range(args.warmup):
+        ctx.step(u, dt=dt, m=cfg["m"], prec="mixed")
+    u = u0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(u, dt=dt, m=cfg["m"], prec="mixed")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile("start")
+    u = u0.clone()
+    for _ in range(2):
+        ctx.step(u, dt=dt, m=cfg["m"], prec="mixed")
+    prof = ctx.profile("read")
+    ctx.profile("stop")
+    kern = {k: dict(ms_total=v[0], launches=v[1], avg_us=(1e3 * v[0] / v[1]) if v[1] else 0.0,
+                    gbs=(v[2] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else 0.0) for k, v in prof.items() if v[1]}
+    out = {
+        "metric": "PCEXP DOF-updates/s (3D vortex, mixed)", "value": round(ctx.K * steps / wall, 1),
+        "unit": "DOF-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / steps, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64 (mixed)", "data": "synthetic",
+        "config": {"workload": "3D isentropic vortex column, periodic [0,10]^3, 48^3 cubes x 6 tetrahedra "
+                               "(663552), DG P2, LF, m=30, CFL 10, mixed precision", "K": ctx.K, "dt": dt},
+        "kernels": kern,
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -134,6 +233,10 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "channel":
+        return bench_channel(args, dev)
+    if args.workload == "vortex3d":
+        return bench_vortex3d(args, dev)
     cfg = W.get_config(2)
     mesh = W.build_mesh(cfg)
     ctx = PCEXP(mesh, cfg["p"], cfg["flux"], device=dev)

@@ -109,6 +109,13 @@ typedef struct {
   uint32_t flags;            /* PCEXP_FLAG_* seen since the previous report */
 } pcexp_step_info;
 
+typedef struct {
+  int32_t iterations;     /* pseudo-time steps taken */
+  int32_t converged;      /* 1 if ||R(rho)|| <= tol was reached */
+  double res_rho_norm0;   /* ||R(rho)|| of eq. (cfl) at the initial state */
+  double res_rho_norm;    /* ... at the returned state */
+} pcexp_steady_info;
+
 /* Create a context for a mesh and discretisation (Sec. 4.2-4.3): builds faces,
  * periodic pairing, geometry, quadrature and basis tables on the host and
  * uploads them.  Synchronises `stream`.  *out is NULL on failure. */
@@ -215,6 +222,17 @@ size_t pcexp_step_vjp_workspace_bytes(const pcexp_ctx* ctx, int32_t m);
 pcexp_status pcexp_step_vjp(pcexp_ctx* ctx, const double* u_n, double dt, int32_t m,
                             int32_t scheme, const double* ubar_np1, double* ubar_n, void* ws,
                             size_t ws_bytes, void* stream);
+
+/* Steady state by pseudo-time stepping (Sec. 5: PCEXP or EXP1 with the CFL
+ * ramp of eq. (cfl), CFL(n) = min{CFL_max, max[||R(rho_n)||^-3, 1 + (n-1)/(2p+1)]},
+ * ||R(rho)|| = (1/|Omega|)(sum of squared rho coefficients)^(1/2), dt from eq.
+ * (x3d) at u_n with CFL(n); the ramp and dt are computed on the device).
+ * u (device, ABI layout) is updated in place until ||R(rho)|| <= tol or
+ * max_iter steps; the norm is read back every check_every steps (one
+ * synchronisation each).  Workspace as pcexp_step.  Not for dense contexts. */
+pcexp_status pcexp_steady(pcexp_ctx* ctx, double* u, double cfl_max, double tol, int32_t max_iter,
+                          int32_t check_every, int32_t m, int32_t scheme, int32_t prec, int32_t jvp,
+                          void* ws, size_t ws_bytes, pcexp_steady_info* info, void* stream);
 
 /* Kernel-class timing with HIP events for the launches made by pcexp_step /
  * pcexp_arnoldi_phi (for roofline reports).  Each timed operation is one

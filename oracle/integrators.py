@@ -105,3 +105,18 @@ def cfl_ramp(n, rnorm, p, cfl_max):
     """Eq. (cfl): CFL(n) = min{CFL_max, max[||R(rho_n)||^-3, 1 + (n-1)/(2p+1)]}."""
     big = np.inf if rnorm == 0.0 else rnorm ** -3
     return float(min(cfl_max, max(big, 1.0 + (n - 1) / (2 * p + 1))))
+
+
+def steady_iterations(dg, op, u, niter, cfl_max, m, scheme="pcexp"):
+    """Pseudo-time stepping toward R(u) = 0 (Sec. 5): at iteration n = 1, 2, ...
+    CFL(n) from eq. (cfl) with ||R(rho_n)||, dt from eq. (x3d) at u_n with that
+    CFL, then one PCEXP (or EXP1) step.  Returns the state and the list of
+    ||R(rho_n)||."""
+    hist = []
+    for n in range(1, niter + 1):
+        R = dg.residual(u)
+        r = res_rho_norm(dg, R)
+        hist.append(r)
+        dt = stable_dt(dg, u, cfl_ramp(n, r, dg.p, cfl_max))
+        u = pcexp_step(op, u, dt, m, scheme)
+    return u, hist

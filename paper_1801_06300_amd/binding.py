@@ -54,6 +54,15 @@ class StepInfo(ctypes.Structure):
                     res_rho_norm=self.res_rho_norm, flags=int(self.flags))
 
 
+class SteadyInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("res_rho_norm0", ctypes.c_double), ("res_rho_norm", ctypes.c_double)]
+
+    def as_dict(self):
+        return dict(iterations=self.iterations, converged=bool(self.converged),
+                    res_rho_norm0=self.res_rho_norm0, res_rho_norm=self.res_rho_norm)
+
+
 _VP = ctypes.c_void_p
 _SIGS = {
     "pcexp_create": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.POINTER(DiscDesc), _VP, ctypes.POINTER(_VP)]),
@@ -79,6 +88,9 @@ _SIGS = {
                                          ctypes.c_int32, ctypes.c_int32, _VP, _VP, ctypes.c_size_t,
                                          ctypes.POINTER(KrylovInfo), _VP]),
     "pcexp_profile": (ctypes.c_int, [_VP, ctypes.c_int32, c_double_p]),
+    "pcexp_steady": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
+                                    ctypes.c_size_t, ctypes.POINTER(SteadyInfo), _VP]),
     "pcexp_step": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_int32, ctypes.c_int32, _VP, ctypes.c_size_t,
                                   ctypes.POINTER(StepInfo), _VP]),
@@ -321,6 +333,18 @@ class PCEXP:
         self._check(self.lib.pcexp_profile(self.ctx, 2, out), "profile")
         return {name: (out[3 * i], int(out[3 * i + 1]), out[3 * i + 2])
                 for i, name in enumerate(self.PROFILE_CLASSES)}
+
+    def steady(self, u, cfl_max=1000.0, tol=1e-10, max_iter=500, check_every=10, m=30, scheme="pcexp",
+               prec="f64", jvp="tangent"):
+        """Pseudo-time iteration with the CFL ramp of eq. (cfl), u updated in place; returns the info dict."""
+        if not (u.is_cuda and u.dtype == self.torch.float64 and u.is_contiguous()):
+            raise ValueError("steady updates u in place: pass a contiguous float64 device tensor")
+        ws, nbytes = self.workspace(m, 1, prec, jvp)
+        inf = SteadyInfo()
+        self._check(self.lib.pcexp_steady(self.ctx, _ptr(u), float(cfl_max), float(tol), int(max_iter),
+                                          int(check_every), m, SCHEME[scheme], PREC[prec], JVP[jvp], _ptr(ws),
+                                          nbytes, ctypes.byref(inf), self._stream()), "steady")
+        return inf.as_dict()
 
     def step(self, u, dt=0.0, cfl=0.0, m=30, scheme="pcexp", prec="f64", jvp="tangent", info=False):
         """u_n -> u_{n+1} in place (u must be a contiguous FP64 device tensor)."""

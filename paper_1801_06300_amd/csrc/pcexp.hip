@@ -747,24 +747,36 @@ pcexp_status pcexp_arnoldi_phi(pcexp_ctx* c, const double* u_lin, const double* 
   return PCEXP_OK;
 }
 
-pcexp_status pcexp_step(pcexp_ctx* c, double* u, double dt, double cfl, int32_t m, int32_t scheme, int32_t prec,
-                        int32_t jvp, void* ws, size_t ws_bytes, pcexp_step_info* info, void* stream) {
-  pcexp_status s = check_common(c, m, 1, prec, jvp, ws, ws_bytes);
-  if (s != PCEXP_OK) return s;
-  if (!u) return fail(c, PCEXP_E_ARG, "u is NULL");
-  if (scheme != PCEXP_SCHEME_PCEXP && scheme != PCEXP_SCHEME_EXP1) return fail(c, PCEXP_E_ARG, "bad scheme");
-  if (!(dt > 0.0) && !(cfl > 0.0)) return fail(c, PCEXP_E_ARG, "need dt > 0 or cfl > 0");
-  if (!(dt > 0.0) && c->dense) return fail(c, PCEXP_E_ARG, "dense contexts need dt > 0");
-  if (!std::isfinite(dt) || !std::isfinite(cfl)) return fail(c, PCEXP_E_ARG, "dt/cfl must be finite");
-  hipStream_t st = (hipStream_t)stream;
-  const WsLayout L = ws_layout(c, m, 1, prec);
-  char* w = (char*)ws;
+}  // extern "C"
+
+namespace {
+
+// How a step chooses dt: fixed, from a constant CFL (eq. (x3d)), or from the
+// CFL ramp of eq. (cfl) driven by ||R(rho_n)|| (pseudo-time iteration n).
+struct DtMode {
+  double dt = 0.0, cfl = 0.0, cfl_max = 0.0;
+  int ramp_iter = 0;   // > 0: ramp at this iteration
+};
+
+// cfl = min(cfl_max, max(r^-3, 1 + (n-1)/(2p+1))), r = sqrt(sum R_rho^2) / |Omega| (eq. (cfl)).
+__global__ void cfl_ramp_kernel(const double* rsqrt, double inv_vol, int n, int p, double cfl_max, double* cfl,
+                                double* rnorm) {
+  const double r = *rsqrt * inv_vol;
+  const double big = r > 0.0 ? 1.0 / (r * r * r) : INFINITY;
+  const double lin = 1.0 + (double)(n - 1) / (2 * p + 1);
+  *cfl = fmin(cfl_max, fmax(big, lin));
+  *rnorm = r;
+}
+
+// One step on internal vectors: un (u_n) is replaced by u_{n+1}.  scal[0] = dt,
+// scal[4] = ||R(rho_n)|| (ramp mode), scal[5] = CFL used (ramp mode).
+pcexp_status step_core(pcexp_ctx* c, double* un, const DtMode& dm, int m, int scheme, int prec, int jvp, char* w,
+                       const WsLayout& L, hipStream_t st) {
   KState* ks1 = (KState*)(w + L.ks1);
   KState* ks2 = (KState*)(w + L.ks2);
   double* part = (double*)(w + L.part);
   double* phi = (double*)(w + L.phi);
   double* scal = (double*)(w + L.scal);
-  double* un = (double*)(w + L.un);
   double* Rn = (double*)(w + L.Rn);
   double* us = (double*)(w + L.us);
   double* Rs = (double*)(w + L.Rs);
@@ -773,69 +785,112 @@ pcexp_status pcexp_step(pcexp_ctx* c, double* u, double dt, double cfl, int32_t 
   unsigned* cnt = (unsigned*)(w + L.cnt);
   const size_t n = c->Kint;
   double* dtp = &scal[0];
+  const bool exp1 = scheme == PCEXP_SCHEME_EXP1;
 
-  k_fill<unsigned>(cnt, 0u, 64, nullptr, st);
-  to_int(c, u, un, st);
-  if (dt > 0.0) k_set_scalar(dtp, dt, st);
-  else ek_stable_dt(elem_args(c), un, nullptr, cfl, dtp, part, &cnt[0], st);
   if (!residual_int(c, un, Rn, st)) return fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
+  if (dm.dt > 0.0) {
+    k_set_scalar(dtp, dm.dt, st);
+  } else if (dm.ramp_iter > 0) {
+    k_sumsq(Rn, (size_t)c->nb * c->Epad, &scal[6], 1, part, &cnt[3], st);
+    launch(cfl_ramp_kernel, dim3(1), dim3(1), 0, st, (const double*)&scal[6], 1.0 / c->volume_total, dm.ramp_iter,
+           c->p, dm.cfl_max, &scal[5], &scal[4]);
+    ek_stable_dt(elem_args(c), un, &scal[5], 0.0, dtp, part, &cnt[0], st);
+  } else {
+    ek_stable_dt(elem_args(c), un, nullptr, dm.cfl, dtp, part, &cnt[0], st);
+  }
   const bool mixed = (prec == PCEXP_PREC_MIXED);
   if (mixed) k_cast<double, float>(un, un32, n, st);
 
+  // stage 1: x1 = dt Phi_1(dt J_n) R_n; u* = u_n + x1 (EXP1: the result, written over u_n)
+  double* out1 = exp1 ? un : us;
   if (mixed) {
     float* V = (float*)(w + L.V);
     arnoldi_run<float>(c, jvp, prec, un, un32, Rn, Rn, dtp, 1, m, ks1, part, phi, V, st);
     Prof pr(c, st, PC_COMB, (double)c->K * (m * 4.0 + 8 + 8 + 4));
-    k_combine<float, float>(V, c->Kld, ks1, un, us, (float*)x1, 1.0, dtp, n, st);
+    k_combine<float, float>(V, c->Kld, ks1, un, out1, exp1 ? (float*)nullptr : (float*)x1, 1.0, dtp, n, st);
   } else {
     double* V = (double*)(w + L.V);
     arnoldi_run<double>(c, jvp, prec, un, nullptr, Rn, Rn, dtp, 1, m, ks1, part, phi, V, st);
     Prof pr(c, st, PC_COMB, (double)c->K * (m * 8.0 + 8 + 8 + 8));
-    k_combine<double, double>(V, c->Kld, ks1, un, us, (double*)x1, 1.0, dtp, n, st);
+    k_combine<double, double>(V, c->Kld, ks1, un, out1, exp1 ? (double*)nullptr : (double*)x1, 1.0, dtp, n, st);
   }
-  if (scheme == PCEXP_SCHEME_EXP1) {
-    to_abi(c, us, u, st);
+  if (exp1) return PCEXP_OK;
+
+  // N* - N_n = R(u*) - R_n - J_n x1
+  if (!residual_int(c, us, Rs, st)) return fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
+  if (mixed) {
+    float* jx = (float*)(w + L.V);  // Krylov storage is free between the two Arnoldi runs
+    jvp_int(c, jvp, prec, un, un32, x1, jx, nullptr, nullptr, Rn, nullptr, st);
+    k_glue_d<float>(Rs, Rn, jx, Rs, n, st);
   } else {
-    // N* - N_n = R(u*) - R_n - J_n x1
-    if (!residual_int(c, us, Rs, st)) return fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
-    if (mixed) {
-      float* jx = (float*)(w + L.V);  // Krylov storage is free between the two Arnoldi runs
-      jvp_int(c, jvp, prec, un, un32, x1, jx, nullptr, nullptr, Rn, nullptr, st);
-      k_glue_d<float>(Rs, Rn, jx, Rs, n, st);
-    } else {
-      double* jx = (double*)(w + L.V);
-      if (jvp == PCEXP_JVP_FD) {
-        k_sumsq(un, n, &scal[1], 1, part, &cnt[1], st);
-        k_sumsq((const double*)x1, n, &scal[2], 1, part, &cnt[2], st);
-        k_fd_eps(&scal[1], &scal[2], kSqrtEps, &scal[3], st);
-      }
-      jvp_int(c, jvp, prec, un, nullptr, x1, jx, nullptr, nullptr, Rn, &scal[3], st);
-      k_glue_d<double>(Rs, Rn, jx, Rs, n, st);
+    double* jx = (double*)(w + L.V);
+    if (jvp == PCEXP_JVP_FD) {
+      k_sumsq(un, n, &scal[1], 1, part, &cnt[1], st);
+      k_sumsq((const double*)x1, n, &scal[2], 1, part, &cnt[2], st);
+      k_fd_eps(&scal[1], &scal[2], kSqrtEps, &scal[3], st);
     }
-    if (mixed) {
-      float* V = (float*)(w + L.V);
-      arnoldi_run<float>(c, jvp, prec, un, un32, Rs, Rn, dtp, 1, m, ks2, part, phi, V, st);
-      Prof pr(c, st, PC_COMB, (double)c->K * (m * 4.0 + 8 + 8));
-      k_combine<float, double>(V, c->Kld, ks2, us, un, (double*)nullptr, 0.5, dtp, n, st);
-    } else {
-      double* V = (double*)(w + L.V);
-      arnoldi_run<double>(c, jvp, prec, un, nullptr, Rs, Rn, dtp, 1, m, ks2, part, phi, V, st);
-      Prof pr(c, st, PC_COMB, (double)c->K * (m * 8.0 + 8 + 8));
-      k_combine<double, double>(V, c->Kld, ks2, us, un, (double*)nullptr, 0.5, dtp, n, st);
-    }
-    to_abi(c, un, u, st);
+    jvp_int(c, jvp, prec, un, nullptr, x1, jx, nullptr, nullptr, Rn, &scal[3], st);
+    k_glue_d<double>(Rs, Rn, jx, Rs, n, st);
   }
+  // stage 2: u_{n+1} = u* + dt/2 Phi_1(dt J_n)(N* - N_n)
+  if (mixed) {
+    float* V = (float*)(w + L.V);
+    arnoldi_run<float>(c, jvp, prec, un, un32, Rs, Rn, dtp, 1, m, ks2, part, phi, V, st);
+    Prof pr(c, st, PC_COMB, (double)c->K * (m * 4.0 + 8 + 8));
+    k_combine<float, double>(V, c->Kld, ks2, us, un, (double*)nullptr, 0.5, dtp, n, st);
+  } else {
+    double* V = (double*)(w + L.V);
+    arnoldi_run<double>(c, jvp, prec, un, nullptr, Rs, Rn, dtp, 1, m, ks2, part, phi, V, st);
+    Prof pr(c, st, PC_COMB, (double)c->K * (m * 8.0 + 8 + 8));
+    k_combine<double, double>(V, c->Kld, ks2, us, un, (double*)nullptr, 0.5, dtp, n, st);
+  }
+  return PCEXP_OK;
+}
+
+pcexp_status check_step_args(pcexp_ctx* c, int m, int scheme, int prec, int jvp, void* ws, size_t ws_bytes) {
+  pcexp_status s = check_common(c, m, 1, prec, jvp, ws, ws_bytes);
+  if (s != PCEXP_OK) return s;
+  if (scheme != PCEXP_SCHEME_PCEXP && scheme != PCEXP_SCHEME_EXP1) return fail(c, PCEXP_E_ARG, "bad scheme");
+  return PCEXP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pcexp_status pcexp_step(pcexp_ctx* c, double* u, double dt, double cfl, int32_t m, int32_t scheme, int32_t prec,
+                        int32_t jvp, void* ws, size_t ws_bytes, pcexp_step_info* info, void* stream) {
+  pcexp_status s = check_step_args(c, m, scheme, prec, jvp, ws, ws_bytes);
+  if (s != PCEXP_OK) return s;
+  if (!u) return fail(c, PCEXP_E_ARG, "u is NULL");
+  if (!(dt > 0.0) && !(cfl > 0.0)) return fail(c, PCEXP_E_ARG, "need dt > 0 or cfl > 0");
+  if (!(dt > 0.0) && c->dense) return fail(c, PCEXP_E_ARG, "dense contexts need dt > 0");
+  if (!std::isfinite(dt) || !std::isfinite(cfl)) return fail(c, PCEXP_E_ARG, "dt/cfl must be finite");
+  hipStream_t st = (hipStream_t)stream;
+  const WsLayout L = ws_layout(c, m, 1, prec);
+  char* w = (char*)ws;
+  double* scal = (double*)(w + L.scal);
+  double* un = (double*)(w + L.un);
+  double* Rn = (double*)(w + L.Rn);
+  double* part = (double*)(w + L.part);
+  unsigned* cnt = (unsigned*)(w + L.cnt);
+  k_fill<unsigned>(cnt, 0u, 64, nullptr, st);
+  to_int(c, u, un, st);
+  DtMode dm;
+  dm.dt = dt > 0.0 ? dt : 0.0;
+  dm.cfl = cfl;
+  s = step_core(c, un, dm, m, scheme, prec, jvp, w, L, st);
+  if (s != PCEXP_OK) return s;
+  to_abi(c, un, u, st);
   s = hip_check(c, "step");
   if (s != PCEXP_OK) return s;
   if (info) {
     std::memset(info, 0, sizeof(*info));
-    if (!c->dense) {
-      k_sumsq(Rn, (size_t)c->nb * c->Epad, &scal[4], 1, part, &cnt[3], st);
-    }
+    if (!c->dense) k_sumsq(Rn, (size_t)c->nb * c->Epad, &scal[4], 1, part, &cnt[3], st);
     KState h1, h2;
     double sc[8];
-    if (hipMemcpyAsync(&h1, ks1, sizeof(KState), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipMemcpyAsync(&h2, ks2, sizeof(KState), hipMemcpyDeviceToHost, st) != hipSuccess ||
+    if (hipMemcpyAsync(&h1, (KState*)(w + L.ks1), sizeof(KState), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&h2, (KState*)(w + L.ks2), sizeof(KState), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipMemcpyAsync(sc, scal, sizeof(sc), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       return fail(c, PCEXP_E_HIP, "info sync failed");
@@ -846,6 +901,71 @@ pcexp_status pcexp_step(pcexp_ctx* c, double* u, double dt, double cfl, int32_t 
     return report_flags(c, &info->flags);
   }
   return PCEXP_OK;
+}
+
+pcexp_status pcexp_steady(pcexp_ctx* c, double* u, double cfl_max, double tol, int32_t max_iter,
+                          int32_t check_every, int32_t m, int32_t scheme, int32_t prec, int32_t jvp, void* ws,
+                          size_t ws_bytes, pcexp_steady_info* info, void* stream) {
+  pcexp_status s = check_step_args(c, m, scheme, prec, jvp, ws, ws_bytes);
+  if (s != PCEXP_OK) return s;
+  if (!u) return fail(c, PCEXP_E_ARG, "u is NULL");
+  if (c->dense) return fail(c, PCEXP_E_UNSUPPORTED, "the CFL ramp needs a mesh");
+  if (!(cfl_max > 0.0) || !std::isfinite(cfl_max) || !(tol >= 0.0) || max_iter < 1 || check_every < 1)
+    return fail(c, PCEXP_E_ARG, "need cfl_max > 0, tol >= 0, max_iter >= 1, check_every >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  const WsLayout L = ws_layout(c, m, 1, prec);
+  char* w = (char*)ws;
+  double* scal = (double*)(w + L.scal);
+  double* un = (double*)(w + L.un);
+  double* Rn = (double*)(w + L.Rn);
+  double* part = (double*)(w + L.part);
+  unsigned* cnt = (unsigned*)(w + L.cnt);
+  k_fill<unsigned>(cnt, 0u, 64, nullptr, st);
+  to_int(c, u, un, st);
+  double r0 = -1.0, r = -1.0;
+  int it = 0;
+  bool conv = false;
+  while (it < max_iter) {
+    DtMode dm;
+    dm.cfl_max = cfl_max;
+    dm.ramp_iter = it + 1;
+    s = step_core(c, un, dm, m, scheme, prec, jvp, w, L, st);
+    if (s != PCEXP_OK) return s;
+    ++it;
+    if (it == 1 || it % check_every == 0 || it == max_iter) {
+      // scal[4] holds ||R(rho)|| at the start of the latest step
+      double sc[8];
+      if (hipMemcpyAsync(sc, scal, sizeof(sc), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return fail(c, PCEXP_E_HIP, "steady sync failed");
+      if (it == 1) r0 = sc[4];
+      r = sc[4];
+      if (!std::isfinite(r)) return fail(c, PCEXP_E_NONFINITE, "residual norm is not finite");
+      if (r <= tol) {
+        conv = true;
+        break;
+      }
+    }
+  }
+  // residual norm of the final state
+  if (!residual_int(c, un, Rn, st)) return fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
+  k_sumsq(Rn, (size_t)c->nb * c->Epad, &scal[6], 1, part, &cnt[3], st);
+  double rf = 0.0;
+  if (hipMemcpyAsync(&rf, &scal[6], sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(c, PCEXP_E_HIP, "steady sync failed");
+  rf /= c->volume_total;
+  to_abi(c, un, u, st);
+  s = hip_check(c, "steady");
+  if (s != PCEXP_OK) return s;
+  if (info) {
+    info->iterations = it;
+    info->converged = (conv || rf <= tol) ? 1 : 0;
+    info->res_rho_norm0 = r0;
+    info->res_rho_norm = rf;
+  }
+  uint32_t f;
+  return report_flags(c, &f);
 }
 
 pcexp_status pcexp_pressure_functional(pcexp_ctx* c, const double* u, double p_ref, double* value_host,
