@@ -243,8 +243,9 @@ pcexp_status pcexp_steady(pcexp_ctx* ctx, double* u, double cfl_max, double tol,
  * [0, PCEXP_PROF_NCLASS), out[3c] = total milliseconds, out[3c+1] = launches,
  * out[3c+2] = algorithmic bytes moved (reads + writes the operation needs).
  * Classes: 0 residual, 1 JVP, 2 Gram-Schmidt reduction pass (V^T [U W]),
- * 3 its one-block finalisation (no HBM bytes), 4 Gram-Schmidt update pass,
- * 5 Hessenberg phi, 6 Krylov combination, 7 other. */
+ * 3 the one-block closing of the last Hessenberg column (no HBM bytes),
+ * 4 Gram-Schmidt finalise-and-update pass, 5 Hessenberg phi, 6 Krylov
+ * combination, 7 other. */
 #define PCEXP_PROF_NCLASS 8
 pcexp_status pcexp_profile(pcexp_ctx* ctx, int32_t op, double* out);
 

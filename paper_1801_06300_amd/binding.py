@@ -319,7 +319,7 @@ class PCEXP:
                     "arnoldi_phi")
         return (out, inf.as_dict()) if info else out
 
-    PROFILE_CLASSES = ("residual", "jvp", "gs_reduce", "gs_finalize", "gs_update", "hess_phi", "combine", "other")
+    PROFILE_CLASSES = ("residual", "jvp", "gs_reduce", "gs_close", "gs_update", "hess_phi", "combine", "other")
 
     def profile(self, op):
         """op 'start' (enable + reset), 'stop', or 'read' -> {class: (ms, launches, bytes)}."""

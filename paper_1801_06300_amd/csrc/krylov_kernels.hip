@@ -116,17 +116,21 @@ __device__ __forceinline__ void block_partials(const double* acc, int nvec, doub
 __global__ void init_state_kernel(KState* ks, double eta) {
   const int t = threadIdx.x;
   for (int i = t; i < KLD * KMAX; i += blockDim.x) ks->H[i] = 0.0;
+  for (int i = t; i < 2 * KLD; i += blockDim.x) ks->htent[i] = 0.0;
   for (int i = t; i < KMAX + 2; i += blockDim.x) {
     ks->sigma[i] = 0.0;
-    ks->hcol[i] = 0.0;
+    ks->sig_t[i] = 0.0;
+    ks->nu_t[i] = 0.0;
+    ks->wn_t[i] = 0.0;
   }
   for (int i = t; i < KMAX + 4; i += blockDim.x) ks->y[i] = 0.0;
   if (t < 8) ks->counter[t] = 0u;
   if (t == 0) {
-    ks->beta = ks->wnorm = ks->hlast = ks->fd_eps = 0.0;
+    ks->beta = ks->hlast = ks->fd_eps = 0.0;
     ks->eta = eta;
     ks->m_eff = 0;
     ks->done = 0;
+    ks->done_at = 0x7fffffff;
     ks->breakdown = 0;
   }
 }
@@ -158,9 +162,10 @@ __global__ __launch_bounds__(64) void start_finalize(KState* ks, const double* p
     const double beta = sqrt(s);
     ks->beta = beta;
     if (beta > 0.0) {
-      ks->sigma[0] = 1.0 / beta;
+      ks->sig_t[0] = 1.0 / beta;
     } else {
       ks->done = 1;
+      ks->done_at = -1;
       ks->m_eff = 0;
     }
   }
@@ -306,116 +311,141 @@ __global__ __launch_bounds__(RT) void dcgs_reduce(const TV* __restrict__ V, size
   }
 }
 
-__global__ __launch_bounds__(RT) void dcgs_finalize(KState* ks, const double* part, int j, int nblk) {
-  if (ks->done) return;
+// Finalise iteration j and rewrite V_j, V_{j+1} in one pass.  Slot j holds U
+// (once-orthogonalised q_j with tentative scale sig_t[j], u = sig_t[j] U),
+// slot j+1 holds W = J u; the partials hold V_i.U, V_i.W (i < j), U.U, U.W, W.W.
+//   s = Q^T u, rho^2 = |u|^2 - |s|^2, q_j = (u - Q s)/rho; column j-1 of H
+//   gets nu s and nu rho (nu = nu_t[j]); J q_j = (W - J Q s)/rho with J Q s
+//   from the Arnoldi relation of the finished columns; h = [Q q_j]^T J q_j;
+//   next U' = J q_j - [Q q_j] h, |U'|^2 = |J q_j|^2 - |h|^2 (tentative).
+//   V_j <- U - sum e_i V_i;  V_{j+1} <- W/rho - a U - sum b_i V_i.
+// Every block computes the same algebra (same inputs, same order); block 0
+// publishes H, the scales and the stop flags, into locations no block of this
+// launch reads.
+template <typename TV, int NV, int PW, int CV>
+__global__ __launch_bounds__(RT) void dcgs_fin_update(TV* __restrict__ V, size_t ld, int j, size_t n, KState* ks,
+                                                      const double* part, int nblk) {
+  if (ks->done_at < j) return;
   const int nq = j;
+  const bool writer = blockIdx.x == 0;
   __shared__ double col[2 * KMAX + 3];
-  __shared__ double s[KMAX], z[KMAX], g[KMAX];
-  __shared__ double Hs[KMAX * KMAX];   // H[l][i], l < nq, i < nq, row-major (staged once)
-  __shared__ double rho_s;
-  __shared__ int stop;
+  __shared__ double s[KMAX], z[KMAX];
+  __shared__ double Hs[KMAX * KMAX];   // H[l][i], l, i < nq; column nq-1 tentative
+  __shared__ double e[NV], b[NV];
+  __shared__ double sa, sir;
+  __shared__ int go;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   block_col_sums(part, 2 * nq + 3, nblk, col);
+  const double* Ht = ks->htent + (size_t)((j + 1) & 1) * KLD;
   for (int t = tid; t < nq * nq; t += RT) {
-    const int i = t / nq, l = t % nq;            // column i, row l (coalesced over l)
-    Hs[l * KMAX + i] = ks->H[(size_t)i * KLD + l];
+    const int i = t / nq, l = t % nq;            // column i, row l
+    Hs[l * KMAX + i] = (i == nq - 1) ? Ht[l] : ks->H[(size_t)i * KLD + l];
+  }
+  for (int i = nq + tid; i < NV; i += RT) {
+    e[i] = 0.0;
+    b[i] = 0.0;
   }
   __syncthreads();
-  if (wid != 0) return;                 // the O(j^2) algebra runs on one wave, lane l <-> row l
-  double* H = ks->H;
-  const double eta = ks->eta;
-  const double sj = ks->sigma[j];
-  const bool live = lane < nq;
-  const double sl = live ? ks->sigma[lane] * sj * col[lane] : 0.0;
-  const double zl = live ? ks->sigma[lane] * col[nq + lane] : 0.0;
-  if (live) { s[lane] = sl; z[lane] = zl; }
-  const double ss = wave_sum(sl * sl);
-  const double alpha = sj * sj * col[2 * nq];
-  const double zeta = sj * col[2 * nq + 1];
-  const double omega = col[2 * nq + 2];
-  if (lane == 0) {
-    stop = 0;
+  if (wid == 0) {   // the O(j^2) algebra on one wave, lane l <-> row l
+    double* H = ks->H;
+    const double eta = ks->eta;
+    const double sj = ks->sig_t[j];
+    const double nu = ks->nu_t[j];
+    const bool live = lane < nq;
+    const double sgl = live ? ks->sigma[lane] : 0.0;
+    const double sl = live ? sgl * sj * col[lane] : 0.0;
+    const double zl = live ? sgl * col[nq + lane] : 0.0;
+    if (live) { s[lane] = sl; z[lane] = zl; }
+    const double ss = wave_sum(sl * sl);
+    const double alpha = sj * sj * col[2 * nq];
+    const double zeta = sj * col[2 * nq + 1];
+    const double omega = col[2 * nq + 2];
     double rho = 1.0;
+    bool stop = false;
     if (j > 0) {
       const double r2 = alpha - ss;
       rho = r2 > 0.0 ? sqrt(r2) : 0.0;
-      const double hjj1 = ks->nu * rho;
-      H[(size_t)(j - 1) * KLD + j] = hjj1;
-      ks->hlast = hjj1;
-      if (!(hjj1 > eta * ks->wnorm)) {  // v_j lies in the span: stop with m_eff = j
-        ks->breakdown = 1;
-        ks->done = 1;
-        ks->m_eff = j;
-        stop = 1;
+      const double hjj1 = nu * rho;
+      stop = !(hjj1 > eta * ks->wn_t[j]);   // v_j lies in the span: stop with m_eff = j
+      if (writer && lane == 0) {
+        H[(size_t)(j - 1) * KLD + j] = hjj1;
+        ks->hlast = hjj1;
+        if (stop) {
+          ks->breakdown = 1;
+          ks->done = 1;
+          ks->done_at = j;
+          ks->m_eff = j;
+        }
       }
     }
-    rho_s = rho;
-  }
-  // finish column j-1 (each lane keeps its own corrected entry: no global read-after-write)
-  double hcol_new = 0.0;
-  if (j > 0 && live) {
-    hcol_new = Hs[lane * KMAX + (j - 1)] + ks->nu * sl;
-    H[(size_t)(j - 1) * KLD + lane] = hcol_new;
-  }
-  __builtin_amdgcn_wave_barrier();
-  if (stop) return;
-  const double rho = rho_s;
-  // J Q s from the finished columns: g_l = sum_i H[l][i] s_i, c = h_{j,j-1} s_{j-1}
-  double gl = 0.0;
-  if (live) {
-    for (int i = (lane > 0 ? lane - 1 : 0); i < nq - 1; ++i) gl += Hs[lane * KMAX + i] * s[i];
-    gl += hcol_new * s[nq - 1];
-  }
-  const double gz = wave_sum(gl * zl), gg = wave_sum(gl * gl), sz = wave_sum(sl * zl);
-  const double c = (j > 0) ? ks->nu * rho * s[j - 1] : 0.0;
-  const double ir = 1.0 / rho;
-  const double qW = (zeta - sz) * ir;
-  const double hl = live ? (zl - gl) * ir : 0.0;
-  const double hj = (qW - c) * ir;
-  const double hh = wave_sum(hl * hl) + hj * hj;
-  const double jq2 = (omega - 2.0 * (gz + c * qW) + gg + c * c) * ir * ir;
-  const double wn = sqrt(jq2 > 0.0 ? jq2 : 0.0);
-  const double t = c * ir + hj;
-  if (live) {
-    H[(size_t)j * KLD + lane] = hl;
-    ks->hcol[lane] = sl * ks->sigma[lane] / sj;
-    ks->coefb[lane] = ks->sigma[lane] * (gl * ir + hl - t * sl * ir);
-  }
-  if (lane == 0) {
-    H[(size_t)j * KLD + j] = hj;
-    ks->wnorm = wn;
-    ks->m_eff = j + 1;
-    ks->acoef = t * sj * ir;
-    ks->rinv = ir;
-    ks->sigma[j] = sj * ir;
-    const double nu2 = jq2 - hh;
-    if (!(nu2 > (eta * wn) * (eta * wn))) {   // J q_j lies in the span: m_eff = j + 1
-      ks->breakdown = 1;
-      ks->done = 1;
-      ks->hlast = nu2 > 0.0 ? sqrt(nu2) : 0.0;
-      H[(size_t)j * KLD + j + 1] = ks->hlast;
+    // finish column j-1 (each lane keeps its own corrected entry)
+    double hcol_new = 0.0;
+    if (j > 0 && live) {
+      hcol_new = Hs[lane * KMAX + (j - 1)] + nu * sl;
+      if (writer) H[(size_t)(j - 1) * KLD + lane] = hcol_new;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (stop) {
+      if (lane == 0) go = 0;
     } else {
-      const double nup = sqrt(nu2);
-      ks->nu = nup;
-      ks->sigma[j + 1] = 1.0 / nup;
-      H[(size_t)j * KLD + j + 1] = nup;   // tentative; corrected by the next iteration
+      // J Q s from the finished columns: g_l = sum_i H[l][i] s_i, c = h_{j,j-1} s_{j-1}
+      double gl = 0.0;
+      if (live) {
+        for (int i = (lane > 0 ? lane - 1 : 0); i < nq - 1; ++i) gl += Hs[lane * KMAX + i] * s[i];
+        gl += hcol_new * s[nq - 1];
+      }
+      const double gz = wave_sum(gl * zl), gg = wave_sum(gl * gl), sz = wave_sum(sl * zl);
+      const double c = (j > 0) ? nu * rho * s[j - 1] : 0.0;
+      const double ir = 1.0 / rho;
+      const double qW = (zeta - sz) * ir;
+      const double hl = live ? (zl - gl) * ir : 0.0;
+      const double hj = (qW - c) * ir;
+      const double hh = wave_sum(hl * hl) + hj * hj;
+      const double jq2 = (omega - 2.0 * (gz + c * qW) + gg + c * c) * ir * ir;
+      const double wn = sqrt(jq2 > 0.0 ? jq2 : 0.0);
+      const double t = c * ir + hj;
+      if (live) {
+        e[lane] = sl * sgl / sj;
+        b[lane] = sgl * (gl * ir + hl - t * sl * ir);
+      }
+      const double nu2 = jq2 - hh;
+      const bool stop2 = !(nu2 > (eta * wn) * (eta * wn));   // J q_j lies in the span: m_eff = j + 1
+      if (writer) {
+        double* Hn = ks->htent + (size_t)(j & 1) * KLD;
+        if (live) {
+          H[(size_t)j * KLD + lane] = hl;
+          Hn[lane] = hl;
+        }
+        if (lane == 0) {
+          H[(size_t)j * KLD + j] = hj;
+          Hn[j] = hj;
+          ks->sigma[j] = sj * ir;
+          ks->wn_t[j + 1] = wn;
+          ks->m_eff = j + 1;
+          if (stop2) {
+            ks->breakdown = 1;
+            ks->done = 1;
+            ks->done_at = j;
+            ks->hlast = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+            H[(size_t)j * KLD + j + 1] = ks->hlast;
+          } else {
+            const double nup = sqrt(nu2);
+            ks->nu_t[j + 1] = nup;
+            ks->sig_t[j + 1] = 1.0 / nup;
+            H[(size_t)j * KLD + j + 1] = nup;   // tentative; corrected by the next iteration
+          }
+        }
+      }
+      if (lane == 0) {
+        sa = t * sj * ir;
+        sir = ir;
+        go = 1;
+      }
     }
   }
-}
-
-// CV vectors per inner step: CV == NV unrolls everything (loads of one entry
-// all in flight); CV < NV bounds the registers of the long-basis buckets.
-template <typename TV, int NV, int PW, int CV>
-__global__ __launch_bounds__(RT) void dcgs_update(TV* __restrict__ V, size_t ld, int j, size_t n, const KState* ks) {
-  if (ks->m_eff <= j) return;          // q_j is not part of the basis
-  const int nq = j;
-  __shared__ double e[NV], b[NV];
-  for (int i = threadIdx.x; i < NV; i += RT) {
-    e[i] = i < nq ? ks->hcol[i] : 0.0;
-    b[i] = i < nq ? ks->coefb[i] : 0.0;
-  }
   __syncthreads();
-  const double a = ks->acoef, ir = ks->rinv;
+  if (!go) return;
+  const double a = sa, ir = sir;
   TV* U = V + (size_t)j * ld;
   TV* W = V + (size_t)(j + 1) * ld;
   const size_t np = PW == 2 ? (n + 1) / 2 : n;
@@ -460,7 +490,7 @@ __global__ __launch_bounds__(RT) void dcgs_close_finalize(KState* ks, const doub
   block_col_sums(part, m + 1, nblk, col);
   __syncthreads();
   if (threadIdx.x != 0) return;
-  const double sm = ks->sigma[m], nu = ks->nu;
+  const double sm = ks->sig_t[m], nu = ks->nu_t[m];
   double ss = 0.0;
   for (int i = 0; i < m; ++i) {
     const double si = ks->sigma[i] * sm * col[i];
@@ -501,21 +531,22 @@ static void launch_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, d
 }
 
 template <typename TV>
-static void launch_update(TV* V, size_t ld, int j, size_t n, const KState* ks, hipStream_t st) {
+static void launch_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st) {
   const int nq = j > 0 ? j : 1;
   const dim3 g((unsigned)gs_blocks(n)), b(RT);
-  if (nq <= 4) launch((dcgs_update<TV, 4, 2, 4>), g, b, 0, st, V, ld, j, n, ks);
-  else if (nq <= 8) launch((dcgs_update<TV, 8, 2, 8>), g, b, 0, st, V, ld, j, n, ks);
-  else if (nq <= 12) launch((dcgs_update<TV, 12, 2, 12>), g, b, 0, st, V, ld, j, n, ks);
-  else if (nq <= 16) launch((dcgs_update<TV, 16, 2, 16>), g, b, 0, st, V, ld, j, n, ks);
-  else if (nq <= 20) launch((dcgs_update<TV, 20, 2, 20>), g, b, 0, st, V, ld, j, n, ks);
-  else if (nq <= 24) launch((dcgs_update<TV, 24, 2, 24>), g, b, 0, st, V, ld, j, n, ks);
+  const int nb = red_blocks(n, nq);
+  if (nq <= 4) launch((dcgs_fin_update<TV, 4, 2, 4>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 8) launch((dcgs_fin_update<TV, 8, 2, 8>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 12) launch((dcgs_fin_update<TV, 12, 2, 12>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 16) launch((dcgs_fin_update<TV, 16, 2, 16>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 20) launch((dcgs_fin_update<TV, 20, 2, 20>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 24) launch((dcgs_fin_update<TV, 24, 2, 24>), g, b, 0, st, V, ld, j, n, ks, part, nb);
   else if (nq <= 28) {
     constexpr int PW = sizeof(TV) == 8 ? 2 : 1;   // FP32 pairs would spill here
-    launch((dcgs_update<TV, 28, PW, 28>), g, b, 0, st, V, ld, j, n, ks);
+    launch((dcgs_fin_update<TV, 28, PW, 28>), g, b, 0, st, V, ld, j, n, ks, part, nb);
   }
-  else if (nq <= 32) launch((dcgs_update<TV, 32, 1, 32>), g, b, 0, st, V, ld, j, n, ks);
-  else launch((dcgs_update<TV, KMAX, 1, 16>), g, b, 0, st, V, ld, j, n, ks);
+  else if (nq <= 32) launch((dcgs_fin_update<TV, 32, 1, 32>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else launch((dcgs_fin_update<TV, KMAX, 1, 16>), g, b, 0, st, V, ld, j, n, ks, part, nb);
 }
 
 template <typename TV>
@@ -524,15 +555,13 @@ void k_gs_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, double* pa
   else launch_reduce<TV, false>(V, ld, j, n, ks, part, st);
 }
 
-void k_gs_finalize(KState* ks, const double* part, int j, size_t n, bool close, hipStream_t st) {
-  const int nblk = red_blocks(n, j > 0 ? j : 1);
-  if (close) launch(dcgs_close_finalize, dim3(1), dim3(RT), 0, st, ks, part, j, nblk);
-  else launch(dcgs_finalize, dim3(1), dim3(RT), 0, st, ks, part, j, nblk);
+template <typename TV>
+void k_gs_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st) {
+  launch_update<TV>(V, ld, j, n, ks, part, st);
 }
 
-template <typename TV>
-void k_gs_update(TV* V, size_t ld, int j, size_t n, const KState* ks, hipStream_t st) {
-  launch_update<TV>(V, ld, j, n, ks, st);
+void k_gs_close(KState* ks, const double* part, int m, size_t n, hipStream_t st) {
+  launch(dcgs_close_finalize, dim3(1), dim3(RT), 0, st, ks, part, m, red_blocks(n, m > 0 ? m : 1));
 }
 
 // ------------------------------------------------------------ Hessenberg phi
@@ -1041,8 +1070,8 @@ template void k_start<double>(const double*, double*, size_t, KState*, double*, 
 template void k_start<float>(const double*, float*, size_t, KState*, double*, hipStream_t);
 template void k_gs_reduce<double>(const double*, size_t, int, size_t, KState*, double*, bool, hipStream_t);
 template void k_gs_reduce<float>(const float*, size_t, int, size_t, KState*, double*, bool, hipStream_t);
-template void k_gs_update<double>(double*, size_t, int, size_t, const KState*, hipStream_t);
-template void k_gs_update<float>(float*, size_t, int, size_t, const KState*, hipStream_t);
+template void k_gs_update<double>(double*, size_t, int, size_t, KState*, const double*, hipStream_t);
+template void k_gs_update<float>(float*, size_t, int, size_t, KState*, const double*, hipStream_t);
 template void k_combine<double, double>(const double*, size_t, const KState*, const double*, double*, double*,
                                         double, const double*, size_t, hipStream_t);
 template void k_combine<float, float>(const float*, size_t, const KState*, const double*, double*, float*,

@@ -23,24 +23,27 @@ constexpr int KMAX = 64;          // largest Krylov dimension
 constexpr int KLD = KMAX + 1;     // leading dimension of H
 constexpr int GS_THREADS = 256;
 
+// Arnoldi state.  Quantities that iteration j reads and iteration j writes
+// are kept apart (tentative values indexed by iteration, H's tentative column
+// double-buffered), because every block of the fused finalise-and-update pass
+// recomputes the iteration's small algebra while block 0 publishes it.
 struct KState {
-  double H[KLD * KMAX];    // column-major Hessenberg, H[j*KLD + i]
-  double sigma[KMAX + 2];  // scale of each stored basis vector
-  double hcol[KMAX + 2];   // re-orthogonalisation coefficients of the current vector
-  double coefb[KMAX + 2];  // coefficients of the next vector's update
-  double acoef, rinv;      // next vector = rinv * W - acoef * U - sum coefb_i V_i
-  double nu;               // tentative norm of the stored next vector
+  double H[KLD * KMAX];    // column-major Hessenberg, H[j*KLD + i] (final columns, and the tentative last one)
+  double htent[2 * KLD];   // tentative column j in htent[(j & 1) * KLD + i]
+  double sigma[KMAX + 2];  // final scale of each stored basis vector (v_i = sigma_i V_i)
+  double sig_t[KMAX + 2];  // tentative scale of slot j while it holds the once-orthogonalised vector
+  double nu_t[KMAX + 2];   // tentative norm estimate of slot j
+  double wn_t[KMAX + 2];   // |J q_{j-1}| (breakdown threshold of iteration j)
   double y[KMAX + 4];      // beta * phi_k(dt H) e_1
   double beta;
-  double wnorm;            // |J v_j| before orthogonalisation
   double hlast;
   double fd_eps;           // FD increment for a unit direction
   double eta;              // breakdown threshold
   double norm_tmp[4];
   int m_eff;
-  int done;
+  int done;                // nonzero once the run has stopped (read by later kernels)
+  int done_at;             // iteration at which it stopped (INT_MAX while running)
   int breakdown;
-  int pad;
   unsigned counter[8];
 };
 
@@ -59,15 +62,16 @@ size_t gs_blocks(size_t n);
 void k_init_state(KState* ks, double eta, hipStream_t st);
 template <typename TV>
 void k_start(const double* b, TV* V0, size_t n, KState* ks, double* part, hipStream_t st);
-// Iteration j, after the JVP has written W = J(sigma_j V_j) into slot j+1:
-// reduce (one pass over V_0..V_{j+1}), finalize (one block), update (one pass
-// rewriting V_j and V_{j+1}).  With close = true and j = m (after the last
-// iteration) reduce + finalize complete column m-1 of H.
+// Iteration j, after the JVP has written W = J(sig_t[j] V_j) into slot j+1:
+// reduce (one pass over V_0..V_{j+1}), then the fused pass that finalises the
+// iteration (every block recomputes the small algebra from the partials,
+// block 0 publishes it) and rewrites V_j and V_{j+1}.  After the last
+// iteration, reduce with close = true and k_gs_close complete column m-1 of H.
 template <typename TV>
 void k_gs_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, double* part, bool close, hipStream_t st);
-void k_gs_finalize(KState* ks, const double* part, int j, size_t n, bool close, hipStream_t st);
 template <typename TV>
-void k_gs_update(TV* V, size_t ld, int j, size_t n, const KState* ks, hipStream_t st);
+void k_gs_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st);
+void k_gs_close(KState* ks, const double* part, int m, size_t n, hipStream_t st);
 void k_hess_phi(KState* ks, const double* dt, int k, int m, double* scratch, hipStream_t st);
 template <typename TV, typename TX>
 void k_combine(const TV* V, size_t ld, const KState* ks, const double* base, double* out,

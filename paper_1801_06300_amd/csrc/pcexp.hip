@@ -271,19 +271,18 @@ void arnoldi_run(pcexp_ctx* c, int jvp, int prec, const double* u_lin, const flo
   }
   k_start<TV>(b, V, n, ks, part, st);
   for (int j = 0; j < m; ++j) {
-    jvp_int(c, jvp, prec, u_lin, u32, V + (size_t)j * ld, V + (size_t)(j + 1) * ld, &ks->sigma[j], &ks->done,
+    jvp_int(c, jvp, prec, u_lin, u32, V + (size_t)j * ld, V + (size_t)(j + 1) * ld, &ks->sig_t[j], &ks->done,
             Rlin, &ks->fd_eps, st);
     const double vb = (double)c->K * sizeof(TV);
-    // the reduction pass reads j + 2 vectors; the update pass reads j + 2 and writes 2
+    // the reduction pass reads j + 2 vectors; the finalise-and-update pass reads j + 2 and writes 2
     { Prof pr(c, st, PC_GSR, (j + 2.0) * vb); k_gs_reduce<TV>(V, ld, j, n, ks, part, false, st); }
-    { Prof pr(c, st, PC_GSF, 0.0); k_gs_finalize(ks, part, j, n, false, st); }
-    { Prof pr(c, st, PC_GSU, (j + 4.0) * vb); k_gs_update<TV>(V, ld, j, n, ks, st); }
+    { Prof pr(c, st, PC_GSU, (j + 4.0) * vb); k_gs_update<TV>(V, ld, j, n, ks, part, st); }
   }
   {
     Prof pr(c, st, PC_GSR, (m + 1.0) * (double)c->K * sizeof(TV));
     k_gs_reduce<TV>(V, ld, m, n, ks, part, true, st);
   }
-  { Prof pr(c, st, PC_GSF, 0.0); k_gs_finalize(ks, part, m, n, true, st); }
+  { Prof pr(c, st, PC_GSF, 0.0); k_gs_close(ks, part, m, n, st); }
   { Prof pr(c, st, PC_PHI, 0.0); k_hess_phi(ks, dtp, k, m, phi, st); }
 }
 
