@@ -100,6 +100,9 @@ typedef struct {
   double h_last;             /* h_{m_eff+1, m_eff} */
   int32_t m_eff;             /* Krylov dimension used (< m after breakdown; 0 if b = 0) */
   int32_t breakdown;         /* 1 if the Arnoldi process broke down */
+  double err_est;            /* a-posteriori relative error estimate (with a Krylov tolerance set) */
+  int32_t dt_halvings;       /* times dt was halved to meet the tolerance */
+  int32_t pad;
 } pcexp_krylov_info;
 
 typedef struct {
@@ -222,6 +225,16 @@ size_t pcexp_step_vjp_workspace_bytes(const pcexp_ctx* ctx, int32_t m);
 pcexp_status pcexp_step_vjp(pcexp_ctx* ctx, const double* u_n, double dt, int32_t m,
                             int32_t scheme, const double* ubar_np1, double* ubar_n, void* ws,
                             size_t ws_bytes, void* stream);
+
+/* Krylov tolerance for pcexp_step / pcexp_steady (0, the default, disables
+ * it).  With tol > 0 the predictor's phi_1 is evaluated together with phi_2
+ * and the a-posteriori estimate of the relative Krylov error (Saad 1992),
+ *   err(dt) = dt h_{m+1,m} |[phi_2(dt H_m) e_1]_m| / |phi_1(dt H_m) e_1|,
+ * and dt is halved on the device until err <= tol; the step (both stages)
+ * then uses that dt (reported in pcexp_step_info.dt).  The paper sets a
+ * Krylov convergence tolerance of 1e-5 (Sec. 5) without defining the
+ * control; this is one reading of it. */
+pcexp_status pcexp_set_krylov_tol(pcexp_ctx* ctx, double tol);
 
 /* Steady state by pseudo-time stepping (Sec. 5: PCEXP or EXP1 with the CFL
  * ramp of eq. (cfl), CFL(n) = min{CFL_max, max[||R(rho_n)||^-3, 1 + (n-1)/(2p+1)]},

@@ -94,3 +94,41 @@ def dense_phi(A, b, dt, k):
     for j in range(1, k):
         M[n + j - 1, n + j] = 1.0
     return expm(M)[:n, n + k - 1]
+
+
+def phi1_with_error(H, beta, h_next, dt):
+    """phi_1(dt H) e_1 and the a-posteriori relative error estimate of the
+    Krylov approximation of phi_1 (Saad 1992): the leading error term of
+    beta V phi_1(dt H) e_1 is beta dt h_{m+1,m} [phi_2(dt H) e_1]_m v_{m+1}, so
+    err = dt h_{m+1,m} |[phi_2(dt H) e_1]_m| / |phi_1(dt H) e_1|.
+    Both functions from the exponential of the augmented matrix with k = 2."""
+    m = H.shape[0]
+    M = np.zeros((m + 2, m + 2), dtype=H.dtype)
+    M[:m, :m] = dt * H
+    M[0, m] = 1.0
+    M[m, m + 1] = 1.0
+    E = expm(M)
+    p1 = E[:m, m]
+    p2 = E[:m, m + 1]
+    n1 = np.sqrt(np.sum(np.real(p1) ** 2))
+    err = float(dt * abs(np.real(h_next)) * abs(np.real(p2[m - 1])) / n1) if n1 > 0 else 0.0
+    return p1, err
+
+
+def arnoldi_phi1_controlled(matvec, b, dt, m, tol, eta=1e-12, max_halvings=40):
+    """dt * phi_1(dt J) b with dt halved until the error estimate is <= tol.
+    Returns (x, dt_used, err, halvings, info)."""
+    shape = np.shape(b)
+    V, H, beta, meff, brk = arnoldi_mgs(matvec, b, m, eta)
+    if meff == 0:
+        return np.zeros(shape), dt, 0.0, 0, dict(m_eff=0)
+    h_next = 0.0 if brk else H[meff, meff - 1]
+    halv = 0
+    while True:
+        y, err = phi1_with_error(H[:meff, :meff], beta, h_next, dt)
+        if err <= tol or halv >= max_halvings:
+            break
+        dt *= 0.5
+        halv += 1
+    x = dt * (beta * (V[:, :meff] @ y)).reshape(shape)
+    return x, dt, err, halv, dict(m_eff=meff, breakdown=brk)

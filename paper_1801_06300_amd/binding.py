@@ -39,10 +39,12 @@ class DiscDesc(ctypes.Structure):
 
 class KrylovInfo(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("h_last", ctypes.c_double), ("m_eff", ctypes.c_int32),
-                ("breakdown", ctypes.c_int32)]
+                ("breakdown", ctypes.c_int32), ("err_est", ctypes.c_double), ("dt_halvings", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
     def as_dict(self):
-        return dict(beta=self.beta, h_last=self.h_last, m_eff=self.m_eff, breakdown=bool(self.breakdown))
+        return dict(beta=self.beta, h_last=self.h_last, m_eff=self.m_eff, breakdown=bool(self.breakdown),
+                    err_est=self.err_est, dt_halvings=self.dt_halvings)
 
 
 class StepInfo(ctypes.Structure):
@@ -88,6 +90,7 @@ _SIGS = {
                                          ctypes.c_int32, ctypes.c_int32, _VP, _VP, ctypes.c_size_t,
                                          ctypes.POINTER(KrylovInfo), _VP]),
     "pcexp_profile": (ctypes.c_int, [_VP, ctypes.c_int32, c_double_p]),
+    "pcexp_set_krylov_tol": (ctypes.c_int, [_VP, ctypes.c_double]),
     "pcexp_steady": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
                                     ctypes.c_size_t, ctypes.POINTER(SteadyInfo), _VP]),
@@ -333,6 +336,10 @@ class PCEXP:
         self._check(self.lib.pcexp_profile(self.ctx, 2, out), "profile")
         return {name: (out[3 * i], int(out[3 * i + 1]), out[3 * i + 2])
                 for i, name in enumerate(self.PROFILE_CLASSES)}
+
+    def set_krylov_tol(self, tol):
+        """Predictor dt control by the Krylov error estimate (0 disables)."""
+        self._check(self.lib.pcexp_set_krylov_tol(self.ctx, float(tol)), "set_krylov_tol")
 
     def steady(self, u, cfl_max=1000.0, tol=1e-10, max_iter=500, check_every=10, m=30, scheme="pcexp",
                prec="f64", jvp="tangent"):

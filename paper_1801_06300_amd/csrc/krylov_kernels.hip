@@ -125,6 +125,7 @@ __global__ void init_state_kernel(KState* ks, double eta) {
   }
   for (int i = t; i < KMAX + 4; i += blockDim.x) ks->y[i] = 0.0;
   if (t < 8) ks->counter[t] = 0u;
+  if (t < 4) ks->norm_tmp[t] = 0.0;
   if (t == 0) {
     ks->beta = ks->hlast = ks->fd_eps = 0.0;
     ks->eta = eta;
@@ -691,6 +692,95 @@ __device__ void phi_body(KState* ks, const double* dtp, int k, double* mem) {
   const int col = (k >= 1) ? n - 1 : 0;
   const double beta = ks->beta;
   for (int i = tid; i < KMAX + 4; i += PHI_T) ks->y[i] = (i < m) ? beta * P[col * n + i] : 0.0;
+}
+
+// Step-size control by the a-posteriori error of the Krylov approximation of
+// phi_1 (Saad 1992): the leading error term of beta V_M phi_1(dt H_M) e_1 is
+// beta dt h_{M+1,M} [phi_2(dt H_M) e_1]_M v_{M+1}, so
+//   err(dt) = dt h_{M+1,M} |[phi_2(dt H_M) e_1]_M| / |phi_1(dt H_M) e_1|
+// estimates the relative error.  Both phi's come from one exponential of the
+// augmented matrix [[dt H, e_1, 0], [0, 0, 1], [0, 0, 0]] (size M + 2).  The
+// Krylov basis does not depend on dt, so dt is halved (here, on the device)
+// until err <= tol (at most 40 times); *dtp returns the accepted dt, y the
+// corresponding beta phi_1(dt H_M) e_1.  norm_tmp[2] = err, norm_tmp[3] =
+// number of halvings.
+__device__ void phi_adapt_body(KState* ks, double* dtp, double tol, double* mem) {
+  const int m = ks->m_eff;
+  const int tid = threadIdx.x;
+  __shared__ double red[PHI_T / 64];
+  __shared__ int accept;
+  if (m == 0) {
+    for (int i = tid; i < KMAX + 4; i += PHI_T) ks->y[i] = 0.0;
+    if (tid == 0) { ks->norm_tmp[2] = 0.0; ks->norm_tmp[3] = 0.0; }
+    return;
+  }
+  const int n = m + 2, nn = n * n;
+  const double hnext = ks->breakdown ? 0.0 : ks->hlast;
+  double dt = *dtp;
+  int halvings = 0;
+  double err = 0.0;
+  const double* P = nullptr;
+  for (;;) {
+    for (int t = tid; t < nn; t += PHI_T) {
+      const int i = t % n, jj = t / n;
+      double v = 0.0;
+      if (i < m && jj < m) {
+        if (i <= jj + 1) v = dt * ks->H[(size_t)jj * KLD + i];
+      } else if (jj == m && i == 0) {
+        v = 1.0;
+      } else if (jj == m + 1 && i == m) {
+        v = 1.0;
+      }
+      mem[t] = v;
+    }
+    __syncthreads();
+    P = expm_core(mem, n);
+    // |phi_1 e_1|^2 over rows < m
+    double sq = 0.0;
+    for (int i = tid; i < m; i += PHI_T) {
+      const double x = P[(size_t)m * n + i];
+      sq += x * x;
+    }
+    sq = wave_sum(sq);
+    if ((tid & 63) == 0) red[tid >> 6] = sq;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < PHI_T / 64; ++w) t += red[w];
+      const double phi2m = fabs(P[(size_t)(m + 1) * n + (m - 1)]);
+      err = t > 0.0 ? dt * hnext * phi2m / sqrt(t) : 0.0;
+      accept = (err <= tol || halvings >= 40) ? 1 : 0;
+      red[0] = err;
+    }
+    __syncthreads();
+    err = red[0];
+    if (accept) break;
+    dt *= 0.5;
+    ++halvings;
+    __syncthreads();
+  }
+  const double beta = ks->beta;
+  for (int i = tid; i < KMAX + 4; i += PHI_T) ks->y[i] = (i < m) ? beta * P[(size_t)m * n + i] : 0.0;
+  if (tid == 0) {
+    *dtp = dt;
+    ks->norm_tmp[2] = err;
+    ks->norm_tmp[3] = (double)halvings;
+  }
+}
+
+__global__ __launch_bounds__(PHI_T) void hess_phi_adapt_lds(KState* ks, double* dtp, double tol) {
+  extern __shared__ double smem[];
+  phi_adapt_body(ks, dtp, tol, smem);
+}
+__global__ __launch_bounds__(PHI_T) void hess_phi_adapt_glb(KState* ks, double* dtp, double tol, double* mem) {
+  phi_adapt_body(ks, dtp, tol, mem);
+}
+
+void k_hess_phi_adapt(KState* ks, double* dt, double tol, int m, double* scratch, hipStream_t st) {
+  const int n = m + 2;
+  const size_t bytes = (size_t)7 * n * n * sizeof(double);
+  if (bytes <= 60 * 1024) launch(hess_phi_adapt_lds, dim3(1), dim3(PHI_T), bytes, st, ks, dt, tol);
+  else launch(hess_phi_adapt_glb, dim3(1), dim3(PHI_T), 0, st, ks, dt, tol, scratch);
 }
 
 __global__ __launch_bounds__(PHI_T) void hess_phi_lds(KState* ks, const double* dtp, int k) {

@@ -73,6 +73,9 @@ template <typename TV>
 void k_gs_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st);
 void k_gs_close(KState* ks, const double* part, int m, size_t n, hipStream_t st);
 void k_hess_phi(KState* ks, const double* dt, int k, int m, double* scratch, hipStream_t st);
+// phi_1 with the Krylov error estimate: halves *dt on the device until the
+// estimated relative error is <= tol; scratch >= 7 (m+2)^2 doubles.
+void k_hess_phi_adapt(KState* ks, double* dt, double tol, int m, double* scratch, hipStream_t st);
 template <typename TV, typename TX>
 void k_combine(const TV* V, size_t ld, const KState* ks, const double* base, double* out,
                TX* xout, double fac, const double* dtp, size_t n, hipStream_t st);

@@ -48,6 +48,7 @@ struct pcexp_ctx {
   size_t Kld = 0;    // stride of Krylov vectors
   double gamma = 1.4, ff[5] = {0, 0, 0, 0, 0};
   double volume_total = 0.0;
+  double krylov_tol = 0.0;   // > 0: stage-1 dt control by the Krylov error estimate
   // tables and geometry
   double *B = nullptr, *Dg = nullptr, *wq = nullptr, *Bf = nullptr, *wf = nullptr, *nref = nullptr,
          *Bc = nullptr, *refp = nullptr;
@@ -242,7 +243,7 @@ WsLayout ws_layout(const pcexp_ctx* c, int m, int k, int prec) {
   L.ks1 = take(sizeof(KState));
   L.ks2 = take(sizeof(KState));
   L.part = take((size_t)3 * 512 * (KMAX + 2) * sizeof(double));
-  const size_t nphi = (size_t)(m + (k > 0 ? k : 0));
+  const size_t nphi = (size_t)(m + (k > 2 ? k : 2));   // k = 1 steps may use the (m+2) error-estimate matrix
   L.phi = take(7 * nphi * nphi * sizeof(double));
   L.scal = take(64 * sizeof(double));
   L.cnt = take(64 * sizeof(unsigned));
@@ -260,8 +261,8 @@ WsLayout ws_layout(const pcexp_ctx* c, int m, int k, int prec) {
 
 template <typename TV>
 void arnoldi_run(pcexp_ctx* c, int jvp, int prec, const double* u_lin, const float* u32, const double* b,
-                 const double* Rlin, const double* dtp, int k, int m, KState* ks, double* part, double* phi,
-                 TV* V, hipStream_t st) {
+                 const double* Rlin, double* dtp, int k, int m, KState* ks, double* part, double* phi,
+                 TV* V, hipStream_t st, double adapt_tol = 0.0) {
   const size_t n = c->Kint, ld = c->Kld;
   const double eta = (prec == PCEXP_PREC_MIXED) ? 1e-5 : 1e-12;
   k_init_state(ks, eta, st);
@@ -283,7 +284,11 @@ void arnoldi_run(pcexp_ctx* c, int jvp, int prec, const double* u_lin, const flo
     k_gs_reduce<TV>(V, ld, m, n, ks, part, true, st);
   }
   { Prof pr(c, st, PC_GSF, 0.0); k_gs_close(ks, part, m, n, st); }
-  { Prof pr(c, st, PC_PHI, 0.0); k_hess_phi(ks, dtp, k, m, phi, st); }
+  {
+    Prof pr(c, st, PC_PHI, 0.0);
+    if (adapt_tol > 0.0 && k == 1) k_hess_phi_adapt(ks, dtp, adapt_tol, m, phi, st);
+    else k_hess_phi(ks, dtp, k, m, phi, st);
+  }
 }
 
 // ---- reverse mode ----------------------------------------------------------
@@ -415,6 +420,8 @@ void fill_info(pcexp_krylov_info* out, const KState& h) {
   out->h_last = h.hlast;
   out->m_eff = h.m_eff;
   out->breakdown = h.breakdown;
+  out->err_est = h.norm_tmp[2];
+  out->dt_halvings = (int32_t)h.norm_tmp[3];
 }
 
 pcexp_status check_common(pcexp_ctx* c, int m, int k, int prec, int jvp, void* ws, size_t ws_bytes) {
@@ -804,12 +811,12 @@ pcexp_status step_core(pcexp_ctx* c, double* un, const DtMode& dm, int m, int sc
   double* out1 = exp1 ? un : us;
   if (mixed) {
     float* V = (float*)(w + L.V);
-    arnoldi_run<float>(c, jvp, prec, un, un32, Rn, Rn, dtp, 1, m, ks1, part, phi, V, st);
+    arnoldi_run<float>(c, jvp, prec, un, un32, Rn, Rn, dtp, 1, m, ks1, part, phi, V, st, c->krylov_tol);
     Prof pr(c, st, PC_COMB, (double)c->K * (m * 4.0 + 8 + 8 + 4));
     k_combine<float, float>(V, c->Kld, ks1, un, out1, exp1 ? (float*)nullptr : (float*)x1, 1.0, dtp, n, st);
   } else {
     double* V = (double*)(w + L.V);
-    arnoldi_run<double>(c, jvp, prec, un, nullptr, Rn, Rn, dtp, 1, m, ks1, part, phi, V, st);
+    arnoldi_run<double>(c, jvp, prec, un, nullptr, Rn, Rn, dtp, 1, m, ks1, part, phi, V, st, c->krylov_tol);
     Prof pr(c, st, PC_COMB, (double)c->K * (m * 8.0 + 8 + 8 + 8));
     k_combine<double, double>(V, c->Kld, ks1, un, out1, exp1 ? (double*)nullptr : (double*)x1, 1.0, dtp, n, st);
   }
@@ -856,6 +863,13 @@ pcexp_status check_step_args(pcexp_ctx* c, int m, int scheme, int prec, int jvp,
 }  // namespace
 
 extern "C" {
+
+pcexp_status pcexp_set_krylov_tol(pcexp_ctx* c, double tol) {
+  if (!c) return PCEXP_E_ARG;
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(c, PCEXP_E_ARG, "tol must be finite and >= 0");
+  c->krylov_tol = tol;
+  return PCEXP_OK;
+}
 
 pcexp_status pcexp_step(pcexp_ctx* c, double* u, double dt, double cfl, int32_t m, int32_t scheme, int32_t prec,
                         int32_t jvp, void* ws, size_t ws_bytes, pcexp_step_info* info, void* stream) {

@@ -54,3 +54,40 @@ def test_steady_converges_f64_and_mixed():
     ua, ub = a.cpu().numpy(), b.cpu().numpy()
     assert rel(ub, ua) < 1e-8
     assert res_rho_norm(g, g.residual(ua)) < 2e-10
+
+
+def test_step_krylov_dt_control_parity():
+    """pcexp_step with a Krylov tolerance: the device halves dt exactly as the
+    oracle does (same accepted dt, same state)."""
+    from paper_1801_06300_amd import PCEXP
+    from oracle.integrators import pcexp_step
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    m, ang = mesh_case("sq4j")
+    prim = W.freestream_prim(2, angle_deg=ang)
+    g = DG(m, 2, "roe", farfield_prim=prim)
+    ctx = PCEXP(m, 2, "roe", farfield_prim=prim)
+    u = vortex_state(g, m, 1e-3)
+    from oracle.integrators import stable_dt
+    dt = stable_dt(g, u, 200.0)
+    ctx.set_krylov_tol(1e-7)
+    ud = _t(u)
+    info = ctx.step(ud, dt=dt, m=12, info=True)
+    oinfo = {}
+    want = pcexp_step(ExactJacobian(g), u, dt, 12, info=oinfo, krylov_tol=1e-7)
+    print(f"[ctl] device dt {info['dt']:.6e} halvings {info['k1']['dt_halvings']} err {info['k1']['err_est']:.3e}; "
+          f"oracle dt {oinfo['k1']['dt']:.6e} halvings {oinfo['k1']['dt_halvings']}", flush=True)
+    assert info["k1"]["dt_halvings"] == oinfo["k1"]["dt_halvings"] > 0
+    assert abs(info["dt"] - oinfo["k1"]["dt"]) == 0.0
+    assert rel(ud.cpu().numpy(), want) < 1e-10
+    ctx.set_krylov_tol(0.0)
+
+
+def test_steady_with_krylov_control_parity():
+    g, ctx, u = _setup(2)
+    ctx.set_krylov_tol(1e-5)
+    ud = _t(u)
+    ctx.steady(ud, cfl_max=1000.0, tol=0.0, max_iter=4, check_every=1, m=30)
+    want, hist = steady_iterations(g, ExactJacobian(g), u, 4, 1000.0, 30, krylov_tol=1e-5)
+    ctx.set_krylov_tol(0.0)
+    assert rel(ud.cpu().numpy(), want) < 1e-9

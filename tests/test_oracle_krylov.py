@@ -233,3 +233,41 @@ def test_dt_and_cfl_ramp():
     assert abs(cfl_ramp(5, 0.5, 2, 1000.0) - 8.0) < 1e-12
     R = g.residual(u + W.perturbation(u.shape, 1, 1e-3))
     assert abs(res_rho_norm(g, R) - np.sqrt(np.sum(R[:, 0, :] ** 2)) / 100.0) < 1e-15
+
+
+def test_krylov_error_estimate_tracks_true_error():
+    """The a-posteriori estimate dt h_{m+1,m} |[phi_2(dt H) e_1]_m| / |phi_1(dt H) e_1|
+    against the true relative error of the Krylov phi_1 (dense phi_1 from
+    scipy.linalg.expm of the augmented matrix of the full operator)."""
+    from scipy.linalg import expm
+    rng = np.random.default_rng(12)
+    n = 80
+    A = rng.standard_normal((n, n)) / np.sqrt(n) - 1.5 * np.eye(n)
+    b = rng.standard_normal(n)
+    M = np.zeros((n + 1, n + 1))
+    for dt in (0.5, 1.0, 2.0):
+        M[:n, :n] = dt * A
+        M[:n, n] = b
+        exact = expm(M)[:n, n]          # phi_1(dt A) b
+        for m in (6, 10, 14):
+            V, H, beta, meff, brk = krylov.arnoldi_mgs(lambda v: A @ v, b, m)
+            y, est = krylov.phi1_with_error(H[:meff, :meff], beta, H[meff, meff - 1], dt)
+            approx = beta * V[:, :meff] @ y
+            true = np.linalg.norm(approx - exact) / np.linalg.norm(exact)
+            if 1e-13 < true < 1e-2:
+                assert 0.1 < est / true < 10.0, (dt, m, est, true)
+
+
+def test_krylov_dt_control_meets_tolerance():
+    from scipy.linalg import expm
+    rng = np.random.default_rng(13)
+    n = 80
+    A = rng.standard_normal((n, n)) / np.sqrt(n) * 3 - 2.0 * np.eye(n)
+    b = rng.standard_normal(n)
+    x, dt, err, halv, info = krylov.arnoldi_phi1_controlled(lambda v: A @ v, b, 8.0, 8, 1e-6)
+    assert halv > 0 and dt == 8.0 / 2 ** halv and err <= 1e-6
+    M = np.zeros((n + 1, n + 1))
+    M[:n, :n] = dt * A
+    M[:n, n] = b
+    exact = dt * expm(M)[:n, n]
+    assert np.linalg.norm(x - exact) / np.linalg.norm(exact) < 1e-5
