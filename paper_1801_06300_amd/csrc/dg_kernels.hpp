@@ -103,6 +103,15 @@ struct Tile {
     return best;
   }
   static constexpr int TE = pick();
+  // Outputs per thread in the contractions: the smallest divisor NI of NB
+  // with NV * (NB / NI) * TE <= NT (one round); each thread then reuses every
+  // flux value it reads from LDS for NI basis functions.
+  static constexpr int pick_ni() {
+    for (int ni = 1; ni <= Sh::NB; ++ni)
+      if (Sh::NB % ni == 0 && Sh::NV * (Sh::NB / ni) * TE <= NT) return ni;
+    return Sh::NB;
+  }
+  static constexpr int NI = pick_ni();
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
@@ -132,7 +141,10 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   constexpr bool DUAL = (MODE == MODE_TAN);
   using Tl = Tile<D, P, T, DUAL>;
   using S = typename std::conditional<DUAL, Dual<T, 1>, T>::type;
-  constexpr int NOUT = (NVB * TE + NT - 1) / NT;
+  // output items (k, g, e): basis functions i = g + NG c, c < NI
+  constexpr int NI = Tl::NI, NG = NB / NI;
+  constexpr int NITEM = NV * NG * TE;
+  constexpr int NOUT = (NITEM + NT - 1) / NT;
 
   if (io.skip && *io.skip) return;
   __shared__ T su[NVB * TE];
@@ -185,9 +197,11 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   }
   __syncthreads();
 
-  T acc[NOUT];
+  T acc[NOUT][NI];
 #pragma unroll
-  for (int o = 0; o < NOUT; ++o) acc[o] = T(0);
+  for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+    for (int c = 0; c < NI; ++c) acc[o][c] = T(0);
 
   // ---- volume: pointwise flux contracted with the rows of A^{-1}
   for (int t = tid; t < NQ * TE; t += NT) {
@@ -238,14 +252,16 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
     const int t = tid + o * NT;
-    if (t < NVB * TE) {
-      const int ki = t / TE, e = t % TE, k = ki / NB, i = ki % NB;
-      T s = T(0);
+    if (t < NITEM) {
+      const int kg = t / TE, e = t % TE, k = kg / NG, g = kg % NG;
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
 #pragma unroll
-        for (int r = 0; r < D; ++r) s += sw[((q * NV + k) * D + r) * TE + e] * tDg[(q * NB + i) * D + r];
-      acc[o] += s;
+        for (int r = 0; r < D; ++r) {
+          const T fv = sw[((q * NV + k) * D + r) * TE + e];
+#pragma unroll
+          for (int c = 0; c < NI; ++c) acc[o][c] += fv * tDg[(q * NB + g + NG * c) * D + r];
+        }
     }
   }
   __syncthreads();
@@ -330,17 +346,19 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
     const int t = tid + o * NT;
-    if (t < NVB * TE) {
-      const int ki = t / TE, e = t % TE, k = ki / NB, i = ki % NB;
+    if (t < NITEM) {
+      const int kg = t / TE, e = t % TE, k = kg / NG, g = kg % NG;
       if (e0 + e < nE) {
-        T s = T(0);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
           const T* bl = tBf + (f * NORI + sori[f * TE + e]) * NFQ * NB;
 #pragma unroll
-          for (int r = 0; r < NFQ; ++r) s += sw[((f * NFQ + r) * NV + k) * TE + e] * bl[r * NB + i];
+          for (int r = 0; r < NFQ; ++r) {
+            const T fv = sw[((f * NFQ + r) * NV + k) * TE + e];
+#pragma unroll
+            for (int c = 0; c < NI; ++c) acc[o][c] -= fv * bl[r * NB + g + NG * c];
+          }
         }
-        acc[o] -= s;
       }
     }
   }
@@ -349,12 +367,16 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
     const int t = tid + o * NT;
-    if (t < NVB * TE) {
-      const int ki = t / TE, e = t % TE, ge = e0 + e;
+    if (t < NITEM) {
+      const int kg = t / TE, e = t % TE, k = kg / NG, g = kg % NG, ge = e0 + e;
       if (ge < Epad) {
-        T v = ge < nE ? acc[o] : T(0);
-        if (MODE == MODE_FD && ge < nE) v = (v - io.rbase[(size_t)ki * Epad + ge]) / eps;
-        io.out[(size_t)ki * Epad + ge] = v;
+#pragma unroll
+        for (int c = 0; c < NI; ++c) {
+          const int ki = k * NB + g + NG * c;
+          T v = ge < nE ? acc[o][c] : T(0);
+          if (MODE == MODE_FD && ge < nE) v = (v - io.rbase[(size_t)ki * Epad + ge]) / eps;
+          io.out[(size_t)ki * Epad + ge] = v;
+        }
       }
     }
   }
