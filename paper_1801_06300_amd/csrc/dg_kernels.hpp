@@ -82,7 +82,8 @@ template <int D, int P, typename T, bool DUAL>
 struct Tile {
   using Sh = Shape<D, P>;
   static constexpr int NG = Sh::NQ * Sh::NV * D;
-  static constexpr int NFL = Sh::NF * Sh::NFQ * Sh::NV;
+  static constexpr int FS = Sh::NV * (DUAL ? 2 : 1);   // LDS words per face point (neighbour trace)
+  static constexpr int NFL = Sh::NF * Sh::NFQ * FS;
   static constexpr int NW = NG > NFL ? NG : NFL;
   static constexpr int per_elem = (int)sizeof(T) * (Sh::NVB * (DUAL ? 2 : 1) + NW) + Sh::NF;
   // reference tables B, Dg, Bf, wq, wf, nref; staged in LDS when small
@@ -266,6 +267,46 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   }
   __syncthreads();
 
+  // ---- neighbour traces: thread (k, e) gathers the neighbour's coefficients
+  // of variable k once per face and evaluates them at all NFQ points (the
+  // face threads below then read them from LDS)
+  constexpr int FS = Tl::FS;
+  for (int t = tid; t < NV * TE; t += NT) {
+    const int k = t / TE, e = t % TE, ge = e0 + e;
+    if (ge >= nE) continue;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int nb = prm.nbr[(size_t)f * Epad + ge];
+      if (nb < 0) continue;
+      const int info = prm.finfo[(size_t)f * Epad + ge];
+      const int fN = info & 3, oN = (info >> 2) & 7;
+      const T rsn = T(1) / prm.sdet[nb];
+      T cu[NB], cv[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        T uu = io.u[(size_t)(k * NB + i) * Epad + nb];
+        T vv = T(0);
+        if (MODE != MODE_RES) vv = io.v[(size_t)(k * NB + i) * Epad + nb] * scale;
+        if (MODE == MODE_FD) uu = uu + eps * vv;
+        cu[i] = uu;
+        cv[i] = vv;
+      }
+#pragma unroll
+      for (int r = 0; r < NFQ; ++r) {
+        const T* br = tBf + ((fN * NORI + oN) * NFQ + r) * NB;
+        T a = T(0), b = T(0);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          a += cu[i] * br[i];
+          if (DUAL) b += cv[i] * br[i];
+        }
+        sw[((f * NFQ + r) * FS + k) * TE + e] = a * rsn;
+        if (DUAL) sw[((f * NFQ + r) * FS + NV + k) * TE + e] = b * rsn;
+      }
+    }
+  }
+  __syncthreads();
+
   // ---- faces: traces, numerical flux (each face computed by both sides)
   for (int t = tid; t < NF * NFQ * TE; t += NT) {
     const int fr = t / TE, e = t % TE, f = fr / NFQ, r = fr % NFQ, ge = e0 + e;
@@ -309,26 +350,13 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
 #pragma unroll
     for (int c = 0; c < D; ++c) n[c] = nl[c] / len;
     if (nb >= 0) {
-      const int fN = info & 3, oN = (info >> 2) & 7;
-      const T* br = tBf + ((fN * NORI + oN) * NFQ + r) * NB;
-      const T rsn = T(1) / prm.sdet[nb];
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
-        T a = T(0), b = T(0);
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-          T uu = io.u[(size_t)(k * NB + i) * Epad + nb];
-          T vv = T(0);
-          if (MODE != MODE_RES) vv = io.v[(size_t)(k * NB + i) * Epad + nb] * scale;
-          if (MODE == MODE_FD) uu = uu + eps * vv;
-          a += uu * br[i];
-          if (DUAL) b += vv * br[i];
-        }
         if constexpr (DUAL) {
-          UR[k].v = a * rsn;
-          UR[k].d[0] = b * rsn;
+          UR[k].v = sw[((f * NFQ + r) * FS + k) * TE + e];
+          UR[k].d[0] = sw[((f * NFQ + r) * FS + NV + k) * TE + e];
         } else {
-          UR[k] = a * rsn;
+          UR[k] = sw[((f * NFQ + r) * FS + k) * TE + e];
         }
       }
     } else if (((info >> 8) & 3) == 1) {
@@ -340,7 +368,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     num_flux<D, FLUX>(UL, UR, n, prm.gamma, F);
     const T wgt = twf[r] * len * rs;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) sw[((f * NFQ + r) * NV + k) * TE + e] = wgt * Part<S>::get(F[k]);
+    for (int k = 0; k < NV; ++k) sw[((f * NFQ + r) * FS + k) * TE + e] = wgt * Part<S>::get(F[k]);
   }
   __syncthreads();
 #pragma unroll
@@ -354,7 +382,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
           const T* bl = tBf + (f * NORI + sori[f * TE + e]) * NFQ * NB;
 #pragma unroll
           for (int r = 0; r < NFQ; ++r) {
-            const T fv = sw[((f * NFQ + r) * NV + k) * TE + e];
+            const T fv = sw[((f * NFQ + r) * FS + k) * TE + e];
 #pragma unroll
             for (int c = 0; c < NI; ++c) acc[o][c] -= fv * bl[r * NB + g + NG * c];
           }
