@@ -75,19 +75,36 @@ __device__ __forceinline__ double col_sum(const double* part, int c, int nblk) {
   return wave_sum(a);
 }
 
-// Fixed-order sums of columns [0, ncol) into col[] by a whole RT-thread
-// block: 8 lanes per column, all loads of a lane independent.
+// Fixed-order sums of columns [0, ncol) of part into col[] by a whole
+// RT-thread block: 8 lanes per column, lane `sub` summing partials sub,
+// sub + 8, ... in ascending order, then a butterfly over the 8 lanes.  The
+// loads of one round (64 columns) are split from the adds so that a caller
+// can issue them together with its other loads.  They are unconditional --
+// column clamped to ncol - 1, slot < MAXB <= PLD, inside every partial
+// buffer -- and slots at or past nblk are dropped by a select at the sum.
+constexpr int CS_PER = MAXB / 8;
+constexpr int CS_COLS = RT / 8;
+__device__ __forceinline__ void col_sums_load(const double* part, int c0, int ncol, double (&x)[CS_PER]) {
+  const int c = c0 + (threadIdx.x >> 3), sub = threadIdx.x & 7;
+  const int cc = c < ncol ? c : ncol - 1;
+#pragma unroll
+  for (int r = 0; r < CS_PER; ++r) x[r] = part[(size_t)cc * PLD + sub + 8 * r];
+}
+__device__ __forceinline__ void col_sums_finish(const double (&x)[CS_PER], int c0, int ncol, int nblk, double* col) {
+  const int c = c0 + (threadIdx.x >> 3), sub = threadIdx.x & 7;
+  double a = 0.0;
+#pragma unroll
+  for (int r = 0; r < CS_PER; ++r) a += (sub + 8 * r < nblk) ? x[r] : 0.0;
+  a += __shfl_xor(a, 4, 64);
+  a += __shfl_xor(a, 2, 64);
+  a += __shfl_xor(a, 1, 64);
+  if (c < ncol && sub == 0) col[c] = a;
+}
 __device__ __forceinline__ void block_col_sums(const double* part, int ncol, int nblk, double* col) {
-  const int g = threadIdx.x >> 3, sub = threadIdx.x & 7;
-  for (int c0 = 0; c0 < ncol; c0 += RT / 8) {
-    const int c = c0 + g;
-    double a = 0.0;
-    if (c < ncol)
-      for (int b = sub; b < nblk; b += 8) a += part[(size_t)c * PLD + b];
-    a += __shfl_xor(a, 4, 64);
-    a += __shfl_xor(a, 2, 64);
-    a += __shfl_xor(a, 1, 64);
-    if (c < ncol && sub == 0) col[c] = a;
+  for (int c0 = 0; c0 < ncol; c0 += CS_COLS) {
+    double x[CS_PER];
+    col_sums_load(part, c0, ncol, x);
+    col_sums_finish(x, c0, ncol, nblk, col);
   }
 }
 
@@ -241,6 +258,19 @@ __device__ __forceinline__ void load_pw(const TV* base, size_t p, size_t n, doub
   if (PW == 2) load_pair(base, p, n, x[0], x[1]);
   else x[0] = (double)base[p];
 }
+// Unmasked variant for passes that write back what they read: past the end
+// of the vector the second entry holds whatever the slot's padding holds,
+// and store_pair never writes it.
+template <typename TV, int PW>
+__device__ __forceinline__ void load_pw_raw(const TV* base, size_t p, double* x) {
+  if (PW == 2) {
+    const typename Pair<TV>::type v = reinterpret_cast<const typename Pair<TV>::type*>(base)[p];
+    x[0] = (double)v.x;
+    x[1] = (double)v.y;
+  } else {
+    x[0] = (double)base[p];
+  }
+}
 
 template <typename TV, int NV, int PW, bool CLOSE>
 __global__ __launch_bounds__(RT) void dcgs_reduce(const TV* __restrict__ V, size_t ld, int j, size_t n,
@@ -330,34 +360,103 @@ __global__ __launch_bounds__(RT) void dcgs_fin_update(TV* __restrict__ V, size_t
   const int nq = j;
   const bool writer = blockIdx.x == 0;
   __shared__ double col[2 * KMAX + 3];
-  __shared__ double s[KMAX], z[KMAX];
+  __shared__ double s[KMAX], z[KMAX], g[KMAX], hc[KMAX];
   __shared__ double Hs[KMAX * KMAX];   // H[l][i], l, i < nq; column nq-1 tentative
   __shared__ double e[NV], b[NV];
   __shared__ double sa, sir;
   __shared__ int go;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  block_col_sums(part, 2 * nq + 3, nblk, col);
+  TV* U = V + (size_t)j * ld;
+  TV* W = V + (size_t)(j + 1) * ld;
+  const size_t np = PW == 2 ? (n + 1) / 2 : n;
+
+  // Every global load the small algebra needs is issued first (partials,
+  // H, the scales), then the loads of the first entries this thread will
+  // update, so that their HBM latency overlaps the algebra: vector loads
+  // complete in issue order, and waiting for the first group does not wait
+  // for the second.
+  constexpr bool ONE_ROUND = 2 * NV + 3 <= CS_COLS;
+  constexpr bool PREFETCH = ONE_ROUND && CV == NV;
+  constexpr int HQ = (NV * NV + RT - 1) / RT;
   const double* Ht = ks->htent + (size_t)((j + 1) & 1) * KLD;
-  for (int t = tid; t < nq * nq; t += RT) {
-    const int i = t / nq, l = t % nq;            // column i, row l
-    Hs[l * KMAX + i] = (i == nq - 1) ? Ht[l] : ks->H[(size_t)i * KLD + l];
+  // (addresses are selected, not the loads, so no load sits under a branch)
+  double hq[HQ];
+#pragma unroll
+  for (int q = 0; q < HQ; ++q) {
+    const int t = tid + q * RT;
+    const int i = t / (nq > 0 ? nq : 1), l = t - i * nq;   // column i, row l
+    const double* src = t >= nq * nq ? ks->H : (i == nq - 1) ? Ht + l : ks->H + (size_t)i * KLD + l;
+    hq[q] = *src;
+  }
+  const double sgv = ks->sigma[tid < nq ? tid : 0];   // used by threads tid < nq only
+  const double sj = ks->sig_t[j];
+  const double nu = ks->nu_t[j];
+  const double wnj = ks->wn_t[j];
+  const double eta = ks->eta;
+  double px[CS_PER];
+  if (ONE_ROUND) col_sums_load(part, 0, 2 * nq + 3, px);
+
+  // Loaded unconditionally (index clamped into the vector, n >= 1): a load
+  // under a branch would make the wait for the partials wait for it as well.
+  const size_t p0 = (size_t)blockIdx.x * RT + threadIdx.x;
+  const size_t pc = p0 < np ? p0 : np - 1;
+  double pv[PREFETCH ? NV : 1][PW], pu[PW], pw[PW];
+  if (PREFETCH) {
+    load_pw_raw<TV, PW>(U, pc, pu);
+    load_pw_raw<TV, PW>(W, pc, pw);
+#pragma unroll
+    for (int i = 0; i < (PREFETCH ? NV : 1); ++i) load_pw_raw<TV, PW>(V + (size_t)clampv(i, nq) * ld, pc, pv[i]);
+  }
+  __builtin_amdgcn_sched_barrier(0);   // keep both groups of loads ahead of the first use
+
+  if (ONE_ROUND) col_sums_finish(px, 0, 2 * nq + 3, nblk, col);
+  else block_col_sums(part, 2 * nq + 3, nblk, col);
+#pragma unroll
+  for (int q = 0; q < HQ; ++q) {
+    const int t = tid + q * RT;
+    const int i = t / (nq > 0 ? nq : 1), l = t - i * nq;
+    if (t < nq * nq) Hs[l * KMAX + i] = hq[q];
   }
   for (int i = nq + tid; i < NV; i += RT) {
     e[i] = 0.0;
     b[i] = 0.0;
   }
   __syncthreads();
-  if (wid == 0) {   // the O(j^2) algebra on one wave, lane l <-> row l
+  // s = Q^T u and z = Q^T W (scaled), the corrected column j-1 of H
+  if (tid < nq) {
+    const int l = tid;
+    const double sl = sgv * sj * col[l];
+    s[l] = sl;
+    z[l] = sgv * col[nq + l];
+    hc[l] = Hs[l * KMAX + (nq - 1)] + nu * sl;
+  }
+  __syncthreads();
+  // g = H_{0:nq, 0:nq} s with the corrected last column (J Q s), 8 lanes per row
+  {
+    const int l = tid >> 3, sub = tid & 7;
+    for (int l0 = 0; l0 < nq; l0 += RT / 8) {
+      const int row = l0 + l;
+      double a = 0.0;
+      if (row < nq) {
+        for (int i = (row > 0 ? row - 1 : 0) + sub; i < nq - 1; i += 8) a += Hs[row * KMAX + i] * s[i];
+        if (sub == 0) a += hc[row] * s[nq - 1];
+      }
+      a += __shfl_xor(a, 4, 64);
+      a += __shfl_xor(a, 2, 64);
+      a += __shfl_xor(a, 1, 64);
+      if (row < nq && sub == 0) g[row] = a;
+    }
+  }
+  __syncthreads();
+  if (wid == 0) {   // scalar reductions and the coefficients, lane l <-> row l
     double* H = ks->H;
-    const double eta = ks->eta;
-    const double sj = ks->sig_t[j];
-    const double nu = ks->nu_t[j];
     const bool live = lane < nq;
-    const double sgl = live ? ks->sigma[lane] : 0.0;
-    const double sl = live ? sgl * sj * col[lane] : 0.0;
-    const double zl = live ? sgl * col[nq + lane] : 0.0;
-    if (live) { s[lane] = sl; z[lane] = zl; }
+    const double sl = live ? s[lane] : 0.0;
+    const double zl = live ? z[lane] : 0.0;
+    const double gl = live ? g[lane] : 0.0;
+    const double sgl = sgv;   // lane == tid in wave 0
     const double ss = wave_sum(sl * sl);
+    const double gz = wave_sum(gl * zl), gg = wave_sum(gl * gl), sz = wave_sum(sl * zl);
     const double alpha = sj * sj * col[2 * nq];
     const double zeta = sj * col[2 * nq + 1];
     const double omega = col[2 * nq + 2];
@@ -367,35 +466,24 @@ __global__ __launch_bounds__(RT) void dcgs_fin_update(TV* __restrict__ V, size_t
       const double r2 = alpha - ss;
       rho = r2 > 0.0 ? sqrt(r2) : 0.0;
       const double hjj1 = nu * rho;
-      stop = !(hjj1 > eta * ks->wn_t[j]);   // v_j lies in the span: stop with m_eff = j
-      if (writer && lane == 0) {
-        H[(size_t)(j - 1) * KLD + j] = hjj1;
-        ks->hlast = hjj1;
-        if (stop) {
-          ks->breakdown = 1;
-          ks->done = 1;
-          ks->done_at = j;
-          ks->m_eff = j;
+      stop = !(hjj1 > eta * wnj);   // v_j lies in the span: stop with m_eff = j
+      if (writer) {
+        if (live) H[(size_t)(j - 1) * KLD + lane] = hc[lane];
+        if (lane == 0) {
+          H[(size_t)(j - 1) * KLD + j] = hjj1;
+          ks->hlast = hjj1;
+          if (stop) {
+            ks->breakdown = 1;
+            ks->done = 1;
+            ks->done_at = j;
+            ks->m_eff = j;
+          }
         }
       }
     }
-    // finish column j-1 (each lane keeps its own corrected entry)
-    double hcol_new = 0.0;
-    if (j > 0 && live) {
-      hcol_new = Hs[lane * KMAX + (j - 1)] + nu * sl;
-      if (writer) H[(size_t)(j - 1) * KLD + lane] = hcol_new;
-    }
-    __builtin_amdgcn_wave_barrier();
     if (stop) {
       if (lane == 0) go = 0;
     } else {
-      // J Q s from the finished columns: g_l = sum_i H[l][i] s_i, c = h_{j,j-1} s_{j-1}
-      double gl = 0.0;
-      if (live) {
-        for (int i = (lane > 0 ? lane - 1 : 0); i < nq - 1; ++i) gl += Hs[lane * KMAX + i] * s[i];
-        gl += hcol_new * s[nq - 1];
-      }
-      const double gz = wave_sum(gl * zl), gg = wave_sum(gl * gl), sz = wave_sum(sl * zl);
       const double c = (j > 0) ? nu * rho * s[j - 1] : 0.0;
       const double ir = 1.0 / rho;
       const double qW = (zeta - sz) * ir;
@@ -447,13 +535,35 @@ __global__ __launch_bounds__(RT) void dcgs_fin_update(TV* __restrict__ V, size_t
   __syncthreads();
   if (!go) return;
   const double a = sa, ir = sir;
-  TV* U = V + (size_t)j * ld;
-  TV* W = V + (size_t)(j + 1) * ld;
-  const size_t np = PW == 2 ? (n + 1) / 2 : n;
-  for (size_t p = (size_t)blockIdx.x * RT + threadIdx.x; p < np; p += (size_t)gridDim.x * RT) {
+  const size_t stride = (size_t)gridDim.x * RT;
+  if (PREFETCH && p0 < np) {   // the first point, from the registers loaded before the algebra
+    double un[PW], wn[PW];
+#pragma unroll
+    for (int k = 0; k < PW; ++k) {
+      un[k] = pu[k];
+      wn[k] = pw[k] * ir - a * pu[k];
+    }
+#pragma unroll
+    for (int i = 0; i < (PREFETCH ? NV : 1); ++i) {
+      const double ei = e[i], bi = b[i];
+#pragma unroll
+      for (int k = 0; k < PW; ++k) {
+        un[k] -= ei * pv[i][k];
+        wn[k] -= bi * pv[i][k];
+      }
+    }
+    if (PW == 2) {
+      store_pair(U, p0, n, un[0], un[1]);
+      store_pair(W, p0, n, wn[0], wn[1]);
+    } else {
+      U[p0] = (TV)un[0];
+      W[p0] = (TV)wn[0];
+    }
+  }
+  for (size_t p = p0 + (PREFETCH ? stride : 0); p < np; p += stride) {
     double u[PW], w[PW], un[PW], wn[PW];
-    load_pw<TV, PW>(U, p, n, u);
-    load_pw<TV, PW>(W, p, n, w);
+    load_pw_raw<TV, PW>(U, p, u);
+    load_pw_raw<TV, PW>(W, p, w);
 #pragma unroll
     for (int k = 0; k < PW; ++k) {
       un[k] = u[k];
@@ -464,7 +574,7 @@ __global__ __launch_bounds__(RT) void dcgs_fin_update(TV* __restrict__ V, size_t
       if (CV < NV && c0 >= nq) break;
       double v[CV][PW];
 #pragma unroll
-      for (int i = 0; i < CV; ++i) load_pw<TV, PW>(V + (size_t)clampv(c0 + i, nq) * ld, p, n, v[i]);
+      for (int i = 0; i < CV; ++i) load_pw_raw<TV, PW>(V + (size_t)clampv(c0 + i, nq) * ld, p, v[i]);
 #pragma unroll
       for (int i = 0; i < CV; ++i) {
         const double ei = e[c0 + i], bi = b[c0 + i];
