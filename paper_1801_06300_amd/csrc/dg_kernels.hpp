@@ -147,54 +147,114 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   constexpr int NITEM = NV * NG * TE;
   constexpr int NOUT = (NITEM + NT - 1) / NT;
 
-  if (io.skip && *io.skip) return;
   __shared__ T su[NVB * TE];
   __shared__ T sv[DUAL ? NVB * TE : 1];
   __shared__ T sw[Tl::NW * TE];
   __shared__ unsigned char sori[NF * TE];
   __shared__ T stab[Tl::STAGE_TAB ? Tl::NTAB : 1];
-
-  // reference tables: every lane reads them, so keep them in LDS when small
-  constexpr int oDg = NQ * NB, oBf = oDg + NQ * NB * D, owq = oBf + NF * NORI * NFQ * NB, owf = owq + NQ,
-                onr = owf + NFQ;
-  const T *tB, *tDg, *tBf, *twq, *twf, *tnref;
-  if constexpr (Tl::STAGE_TAB) {
-    for (int t = threadIdx.x; t < Tl::NTAB; t += NT) {
-      T x;
-      if (t < oDg) x = prm.B[t];
-      else if (t < oBf) x = prm.Dg[t - oDg];
-      else if (t < owq) x = prm.Bf[t - oBf];
-      else if (t < owf) x = prm.wq[t - owq];
-      else if (t < onr) x = prm.wf[t - owf];
-      else x = prm.nref[t - onr];
-      stab[t] = x;
-    }
-    tB = stab; tDg = stab + oDg; tBf = stab + oBf; twq = stab + owq; twf = stab + owf; tnref = stab + onr;
-  } else {
-    tB = prm.B; tDg = prm.Dg; tBf = prm.Bf; twq = prm.wq; twf = prm.wf; tnref = prm.nref;
-  }
+  // sw holds, in turn, the weighted volume fluxes (k, r, q, e) and the face
+  // values (c, f, r, e), with the pointwise index (q or face point) next to
+  // e: the threads of a pointwise phase, t = q * TE + e, then touch
+  // consecutive words and the LDS banks without conflicts.
+  constexpr int NFP = NF * NFQ;
+  auto vix = [](int q, int k, int r, int e) { return ((k * D + r) * NQ + q) * TE + e; };
+  auto fix = [](int c, int fp, int e) { return (c * NFP + fp) * TE + e; };
 
   const int Epad = prm.Epad, nE = prm.nE;
   const int e0 = xcd_tile(blockIdx.x, gridDim.x) * TE;
   const int tid = threadIdx.x;
   const T gm1 = prm.gamma - T(1);
 
+  // Every global load the block needs before its first barrier is issued up
+  // front, from clamped addresses and outside branches, so that the block
+  // waits for one memory round trip: the skip flag and scales, the reference
+  // tables, the tile's coefficients and, when each pointwise phase is a
+  // single round (thread tid then works on element e0 + tid % TE in all of
+  // them), that element's geometry.
+  const bool skipped = io.skip ? (*io.skip != 0) : false;
   T scale = T(1);
   if (MODE != MODE_RES && io.vscale) scale = (T)(*io.vscale);
   T eps = T(0);
   if (MODE == MODE_FD) eps = (T)(*io.fd_eps);
 
-  // ---- stage the tile's coefficients (u, and the direction v for the tangent)
-  for (int t = tid; t < NVB * TE; t += NT) {
-    const int ki = t / TE, e = t % TE, ge = e0 + e;
-    T uu = T(0), vv = T(0);
-    if (ge < nE) {
-      uu = io.u[(size_t)ki * Epad + ge];
-      if (MODE != MODE_RES) vv = io.v[(size_t)ki * Epad + ge] * scale;
+  // reference tables: every lane reads them, so keep them in LDS when small
+  constexpr int oDg = NQ * NB, oBf = oDg + NQ * NB * D, owq = oBf + NF * NORI * NFQ * NB, owf = owq + NQ,
+                onr = owf + NFQ;
+  constexpr int NTR = Tl::STAGE_TAB ? (Tl::NTAB + NT - 1) / NT : 1;
+  T xt[NTR];
+  if constexpr (Tl::STAGE_TAB) {
+#pragma unroll
+    for (int s = 0; s < NTR; ++s) {
+      int t = tid + s * NT;
+      t = t < Tl::NTAB ? t : Tl::NTAB - 1;
+      const T* src = t < oDg   ? prm.B + t
+                     : t < oBf ? prm.Dg + (t - oDg)
+                     : t < owq ? prm.Bf + (t - oBf)
+                     : t < owf ? prm.wq + (t - owq)
+                     : t < onr ? prm.wf + (t - owf)
+                               : prm.nref + (t - onr);
+      xt[s] = *src;
     }
-    if (MODE == MODE_FD) uu = uu + eps * vv;
-    su[t] = uu;
-    if (DUAL) sv[t] = vv;
+  }
+  constexpr int NSTG = (NVB * TE + NT - 1) / NT;
+  T ru[NSTG], rv[NSTG];
+#pragma unroll
+  for (int s = 0; s < NSTG; ++s) {
+    const int t = tid + s * NT;
+    const int tc = t < NVB * TE ? t : NVB * TE - 1;
+    const int ki = tc / TE, ge = e0 + tc % TE;
+    const int gc = ge < nE ? ge : nE - 1;
+    ru[s] = io.u[(size_t)ki * Epad + gc];
+    if constexpr (MODE != MODE_RES) rv[s] = io.v[(size_t)ki * Epad + gc];
+    else rv[s] = T(0);
+  }
+  struct Geo {
+    T sdet;
+    T ainv[D * D];
+    int nbr[NF], info[NF];
+  };
+  auto load_geo = [&](int ge) {
+    Geo g;
+    g.sdet = prm.sdet[ge];
+#pragma unroll
+    for (int c = 0; c < D * D; ++c) g.ainv[c] = prm.ainv[(size_t)c * Epad + ge];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      g.nbr[f] = prm.nbr[(size_t)f * Epad + ge];
+      g.info[f] = prm.finfo[(size_t)f * Epad + ge];
+    }
+    return g;
+  };
+  constexpr bool PF = NV * TE <= NT && NQ * TE <= NT && NFP * TE <= NT;
+  Geo pg;
+  if constexpr (PF) {
+    const int ge = e0 + tid % TE;
+    pg = load_geo(ge < nE ? ge : nE - 1);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  if (skipped) return;
+
+  const T *tB, *tDg, *tBf, *twq, *twf, *tnref;
+  if constexpr (Tl::STAGE_TAB) {
+#pragma unroll
+    for (int s = 0; s < NTR; ++s)
+      if (tid + s * NT < Tl::NTAB) stab[tid + s * NT] = xt[s];
+    tB = stab; tDg = stab + oDg; tBf = stab + oBf; twq = stab + owq; twf = stab + owf; tnref = stab + onr;
+  } else {
+    tB = prm.B; tDg = prm.Dg; tBf = prm.Bf; twq = prm.wq; twf = prm.wf; tnref = prm.nref;
+  }
+  // ---- the tile's coefficients (u, and the direction v for the tangent)
+#pragma unroll
+  for (int s = 0; s < NSTG; ++s) {
+    const int t = tid + s * NT;
+    if (t < NVB * TE) {
+      const bool live = e0 + t % TE < nE;
+      T uu = live ? ru[s] : T(0);
+      const T vv = live ? rv[s] * scale : T(0);
+      if (MODE == MODE_FD) uu = uu + eps * vv;
+      su[t] = uu;
+      if (DUAL) sv[t] = vv;
+    }
   }
   __syncthreads();
 
@@ -208,7 +268,10 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   for (int t = tid; t < NQ * TE; t += NT) {
     const int q = t / TE, e = t % TE, ge = e0 + e;
     if (ge >= nE) continue;
-    const T sd = prm.sdet[ge];
+    Geo gg;
+    if constexpr (PF) gg = pg;
+    else gg = load_geo(ge);
+    const T sd = gg.sdet;
     const T rs = T(1) / sd;
     S U[NV];
 #pragma unroll
@@ -242,11 +305,11 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     for (int r = 0; r < D; ++r) {
       T a[D];
 #pragma unroll
-      for (int c = 0; c < D; ++c) a[c] = prm.ainv[(size_t)(r * D + c) * Epad + ge];
+      for (int c = 0; c < D; ++c) a[c] = gg.ainv[r * D + c];
       S F[NV];
       normal_flux<D>(U, a, gm1, F);
 #pragma unroll
-      for (int k = 0; k < NV; ++k) sw[((q * NV + k) * D + r) * TE + e] = wgt * Part<S>::get(F[k]);
+      for (int k = 0; k < NV; ++k) sw[vix(q, k, r, e)] = wgt * Part<S>::get(F[k]);
     }
   }
   __syncthreads();
@@ -259,7 +322,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
       for (int q = 0; q < NQ; ++q)
 #pragma unroll
         for (int r = 0; r < D; ++r) {
-          const T fv = sw[((q * NV + k) * D + r) * TE + e];
+          const T fv = sw[vix(q, k, r, e)];
 #pragma unroll
           for (int c = 0; c < NI; ++c) acc[o][c] += fv * tDg[(q * NB + g + NG * c) * D + r];
         }
@@ -268,25 +331,26 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   __syncthreads();
 
   // ---- neighbour traces: thread (k, e) gathers the neighbour's coefficients
-  // of variable k once per face and evaluates them at all NFQ points (the
+  // of variable k once per face and evaluates them at the face points (the
   // face threads below then read them from LDS)
-  constexpr int FS = Tl::FS;
   for (int t = tid; t < NV * TE; t += NT) {
     const int k = t / TE, e = t % TE, ge = e0 + e;
     if (ge >= nE) continue;
+    Geo gg;
+    if constexpr (PF) gg = pg;
+    else gg = load_geo(ge);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      const int nb = prm.nbr[(size_t)f * Epad + ge];
+      const int nb = gg.nbr[f];
       if (nb < 0) continue;
-      const int info = prm.finfo[(size_t)f * Epad + ge];
-      const int fN = info & 3, oN = (info >> 2) & 7;
+      const int fN = gg.info[f] & 3, oN = (gg.info[f] >> 2) & 7;
       const T rsn = T(1) / prm.sdet[nb];
       T cu[NB], cv[NB];
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         T uu = io.u[(size_t)(k * NB + i) * Epad + nb];
         T vv = T(0);
-        if (MODE != MODE_RES) vv = io.v[(size_t)(k * NB + i) * Epad + nb] * scale;
+        if constexpr (MODE != MODE_RES) vv = io.v[(size_t)(k * NB + i) * Epad + nb] * scale;
         if (MODE == MODE_FD) uu = uu + eps * vv;
         cu[i] = uu;
         cv[i] = vv;
@@ -300,8 +364,8 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
           a += cu[i] * br[i];
           if (DUAL) b += cv[i] * br[i];
         }
-        sw[((f * NFQ + r) * FS + k) * TE + e] = a * rsn;
-        if (DUAL) sw[((f * NFQ + r) * FS + NV + k) * TE + e] = b * rsn;
+        sw[fix(k, f * NFQ + r, e)] = a * rsn;
+        if (DUAL) sw[fix(NV + k, f * NFQ + r, e)] = b * rsn;
       }
     }
   }
@@ -311,11 +375,19 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   for (int t = tid; t < NF * NFQ * TE; t += NT) {
     const int fr = t / TE, e = t % TE, f = fr / NFQ, r = fr % NFQ, ge = e0 + e;
     if (ge >= nE) continue;
-    const int info = prm.finfo[(size_t)f * Epad + ge];
-    const int nb = prm.nbr[(size_t)f * Epad + ge];
+    Geo gg;
+    if constexpr (PF) gg = pg;
+    else gg = load_geo(ge);
+    int info = gg.info[0], nb = gg.nbr[0];
+#pragma unroll
+    for (int ff = 1; ff < NF; ++ff)
+      if (f == ff) {
+        info = gg.info[ff];
+        nb = gg.nbr[ff];
+      }
     const int oE = (info >> 5) & 7;
     if (r == 0) sori[f * TE + e] = (unsigned char)oE;
-    const T sd = prm.sdet[ge];
+    const T sd = gg.sdet;
     const T rs = T(1) / sd;
     const T* bl = tBf + ((f * NORI + oE) * NFQ + r) * NB;
     S UL[NV], UR[NV];
@@ -341,7 +413,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     for (int c = 0; c < D; ++c) {
       T s = T(0);
 #pragma unroll
-      for (int rr = 0; rr < D; ++rr) s += prm.ainv[(size_t)(rr * D + c) * Epad + ge] * tnref[f * D + rr];
+      for (int rr = 0; rr < D; ++rr) s += gg.ainv[rr * D + c] * tnref[f * D + rr];
       nl[c] = s * sd * sd;
       len2 += nl[c] * nl[c];
     }
@@ -353,10 +425,10 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
         if constexpr (DUAL) {
-          UR[k].v = sw[((f * NFQ + r) * FS + k) * TE + e];
-          UR[k].d[0] = sw[((f * NFQ + r) * FS + NV + k) * TE + e];
+          UR[k].v = sw[fix(k, fr, e)];
+          UR[k].d[0] = sw[fix(NV + k, fr, e)];
         } else {
-          UR[k] = sw[((f * NFQ + r) * FS + k) * TE + e];
+          UR[k] = sw[fix(k, fr, e)];
         }
       }
     } else if (((info >> 8) & 3) == 1) {
@@ -368,7 +440,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     num_flux<D, FLUX>(UL, UR, n, prm.gamma, F);
     const T wgt = twf[r] * len * rs;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) sw[((f * NFQ + r) * FS + k) * TE + e] = wgt * Part<S>::get(F[k]);
+    for (int k = 0; k < NV; ++k) sw[fix(k, fr, e)] = wgt * Part<S>::get(F[k]);
   }
   __syncthreads();
 #pragma unroll
@@ -382,7 +454,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
           const T* bl = tBf + (f * NORI + sori[f * TE + e]) * NFQ * NB;
 #pragma unroll
           for (int r = 0; r < NFQ; ++r) {
-            const T fv = sw[((f * NFQ + r) * FS + k) * TE + e];
+            const T fv = sw[fix(k, f * NFQ + r, e)];
 #pragma unroll
             for (int c = 0; c < NI; ++c) acc[o][c] -= fv * bl[r * NB + g + NG * c];
           }

@@ -730,8 +730,10 @@ __device__ double* expm_core(double* mem, int n) {
   if (tid == 0) {
     double nrm = 0.0;
     for (int jj = 0; jj < n; ++jj) nrm = fmax(nrm, colsum[jj]);
+    // an infinite norm (overflow in H or dt) gets the largest exponent a
+    // finite one can have, so the squaring loop stays bounded
     int s = 0;
-    if (nrm > 1.0) s = (int)ceil(log2(nrm));
+    if (nrm > 1.0) s = isfinite(nrm) ? (int)ceil(log2(nrm)) : 1024;
     s_sq = s;
   }
   __syncthreads();
