@@ -86,11 +86,16 @@ struct Tile {
   static constexpr int NFL = Sh::NF * Sh::NFQ * FS;
   static constexpr int NW = NG > NFL ? NG : NFL;
   static constexpr int per_elem = (int)sizeof(T) * (Sh::NVB * (DUAL ? 2 : 1) + NW) + Sh::NF;
-  // reference tables B, Dg, Bf, wq, wf, nref; staged in LDS when small
+  // reference tables B, Dg, Bf, wq, wf, nref, staged in LDS: every lane
+  // reads an entry per multiply-add, and from global memory (L1) those reads
+  // bound the kernel (3D P2: 3288 entries).  A 3D tile gets a larger LDS
+  // budget so that the tables fit beside a tile that fills the pointwise
+  // phases.
   static constexpr int NTAB = Sh::NQ * Sh::NB * (D + 1) + Sh::NF * Sh::NORI * Sh::NFQ * Sh::NB + Sh::NQ +
                               Sh::NFQ + Sh::NF * D;
-  static constexpr bool STAGE_TAB = NTAB * (int)sizeof(T) <= 8192;
+  static constexpr bool STAGE_TAB = NTAB * (int)sizeof(T) <= 32768;
   static constexpr int fixed_lds = STAGE_TAB ? NTAB * (int)sizeof(T) : 0;
+  static constexpr int budget = D == 3 ? 64 * 1024 : kLdsBudget;
   static constexpr int NT = 256;
   static constexpr int rounds(int te) {
     return (Sh::NQ * te + NT - 1) / NT + (Sh::NF * Sh::NFQ * te + NT - 1) / NT;
@@ -98,7 +103,7 @@ struct Tile {
   static constexpr int pick() {
     int best = 1;
     for (int te = 2; te <= 64; ++te) {
-      if (te * per_elem + fixed_lds > kLdsBudget) break;
+      if (te * per_elem + fixed_lds > budget) break;
       if (rounds(te) * best <= rounds(best) * te) best = te;   // rounds/te no larger
     }
     return best;
