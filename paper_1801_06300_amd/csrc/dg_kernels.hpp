@@ -85,7 +85,9 @@ struct Tile {
   static constexpr int FS = Sh::NV * (DUAL ? 2 : 1);   // LDS words per face point (neighbour trace)
   static constexpr int NFL = Sh::NF * Sh::NFQ * FS;
   static constexpr int NW = NG > NFL ? NG : NFL;
-  static constexpr int per_elem = (int)sizeof(T) * (Sh::NVB * (DUAL ? 2 : 1) + NW) + Sh::NF;
+  // per element: coefficients (and direction), flux scratch, geometry (det,
+  // A^-1, neighbours, face codes) and the face orientation codes
+  static constexpr int per_elem = (int)sizeof(T) * (Sh::NVB * (DUAL ? 2 : 1) + NW + 1 + D * D) + 8 * Sh::NF + Sh::NF;
   // reference tables B, Dg, Bf, wq, wf, nref, staged in LDS: every lane
   // reads an entry per multiply-add, and from global memory (L1) those reads
   // bound the kernel (3D P2: 3288 entries).  A 3D tile gets a larger LDS
@@ -157,6 +159,16 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   __shared__ T sw[Tl::NW * TE];
   __shared__ unsigned char sori[NF * TE];
   __shared__ T stab[Tl::STAGE_TAB ? Tl::NTAB : 1];
+  // Per-element geometry.  Neighbours and face codes are staged in LDS.
+  // When the volume and face phases are single rounds, thread tid works on
+  // element e0 + tid % TE in both and keeps its det and A^-1 in registers;
+  // otherwise they are staged in LDS too.
+  constexpr bool PF = NQ * TE <= NT && NF * NFQ * TE <= NT;
+  constexpr int GTE = PF ? 1 : TE;
+  __shared__ T sg_det[GTE];
+  __shared__ T sg_ainv[D * D * GTE];
+  __shared__ int sg_nbr[NF * TE];
+  __shared__ int sg_info[NF * TE];
   // sw holds, in turn, the weighted volume fluxes (k, r, q, e) and the face
   // values (c, f, r, e), with the pointwise index (q or face point) next to
   // e: the threads of a pointwise phase, t = q * TE + e, then touch
@@ -173,9 +185,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   // Every global load the block needs before its first barrier is issued up
   // front, from clamped addresses and outside branches, so that the block
   // waits for one memory round trip: the skip flag and scales, the reference
-  // tables, the tile's coefficients and, when each pointwise phase is a
-  // single round (thread tid then works on element e0 + tid % TE in all of
-  // them), that element's geometry.
+  // tables, the tile's coefficients and its geometry.
   const bool skipped = io.skip ? (*io.skip != 0) : false;
   T scale = T(1);
   if (MODE != MODE_RES && io.vscale) scale = (T)(*io.vscale);
@@ -213,31 +223,44 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     if constexpr (MODE != MODE_RES) rv[s] = io.v[(size_t)ki * Epad + gc];
     else rv[s] = T(0);
   }
-  struct Geo {
-    T sdet;
-    T ainv[D * D];
-    int nbr[NF], info[NF];
-  };
-  auto load_geo = [&](int ge) {
-    Geo g;
-    g.sdet = prm.sdet[ge];
+  constexpr int NGT = PF ? 0 : (1 + D * D) * TE, NGI = 2 * NF * TE;
+  constexpr int NGTL = (NGT + NT - 1) / NT, NGIL = (NGI + NT - 1) / NT;
+  T gt[NGTL > 0 ? NGTL : 1];
+  int gi[NGIL > 0 ? NGIL : 1];
 #pragma unroll
-    for (int c = 0; c < D * D; ++c) g.ainv[c] = prm.ainv[(size_t)c * Epad + ge];
+  for (int s = 0; s < NGTL; ++s) {
+    int t = tid + s * NT;
+    t = t < NGT ? t : NGT - 1;
+    const int c = t / TE, ge = e0 + t % TE, gc = ge < nE ? ge : nE - 1;
+    gt[s] = c == 0 ? prm.sdet[gc] : prm.ainv[(size_t)(c - 1) * Epad + gc];
+  }
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      g.nbr[f] = prm.nbr[(size_t)f * Epad + ge];
-      g.info[f] = prm.finfo[(size_t)f * Epad + ge];
-    }
-    return g;
-  };
-  constexpr bool PF = NV * TE <= NT && NQ * TE <= NT && NFP * TE <= NT;
-  Geo pg;
+  for (int s = 0; s < NGIL; ++s) {
+    int t = tid + s * NT;
+    t = t < NGI ? t : NGI - 1;
+    const int c = t / TE, ge = e0 + t % TE, gc = ge < nE ? ge : nE - 1;
+    gi[s] = c < NF ? prm.nbr[(size_t)c * Epad + gc] : prm.finfo[(size_t)(c - NF) * Epad + gc];
+  }
+  T pg_det = T(0), pg_ainv[D * D];
   if constexpr (PF) {
-    const int ge = e0 + tid % TE;
-    pg = load_geo(ge < nE ? ge : nE - 1);
+    const int ge = e0 + tid % TE, gc = ge < nE ? ge : nE - 1;
+    pg_det = prm.sdet[gc];
+#pragma unroll
+    for (int c = 0; c < D * D; ++c) pg_ainv[c] = prm.ainv[(size_t)c * Epad + gc];
   }
   __builtin_amdgcn_sched_barrier(0);
   if (skipped) return;
+  // geometry of element e of the tile (with PF: the thread's own element)
+  auto g_det = [&](int e) -> T {
+    if constexpr (PF) return pg_det;
+    else return sg_det[e];
+  };
+  auto g_ainv = [&](int e, int c) -> T {
+    if constexpr (PF) return pg_ainv[c];
+    else return sg_ainv[c * TE + e];
+  };
+  auto g_nbr = [&](int e, int f) -> int { return sg_nbr[f * TE + e]; };
+  auto g_info = [&](int e, int f) -> int { return sg_info[f * TE + e]; };
 
   const T *tB, *tDg, *tBf, *twq, *twf, *tnref;
   if constexpr (Tl::STAGE_TAB) {
@@ -247,6 +270,24 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     tB = stab; tDg = stab + oDg; tBf = stab + oBf; twq = stab + owq; twf = stab + owf; tnref = stab + onr;
   } else {
     tB = prm.B; tDg = prm.Dg; tBf = prm.Bf; twq = prm.wq; twf = prm.wf; tnref = prm.nref;
+  }
+#pragma unroll
+  for (int s = 0; s < NGTL; ++s) {
+    const int t = tid + s * NT;
+    if (t < NGT) {
+      const int c = t / TE, e = t % TE;
+      if (c == 0) sg_det[e] = gt[s];
+      else sg_ainv[(c - 1) * TE + e] = gt[s];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NGIL; ++s) {
+    const int t = tid + s * NT;
+    if (t < NGI) {
+      const int c = t / TE, e = t % TE;
+      if (c < NF) sg_nbr[c * TE + e] = gi[s];
+      else sg_info[(c - NF) * TE + e] = gi[s];
+    }
   }
   // ---- the tile's coefficients (u, and the direction v for the tangent)
 #pragma unroll
@@ -273,10 +314,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   for (int t = tid; t < NQ * TE; t += NT) {
     const int q = t / TE, e = t % TE, ge = e0 + e;
     if (ge >= nE) continue;
-    Geo gg;
-    if constexpr (PF) gg = pg;
-    else gg = load_geo(ge);
-    const T sd = gg.sdet;
+    const T sd = g_det(e);
     const T rs = T(1) / sd;
     S U[NV];
 #pragma unroll
@@ -310,7 +348,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     for (int r = 0; r < D; ++r) {
       T a[D];
 #pragma unroll
-      for (int c = 0; c < D; ++c) a[c] = gg.ainv[r * D + c];
+      for (int c = 0; c < D; ++c) a[c] = g_ainv(e, r * D + c);
       S F[NV];
       normal_flux<D>(U, a, gm1, F);
 #pragma unroll
@@ -335,43 +373,38 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   }
   __syncthreads();
 
-  // ---- neighbour traces: thread (k, e) gathers the neighbour's coefficients
-  // of variable k once per face and evaluates them at the face points (the
-  // face threads below then read them from LDS)
-  for (int t = tid; t < NV * TE; t += NT) {
-    const int k = t / TE, e = t % TE, ge = e0 + e;
+  // ---- neighbour traces: item (k, f, e) gathers the neighbour's
+  // coefficients of variable k across face f once and evaluates them at the
+  // face points (the face threads below then read them from LDS)
+  for (int t = tid; t < NV * NF * TE; t += NT) {
+    const int kf = t / TE, e = t % TE, k = kf / NF, f = kf % NF, ge = e0 + e;
     if (ge >= nE) continue;
-    Geo gg;
-    if constexpr (PF) gg = pg;
-    else gg = load_geo(ge);
+    const int nb = g_nbr(e, f);
+    if (nb < 0) continue;
+    const int info = g_info(e, f);
+    const int fN = info & 3, oN = (info >> 2) & 7;
+    const T rsn = T(1) / prm.sdet[nb];
+    T cu[NB], cv[NB];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const int nb = gg.nbr[f];
-      if (nb < 0) continue;
-      const int fN = gg.info[f] & 3, oN = (gg.info[f] >> 2) & 7;
-      const T rsn = T(1) / prm.sdet[nb];
-      T cu[NB], cv[NB];
+    for (int i = 0; i < NB; ++i) {
+      T uu = io.u[(size_t)(k * NB + i) * Epad + nb];
+      T vv = T(0);
+      if constexpr (MODE != MODE_RES) vv = io.v[(size_t)(k * NB + i) * Epad + nb] * scale;
+      if (MODE == MODE_FD) uu = uu + eps * vv;
+      cu[i] = uu;
+      cv[i] = vv;
+    }
+#pragma unroll
+    for (int r = 0; r < NFQ; ++r) {
+      const T* br = tBf + ((fN * NORI + oN) * NFQ + r) * NB;
+      T a = T(0), b = T(0);
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
-        T uu = io.u[(size_t)(k * NB + i) * Epad + nb];
-        T vv = T(0);
-        if constexpr (MODE != MODE_RES) vv = io.v[(size_t)(k * NB + i) * Epad + nb] * scale;
-        if (MODE == MODE_FD) uu = uu + eps * vv;
-        cu[i] = uu;
-        cv[i] = vv;
+        a += cu[i] * br[i];
+        if (DUAL) b += cv[i] * br[i];
       }
-#pragma unroll
-      for (int r = 0; r < NFQ; ++r) {
-        const T* br = tBf + ((fN * NORI + oN) * NFQ + r) * NB;
-        T a = T(0), b = T(0);
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-          a += cu[i] * br[i];
-          if (DUAL) b += cv[i] * br[i];
-        }
-        sw[fix(k, f * NFQ + r, e)] = a * rsn;
-        if (DUAL) sw[fix(NV + k, f * NFQ + r, e)] = b * rsn;
-      }
+      sw[fix(k, f * NFQ + r, e)] = a * rsn;
+      if (DUAL) sw[fix(NV + k, f * NFQ + r, e)] = b * rsn;
     }
   }
   __syncthreads();
@@ -380,19 +413,11 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   for (int t = tid; t < NF * NFQ * TE; t += NT) {
     const int fr = t / TE, e = t % TE, f = fr / NFQ, r = fr % NFQ, ge = e0 + e;
     if (ge >= nE) continue;
-    Geo gg;
-    if constexpr (PF) gg = pg;
-    else gg = load_geo(ge);
-    int info = gg.info[0], nb = gg.nbr[0];
-#pragma unroll
-    for (int ff = 1; ff < NF; ++ff)
-      if (f == ff) {
-        info = gg.info[ff];
-        nb = gg.nbr[ff];
-      }
+    const int info = g_info(e, f);
+    const int nb = g_nbr(e, f);
     const int oE = (info >> 5) & 7;
     if (r == 0) sori[f * TE + e] = (unsigned char)oE;
-    const T sd = gg.sdet;
+    const T sd = g_det(e);
     const T rs = T(1) / sd;
     const T* bl = tBf + ((f * NORI + oE) * NFQ + r) * NB;
     S UL[NV], UR[NV];
@@ -418,7 +443,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     for (int c = 0; c < D; ++c) {
       T s = T(0);
 #pragma unroll
-      for (int rr = 0; rr < D; ++rr) s += gg.ainv[rr * D + c] * tnref[f * D + rr];
+      for (int rr = 0; rr < D; ++rr) s += g_ainv(e, rr * D + c) * tnref[f * D + rr];
       nl[c] = s * sd * sd;
       len2 += nl[c] * nl[c];
     }
