@@ -98,7 +98,7 @@ typedef struct {
 typedef struct {
   double beta;               /* |b|_2 */
   double h_last;             /* h_{m_eff+1, m_eff} */
-  int32_t m_eff;             /* Krylov dimension used (< m after breakdown; 0 if b = 0) */
+  int32_t m_eff;             /* Krylov dimension used (< m after breakdown or an adaptive stop; 0 if b = 0) */
   int32_t breakdown;         /* 1 if the Arnoldi process broke down */
   double err_est;            /* a-posteriori relative error estimate (with a Krylov tolerance set) */
   int32_t dt_halvings;       /* times dt was halved to meet the tolerance */
@@ -220,7 +220,9 @@ pcexp_status pcexp_pressure_functional(pcexp_ctx* ctx, const double* u, double p
  * exact exponential).  Arrays device FP64, ABI layout; ubar_n != ubar_np1.
  * Workspace: pcexp_step_vjp_workspace_bytes (3(m+1) + 14 vectors of K plus
  * small state), 256-byte aligned, caller-owned.  Synchronises once (to read
- * the Krylov dimensions reached). */
+ * the Krylov dimensions reached).  The Krylov controls of
+ * pcexp_set_krylov_tol / pcexp_set_krylov_adapt do not apply: it
+ * differentiates the fixed-dimension, fixed-dt step. */
 size_t pcexp_step_vjp_workspace_bytes(const pcexp_ctx* ctx, int32_t m);
 pcexp_status pcexp_step_vjp(pcexp_ctx* ctx, const double* u_n, double dt, int32_t m,
                             int32_t scheme, const double* ubar_np1, double* ubar_n, void* ws,
@@ -235,6 +237,20 @@ pcexp_status pcexp_step_vjp(pcexp_ctx* ctx, const double* u_n, double dt, int32_
  * Krylov convergence tolerance of 1e-5 (Sec. 5) without defining the
  * control; this is one reading of it. */
 pcexp_status pcexp_set_krylov_tol(pcexp_ctx* ctx, double tol);
+
+/* Adaptive Krylov dimension for pcexp_step / pcexp_steady (the paper's
+ * Krylov tolerance of Sec. 5 read as a stopping rule for the Arnoldi process;
+ * the paper finds EXP1 with it the faster steady solver, Sec. 5).  With
+ * check_every = c > 0 and a tolerance tol > 0 set by pcexp_set_krylov_tol,
+ * each Arnoldi run of a step (predictor and corrector) evaluates, after
+ * every iteration j with j % c == 0 (1 <= j < m), the estimate above for
+ * dimension j at the current dt and stops with m_eff = j when it is <= tol;
+ * m is the upper bound.  Only the predictor may then halve dt (when even
+ * dimension m misses tol).  Each check is one small launch on the stream (no
+ * synchronisation); the dimension reached is in pcexp_step_info.
+ * check_every = 0 (the default) keeps the dimension fixed at m.  Errors:
+ * PCEXP_E_ARG for check_every outside [0, 64]. */
+pcexp_status pcexp_set_krylov_adapt(pcexp_ctx* ctx, int32_t check_every);
 
 /* Steady state by pseudo-time stepping (Sec. 5: PCEXP or EXP1 with the CFL
  * ramp of eq. (cfl), CFL(n) = min{CFL_max, max[||R(rho_n)||^-3, 1 + (n-1)/(2p+1)]},

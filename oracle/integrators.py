@@ -53,16 +53,19 @@ class DenseSplit:
         return (self.A_jac @ np.reshape(v, -1)).reshape(np.shape(v))
 
 
-def pcexp_step(op, u, dt, m, scheme="pcexp", eta=1e-12, info=None, krylov_tol=0.0):
+def pcexp_step(op, u, dt, m, scheme="pcexp", eta=1e-12, info=None, krylov_tol=0.0, krylov_every=0):
     """One PCEXP (or EXP1) step u_n -> u_{n+1}.  With krylov_tol > 0 the
     predictor's dt is halved until the Krylov error estimate is <= krylov_tol
-    (krylov.arnoldi_phi1_controlled) and both stages use that dt."""
+    (krylov.arnoldi_phi1_controlled) and both stages use that dt; with also
+    krylov_every > 0 each stage's Krylov dimension is chosen adaptively
+    (krylov.adaptive_dimension) before that."""
     u = np.asarray(u)
     shape = u.shape
     Rn = op.residual(u)
     mv = lambda v: op.jvp(u, np.reshape(v, shape), Rn)
     if krylov_tol > 0.0:
-        x1, dt, err, halv, i1 = krylov.arnoldi_phi1_controlled(mv, Rn, dt, m, krylov_tol, eta)
+        x1, dt, err, halv, i1 = krylov.arnoldi_phi1_controlled(mv, Rn, dt, m, krylov_tol, eta,
+                                                               check_every=krylov_every)
         i1 = dict(i1, dt=dt, err_est=err, dt_halvings=halv)
     else:
         x1, i1 = krylov.arnoldi_phi(mv, Rn, dt, 1, m, eta, return_info=True)
@@ -74,10 +77,17 @@ def pcexp_step(op, u, dt, m, scheme="pcexp", eta=1e-12, info=None, krylov_tol=0.
         return ustar
     Rs = op.residual(ustar)
     d = Rs - Rn - op.jvp(u, x1, Rn)
-    x2, i2 = krylov.arnoldi_phi(mv, d, dt, 1, m, eta, return_info=True)
+    if krylov_tol > 0.0 and krylov_every > 0:
+        x2, _, err2, _, i2 = krylov.arnoldi_phi1_controlled(mv, d, dt, m, krylov_tol, eta,
+                                                            check_every=krylov_every, dt_control=False)
+        i2 = dict(i2, err_est=err2)
+        unext = ustar + 0.5 * x2
+    else:
+        x2, i2 = krylov.arnoldi_phi(mv, d, dt, 1, m, eta, return_info=True)
+        unext = ustar + 0.5 * dt * x2
     if info is not None:
         info["k2"] = i2
-    return ustar + 0.5 * dt * x2
+    return unext
 
 
 def heun_step(op, u, dt):
@@ -113,7 +123,7 @@ def cfl_ramp(n, rnorm, p, cfl_max):
     return float(min(cfl_max, max(big, 1.0 + (n - 1) / (2 * p + 1))))
 
 
-def steady_iterations(dg, op, u, niter, cfl_max, m, scheme="pcexp", krylov_tol=0.0):
+def steady_iterations(dg, op, u, niter, cfl_max, m, scheme="pcexp", krylov_tol=0.0, krylov_every=0):
     """Pseudo-time stepping toward R(u) = 0 (Sec. 5): at iteration n = 1, 2, ...
     CFL(n) from eq. (cfl) with ||R(rho_n)||, dt from eq. (x3d) at u_n with that
     CFL, then one PCEXP (or EXP1) step.  Returns the state and the list of
@@ -124,5 +134,5 @@ def steady_iterations(dg, op, u, niter, cfl_max, m, scheme="pcexp", krylov_tol=0
         r = res_rho_norm(dg, R)
         hist.append(r)
         dt = stable_dt(dg, u, cfl_ramp(n, r, dg.p, cfl_max))
-        u = pcexp_step(op, u, dt, m, scheme, krylov_tol=krylov_tol)
+        u = pcexp_step(op, u, dt, m, scheme, krylov_tol=krylov_tol, krylov_every=krylov_every)
     return u, hist

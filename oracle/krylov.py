@@ -115,18 +115,41 @@ def phi1_with_error(H, beta, h_next, dt):
     return p1, err
 
 
-def arnoldi_phi1_controlled(matvec, b, dt, m, tol, eta=1e-12, max_halvings=40):
-    """dt * phi_1(dt J) b with dt halved until the error estimate is <= tol.
+def adaptive_dimension(H, beta, meff, dt, tol, check_every):
+    """Adaptive Krylov dimension (the Krylov tolerance of Sec. 5 read as a
+    stopping rule): the smallest j with j % check_every == 0 and
+    1 <= j < meff whose error estimate (phi1_with_error, with h_{j+1,j} of
+    the Arnoldi relation) at dt is <= tol; meff when there is none.  The
+    first j columns of an Arnoldi process do not depend on later iterations,
+    so checking the finished relation equals stopping the process at j.
+    Returns (m_eff, stopped)."""
+    if check_every <= 0:
+        return meff, False
+    for j in range(check_every, meff, check_every):
+        _, err = phi1_with_error(H[:j, :j], beta, H[j, j - 1], dt)
+        if err <= tol:
+            return j, True
+    return meff, False
+
+
+def arnoldi_phi1_controlled(matvec, b, dt, m, tol, eta=1e-12, max_halvings=40, check_every=0,
+                            dt_control=True):
+    """dt * phi_1(dt J) b with the Krylov tolerance: the dimension is first
+    chosen by adaptive_dimension (check_every > 0), then, if dt_control, dt
+    is halved until the error estimate is <= tol.
     Returns (x, dt_used, err, halvings, info)."""
     shape = np.shape(b)
     V, H, beta, meff, brk = arnoldi_mgs(matvec, b, m, eta)
     if meff == 0:
         return np.zeros(shape), dt, 0.0, 0, dict(m_eff=0)
+    meff, stopped = adaptive_dimension(H, beta, meff, dt, tol, check_every)
+    if stopped:
+        brk = False
     h_next = 0.0 if brk else H[meff, meff - 1]
     halv = 0
     while True:
         y, err = phi1_with_error(H[:meff, :meff], beta, h_next, dt)
-        if err <= tol or halv >= max_halvings:
+        if not dt_control or err <= tol or halv >= max_halvings:
             break
         dt *= 0.5
         halv += 1

@@ -91,6 +91,7 @@ _SIGS = {
                                          ctypes.POINTER(KrylovInfo), _VP]),
     "pcexp_profile": (ctypes.c_int, [_VP, ctypes.c_int32, c_double_p]),
     "pcexp_set_krylov_tol": (ctypes.c_int, [_VP, ctypes.c_double]),
+    "pcexp_set_krylov_adapt": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "pcexp_steady": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
                                     ctypes.c_size_t, ctypes.POINTER(SteadyInfo), _VP]),
@@ -340,6 +341,11 @@ class PCEXP:
     def set_krylov_tol(self, tol):
         """Predictor dt control by the Krylov error estimate (0 disables)."""
         self._check(self.lib.pcexp_set_krylov_tol(self.ctx, float(tol)), "set_krylov_tol")
+
+    def set_krylov_adapt(self, check_every):
+        """Adaptive Krylov dimension: with a tolerance set, check the estimate every
+        `check_every` Arnoldi iterations and stop once it is met (0 disables)."""
+        self._check(self.lib.pcexp_set_krylov_adapt(self.ctx, int(check_every)), "set_krylov_adapt")
 
     def steady(self, u, cfl_max=1000.0, tol=1e-10, max_iter=500, check_every=10, m=30, scheme="pcexp",
                prec="f64", jvp="tangent"):

@@ -816,60 +816,69 @@ __device__ void phi_body(KState* ks, const double* dtp, int k, double* mem) {
 // until err <= tol (at most 40 times); *dtp returns the accepted dt, y the
 // corresponding beta phi_1(dt H_M) e_1.  norm_tmp[2] = err, norm_tmp[3] =
 // number of halvings.
+// Saad's a-posteriori estimate of the Krylov approximation of phi_1(dt J) b
+// with dimension m: err = dt h_{m+1,m} |[phi_2(dt H_m) e_1]_m| / |phi_1(dt H_m) e_1|,
+// both phi from the exponential of the augmented (m+2) x (m+2) matrix, which
+// is left in *P (phi_1(dt H_m) e_1 is its column m, rows < m).  Every thread
+// returns err.
+__device__ double krylov_estimate(const KState* ks, double dt, int m, double hnext, double* mem, const double** P) {
+  const int tid = threadIdx.x;
+  __shared__ double red[PHI_T / 64];
+  const int n = m + 2, nn = n * n;
+  for (int t = tid; t < nn; t += PHI_T) {
+    const int i = t % n, jj = t / n;
+    double v = 0.0;
+    if (i < m && jj < m) {
+      if (i <= jj + 1) v = dt * ks->H[(size_t)jj * KLD + i];
+    } else if (jj == m && i == 0) {
+      v = 1.0;
+    } else if (jj == m + 1 && i == m) {
+      v = 1.0;
+    }
+    mem[t] = v;
+  }
+  __syncthreads();
+  const double* Q = expm_core(mem, n);
+  double sq = 0.0;
+  for (int i = tid; i < m; i += PHI_T) {
+    const double x = Q[(size_t)m * n + i];
+    sq += x * x;
+  }
+  sq = wave_sum(sq);
+  if ((tid & 63) == 0) red[tid >> 6] = sq;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < PHI_T / 64; ++w) t += red[w];
+    const double phi2m = fabs(Q[(size_t)(m + 1) * n + (m - 1)]);
+    red[0] = t > 0.0 ? dt * hnext * phi2m / sqrt(t) : 0.0;
+  }
+  __syncthreads();
+  const double err = red[0];
+  __syncthreads();
+  *P = Q;
+  return err;
+}
+
 __device__ void phi_adapt_body(KState* ks, double* dtp, double tol, double* mem) {
   const int m = ks->m_eff;
   const int tid = threadIdx.x;
-  __shared__ double red[PHI_T / 64];
-  __shared__ int accept;
   if (m == 0) {
     for (int i = tid; i < KMAX + 4; i += PHI_T) ks->y[i] = 0.0;
     if (tid == 0) { ks->norm_tmp[2] = 0.0; ks->norm_tmp[3] = 0.0; }
     return;
   }
-  const int n = m + 2, nn = n * n;
+  const int n = m + 2;
   const double hnext = ks->breakdown ? 0.0 : ks->hlast;
   double dt = *dtp;
   int halvings = 0;
   double err = 0.0;
   const double* P = nullptr;
   for (;;) {
-    for (int t = tid; t < nn; t += PHI_T) {
-      const int i = t % n, jj = t / n;
-      double v = 0.0;
-      if (i < m && jj < m) {
-        if (i <= jj + 1) v = dt * ks->H[(size_t)jj * KLD + i];
-      } else if (jj == m && i == 0) {
-        v = 1.0;
-      } else if (jj == m + 1 && i == m) {
-        v = 1.0;
-      }
-      mem[t] = v;
-    }
-    __syncthreads();
-    P = expm_core(mem, n);
-    // |phi_1 e_1|^2 over rows < m
-    double sq = 0.0;
-    for (int i = tid; i < m; i += PHI_T) {
-      const double x = P[(size_t)m * n + i];
-      sq += x * x;
-    }
-    sq = wave_sum(sq);
-    if ((tid & 63) == 0) red[tid >> 6] = sq;
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int w = 0; w < PHI_T / 64; ++w) t += red[w];
-      const double phi2m = fabs(P[(size_t)(m + 1) * n + (m - 1)]);
-      err = t > 0.0 ? dt * hnext * phi2m / sqrt(t) : 0.0;
-      accept = (err <= tol || halvings >= 40) ? 1 : 0;
-      red[0] = err;
-    }
-    __syncthreads();
-    err = red[0];
-    if (accept) break;
+    err = krylov_estimate(ks, dt, m, hnext, mem, &P);
+    if (err <= tol || halvings >= 40) break;
     dt *= 0.5;
     ++halvings;
-    __syncthreads();
   }
   const double beta = ks->beta;
   for (int i = tid; i < KMAX + 4; i += PHI_T) ks->y[i] = (i < m) ? beta * P[(size_t)m * n + i] : 0.0;
@@ -878,6 +887,41 @@ __device__ void phi_adapt_body(KState* ks, double* dtp, double tol, double* mem)
     ks->norm_tmp[2] = err;
     ks->norm_tmp[3] = (double)halvings;
   }
+}
+
+// Dimension check of an adaptive run, after the finalise-and-update pass of
+// iteration j, when H_j and h_{j+1,j} are final and V_0..V_{j-1} complete:
+// the estimate for dimension j at the current dt; at or below tol the run
+// stops with m_eff = j (the later launches of the run see `done`, as after
+// a breakdown, but the breakdown flag stays clear).
+__device__ void krylov_check_body(KState* ks, const double* dtp, double tol, int j, double* mem) {
+  if (ks->done) return;
+  const double hnext = ks->H[(size_t)(j - 1) * KLD + j];
+  const double* P = nullptr;
+  const double err = krylov_estimate(ks, *dtp, j, hnext, mem, &P);
+  if (threadIdx.x == 0 && err <= tol) {
+    ks->m_eff = j;
+    ks->hlast = hnext;
+    ks->done_at = j;
+    ks->done = 1;
+    ks->norm_tmp[2] = err;
+  }
+}
+
+__global__ __launch_bounds__(PHI_T) void krylov_check_lds(KState* ks, const double* dtp, double tol, int j) {
+  extern __shared__ double smem[];
+  krylov_check_body(ks, dtp, tol, j, smem);
+}
+__global__ __launch_bounds__(PHI_T) void krylov_check_glb(KState* ks, const double* dtp, double tol, int j,
+                                                          double* mem) {
+  krylov_check_body(ks, dtp, tol, j, mem);
+}
+
+void k_krylov_check(KState* ks, const double* dt, double tol, int j, double* scratch, hipStream_t st) {
+  const int n = j + 2;
+  const size_t bytes = (size_t)7 * n * n * sizeof(double);
+  if (bytes <= 60 * 1024) launch(krylov_check_lds, dim3(1), dim3(PHI_T), bytes, st, ks, dt, tol, j);
+  else launch(krylov_check_glb, dim3(1), dim3(PHI_T), 0, st, ks, dt, tol, j, scratch);
 }
 
 __global__ __launch_bounds__(PHI_T) void hess_phi_adapt_lds(KState* ks, double* dtp, double tol) {

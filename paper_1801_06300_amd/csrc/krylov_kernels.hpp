@@ -76,6 +76,10 @@ void k_hess_phi(KState* ks, const double* dt, int k, int m, double* scratch, hip
 // phi_1 with the Krylov error estimate: halves *dt on the device until the
 // estimated relative error is <= tol; scratch >= 7 (m+2)^2 doubles.
 void k_hess_phi_adapt(KState* ks, double* dt, double tol, int m, double* scratch, hipStream_t st);
+// Adaptive dimension: after iteration j (1 <= j < m), stop the run with
+// m_eff = j when the error estimate for dimension j at *dt is <= tol;
+// scratch >= 7 (j+2)^2 doubles.
+void k_krylov_check(KState* ks, const double* dt, double tol, int j, double* scratch, hipStream_t st);
 template <typename TV, typename TX>
 void k_combine(const TV* V, size_t ld, const KState* ks, const double* base, double* out,
                TX* xout, double fac, const double* dtp, size_t n, hipStream_t st);

@@ -49,6 +49,7 @@ struct pcexp_ctx {
   double gamma = 1.4, ff[5] = {0, 0, 0, 0, 0};
   double volume_total = 0.0;
   double krylov_tol = 0.0;   // > 0: stage-1 dt control by the Krylov error estimate
+  int krylov_every = 0;      // > 0 (with krylov_tol): adaptive dimension, checked every krylov_every iterations
   // tables and geometry
   double *B = nullptr, *Dg = nullptr, *wq = nullptr, *Bf = nullptr, *wf = nullptr, *nref = nullptr,
          *Bc = nullptr, *refp = nullptr;
@@ -262,7 +263,7 @@ WsLayout ws_layout(const pcexp_ctx* c, int m, int k, int prec) {
 template <typename TV>
 void arnoldi_run(pcexp_ctx* c, int jvp, int prec, const double* u_lin, const float* u32, const double* b,
                  const double* Rlin, double* dtp, int k, int m, KState* ks, double* part, double* phi,
-                 TV* V, hipStream_t st, double adapt_tol = 0.0) {
+                 TV* V, hipStream_t st, double tol = 0.0, bool dt_control = false, int check_every = 0) {
   const size_t n = c->Kint, ld = c->Kld;
   const double eta = (prec == PCEXP_PREC_MIXED) ? 1e-5 : 1e-12;
   k_init_state(ks, eta, st);
@@ -278,6 +279,11 @@ void arnoldi_run(pcexp_ctx* c, int jvp, int prec, const double* u_lin, const flo
     // the reduction pass reads j + 2 vectors; the finalise-and-update pass reads j + 2 and writes 2
     { Prof pr(c, st, PC_GSR, (j + 2.0) * vb); k_gs_reduce<TV>(V, ld, j, n, ks, part, false, st); }
     { Prof pr(c, st, PC_GSU, (j + 4.0) * vb); k_gs_update<TV>(V, ld, j, n, ks, part, st); }
+    // adaptive dimension: H_j is final now; stop at m_eff = j if its estimate meets tol
+    if (tol > 0.0 && check_every > 0 && k == 1 && j >= 1 && j % check_every == 0) {
+      Prof pr(c, st, PC_PHI, 0.0);
+      k_krylov_check(ks, dtp, tol, j, phi, st);
+    }
   }
   {
     Prof pr(c, st, PC_GSR, (m + 1.0) * (double)c->K * sizeof(TV));
@@ -286,7 +292,7 @@ void arnoldi_run(pcexp_ctx* c, int jvp, int prec, const double* u_lin, const flo
   { Prof pr(c, st, PC_GSF, 0.0); k_gs_close(ks, part, m, n, st); }
   {
     Prof pr(c, st, PC_PHI, 0.0);
-    if (adapt_tol > 0.0 && k == 1) k_hess_phi_adapt(ks, dtp, adapt_tol, m, phi, st);
+    if (tol > 0.0 && dt_control && k == 1) k_hess_phi_adapt(ks, dtp, tol, m, phi, st);
     else k_hess_phi(ks, dtp, k, m, phi, st);
   }
 }
@@ -811,12 +817,14 @@ pcexp_status step_core(pcexp_ctx* c, double* un, const DtMode& dm, int m, int sc
   double* out1 = exp1 ? un : us;
   if (mixed) {
     float* V = (float*)(w + L.V);
-    arnoldi_run<float>(c, jvp, prec, un, un32, Rn, Rn, dtp, 1, m, ks1, part, phi, V, st, c->krylov_tol);
+    arnoldi_run<float>(c, jvp, prec, un, un32, Rn, Rn, dtp, 1, m, ks1, part, phi, V, st, c->krylov_tol, true,
+                       c->krylov_every);
     Prof pr(c, st, PC_COMB, (double)c->K * (m * 4.0 + 8 + 8 + 4));
     k_combine<float, float>(V, c->Kld, ks1, un, out1, exp1 ? (float*)nullptr : (float*)x1, 1.0, dtp, n, st);
   } else {
     double* V = (double*)(w + L.V);
-    arnoldi_run<double>(c, jvp, prec, un, nullptr, Rn, Rn, dtp, 1, m, ks1, part, phi, V, st, c->krylov_tol);
+    arnoldi_run<double>(c, jvp, prec, un, nullptr, Rn, Rn, dtp, 1, m, ks1, part, phi, V, st, c->krylov_tol, true,
+                        c->krylov_every);
     Prof pr(c, st, PC_COMB, (double)c->K * (m * 8.0 + 8 + 8 + 8));
     k_combine<double, double>(V, c->Kld, ks1, un, out1, exp1 ? (double*)nullptr : (double*)x1, 1.0, dtp, n, st);
   }
@@ -841,12 +849,14 @@ pcexp_status step_core(pcexp_ctx* c, double* un, const DtMode& dm, int m, int sc
   // stage 2: u_{n+1} = u* + dt/2 Phi_1(dt J_n)(N* - N_n)
   if (mixed) {
     float* V = (float*)(w + L.V);
-    arnoldi_run<float>(c, jvp, prec, un, un32, Rs, Rn, dtp, 1, m, ks2, part, phi, V, st);
+    arnoldi_run<float>(c, jvp, prec, un, un32, Rs, Rn, dtp, 1, m, ks2, part, phi, V, st, c->krylov_tol, false,
+                       c->krylov_every);
     Prof pr(c, st, PC_COMB, (double)c->K * (m * 4.0 + 8 + 8));
     k_combine<float, double>(V, c->Kld, ks2, us, un, (double*)nullptr, 0.5, dtp, n, st);
   } else {
     double* V = (double*)(w + L.V);
-    arnoldi_run<double>(c, jvp, prec, un, nullptr, Rs, Rn, dtp, 1, m, ks2, part, phi, V, st);
+    arnoldi_run<double>(c, jvp, prec, un, nullptr, Rs, Rn, dtp, 1, m, ks2, part, phi, V, st, c->krylov_tol, false,
+                        c->krylov_every);
     Prof pr(c, st, PC_COMB, (double)c->K * (m * 8.0 + 8 + 8));
     k_combine<double, double>(V, c->Kld, ks2, us, un, (double*)nullptr, 0.5, dtp, n, st);
   }
@@ -868,6 +878,13 @@ pcexp_status pcexp_set_krylov_tol(pcexp_ctx* c, double tol) {
   if (!c) return PCEXP_E_ARG;
   if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(c, PCEXP_E_ARG, "tol must be finite and >= 0");
   c->krylov_tol = tol;
+  return PCEXP_OK;
+}
+
+pcexp_status pcexp_set_krylov_adapt(pcexp_ctx* c, int32_t check_every) {
+  if (!c) return PCEXP_E_ARG;
+  if (check_every < 0 || check_every > KMAX) return fail(c, PCEXP_E_ARG, "check_every must be in [0, 64]");
+  c->krylov_every = check_every;
   return PCEXP_OK;
 }
 

@@ -91,3 +91,56 @@ def test_steady_with_krylov_control_parity():
     want, hist = steady_iterations(g, ExactJacobian(g), u, 4, 1000.0, 30, krylov_tol=1e-5)
     ctx.set_krylov_tol(0.0)
     assert rel(ud.cpu().numpy(), want) < 1e-9
+
+
+@pytest.mark.parametrize("scheme,cfl", [("pcexp", 5.0), ("pcexp", 10.0), ("exp1", 5.0)])
+def test_step_adaptive_dimension_parity(scheme, cfl):
+    """pcexp_step with the adaptive Krylov dimension (tol 1e-8, checked every
+    2 iterations, m <= 30): each Arnoldi run stops at the oracle's dimension
+    (the estimates at the checks are far from the tolerance for these cases:
+    CFL 5 stops both stages at 22; CFL 10 reaches 30 in the predictor, halves
+    dt once and stops the corrector at 22) and the state matches."""
+    from paper_1801_06300_amd import PCEXP
+    from oracle.integrators import pcexp_step, stable_dt
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    m, ang = mesh_case("sq4j")
+    prim = W.freestream_prim(2, angle_deg=ang)
+    print(f"\n[case] adaptive dimension sq4j p=2 roe {scheme} cfl={cfl}", flush=True)
+    g = DG(m, 2, "roe", farfield_prim=prim)
+    ctx = PCEXP(m, 2, "roe", farfield_prim=prim)
+    u = vortex_state(g, m, 1e-3)
+    dt = stable_dt(g, u, cfl)
+    ctx.set_krylov_tol(1e-8)
+    ctx.set_krylov_adapt(2)
+    ud = _t(u)
+    info = ctx.step(ud, dt=dt, m=30, scheme=scheme, info=True)
+    ctx.set_krylov_adapt(0)
+    ctx.set_krylov_tol(0.0)
+    oinfo = {}
+    want = pcexp_step(ExactJacobian(g), u, dt, 30, scheme, info=oinfo, krylov_tol=1e-8, krylov_every=2)
+    print(f"[adapt] device m_eff {info['k1']['m_eff']}/{info['k2']['m_eff']} halvings "
+          f"{info['k1']['dt_halvings']}; oracle {oinfo['k1']['m_eff']}/{oinfo.get('k2', {}).get('m_eff')} "
+          f"halvings {oinfo['k1']['dt_halvings']}", flush=True)
+    assert info["k1"]["m_eff"] == oinfo["k1"]["m_eff"]
+    assert info["k1"]["dt_halvings"] == oinfo["k1"]["dt_halvings"]
+    assert info["dt"] == oinfo["k1"]["dt"]
+    if scheme == "pcexp":
+        assert info["k2"]["m_eff"] == oinfo["k2"]["m_eff"] < 30
+    assert min(info["k1"]["m_eff"], info["k2"]["m_eff"] if scheme == "pcexp" else 0) < 30
+    assert rel(ud.cpu().numpy(), want) < 1e-10
+
+
+def test_steady_exp1_adaptive_dimension_parity():
+    """EXP1 pseudo-time with the adaptive dimension (tol 1e-5, checks every 3
+    iterations, m <= 30) for four ramped iterations equals the oracle's."""
+    g, ctx, u = _setup(1)
+    ctx.set_krylov_tol(1e-5)
+    ctx.set_krylov_adapt(3)
+    ud = _t(u)
+    ctx.steady(ud, cfl_max=1000.0, tol=0.0, max_iter=4, check_every=1, m=30, scheme="exp1")
+    ctx.set_krylov_adapt(0)
+    ctx.set_krylov_tol(0.0)
+    want, hist = steady_iterations(g, ExactJacobian(g), u, 4, 1000.0, 30, "exp1", krylov_tol=1e-5,
+                                   krylov_every=3)
+    assert rel(ud.cpu().numpy(), want) < 1e-9

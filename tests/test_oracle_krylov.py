@@ -271,3 +271,67 @@ def test_krylov_dt_control_meets_tolerance():
     M[:n, n] = b
     exact = dt * expm(M)[:n, n]
     assert np.linalg.norm(x - exact) / np.linalg.norm(exact) < 1e-5
+
+
+def test_krylov_adaptive_dimension_meets_tolerance():
+    """Adaptive dimension: the run stops at the first checked j whose estimate
+    meets tol; the stopped approximation is within a small multiple of tol
+    of the dense phi_1 (scipy.linalg.expm of the augmented full matrix), and
+    a dimension one check earlier is not."""
+    from scipy.linalg import expm
+    rng = np.random.default_rng(14)
+    n = 90
+    A = rng.standard_normal((n, n)) / np.sqrt(n) - 1.5 * np.eye(n)
+    b = rng.standard_normal(n)
+    dt, m, tol, every = 1.0, 40, 1e-8, 3
+    x, dt_used, err, halv, info = krylov.arnoldi_phi1_controlled(lambda v: A @ v, b, dt, m, tol,
+                                                                 check_every=every)
+    meff = info["m_eff"]
+    assert halv == 0 and dt_used == dt and err <= tol
+    assert meff < m and meff % every == 0 and not info["breakdown"]
+    M = np.zeros((n + 1, n + 1))
+    M[:n, :n] = dt * A
+    M[:n, n] = b
+    exact = dt * expm(M)[:n, n]
+    assert np.linalg.norm(x - exact) / np.linalg.norm(exact) < 10 * tol
+    # one check earlier the approximation misses the tolerance
+    V, H, beta, _, _ = krylov.arnoldi_mgs(lambda v: A @ v, b, m)
+    j = meff - every
+    y, _ = krylov.phi1_with_error(H[:j, :j], beta, H[j, j - 1], dt)
+    early = dt * beta * V[:, :j] @ y
+    assert np.linalg.norm(early - exact) / np.linalg.norm(exact) > tol
+
+
+def test_krylov_adaptive_dimension_limits():
+    """A tolerance no dimension below m meets leaves the run at m (the fixed-m
+    result, bit for bit); check_every = 0 never stops early."""
+    rng = np.random.default_rng(15)
+    n = 60
+    A = rng.standard_normal((n, n)) / np.sqrt(n) - 1.0 * np.eye(n)
+    b = rng.standard_normal(n)
+    mv = lambda v: A @ v
+    fixed, _, _, _, i0 = krylov.arnoldi_phi1_controlled(mv, b, 0.5, 12, 1e-30, dt_control=False)
+    for every in (0, 1, 4):
+        x, _, _, _, info = krylov.arnoldi_phi1_controlled(mv, b, 0.5, 12, 1e-30, check_every=every,
+                                                          dt_control=False)
+        assert info["m_eff"] == 12 and np.array_equal(x, fixed)
+    # a loose tolerance stops at the first check
+    x, _, _, _, info = krylov.arnoldi_phi1_controlled(mv, b, 0.5, 12, 1.0, check_every=2, dt_control=False)
+    assert info["m_eff"] == 2
+
+
+def test_pcexp_step_adaptive_dimension_close_to_fixed():
+    """A PCEXP step with the adaptive dimension (tol 1e-9) agrees with the
+    fixed-dimension step to about the tolerance on a linear system, where the
+    fixed step with m = n is exact."""
+    from scipy.linalg import expm
+    rng = np.random.default_rng(16)
+    n = 50
+    A = rng.standard_normal((n, n)) / np.sqrt(n) - 2.0 * np.eye(n)
+    op = DenseSplit(A, A)
+    u0 = rng.standard_normal(n)
+    info = {}
+    u1 = pcexp_step(op, u0, 0.3, 45, krylov_tol=1e-9, krylov_every=2, info=info)
+    assert info["k1"]["m_eff"] < 45 and info["k2"]["m_eff"] < 45
+    exact = expm(0.3 * A) @ u0
+    assert np.linalg.norm(u1 - exact) / np.linalg.norm(exact) < 1e-7
