@@ -686,50 +686,64 @@ void k_gs_close(KState* ks, const double* part, int m, size_t n, hipStream_t st)
 // barriers.  One workgroup; matrices column-major in `mem` (LDS or global).
 constexpr int PHI_T = 256;
 
-__device__ void mat_mul(const double* A, const double* B, double* C, int n) {
-  for (int t = threadIdx.x; t < n * n; t += PHI_T) {
-    const int i = t % n, jj = t / n;
-    double s = 0.0;
-    for (int l = 0; l < n; ++l) s += A[l * n + i] * B[jj * n + l];
-    C[jj * n + i] = s;
+// Small dense products on the matrix cores: C = A B (+ D), np x np column-major
+// (np a multiple of 16), one 16 x 16 output tile per wave at a time,
+// accumulated over k in steps of 4 by v_mfma_f64_16x16x4f64.  Lane l holds
+// A(i, k) with i = l % 16, k = l / 16, B(k, j) with k = l / 16, j = l % 16,
+// and result rows l / 16 + 4 r, r < 4, of column l % 16.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+__device__ void mat_mul_mfma(const double* A, const double* B, const double* D, double* C, int np) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nt = np >> 4;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int tile = wid; tile < nt * nt; tile += PHI_T / 64) {
+    const int ti = tile % nt, tj = tile / nt;
+    mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    const double* a = A + (size_t)lk * np + ti * 16 + li;
+    const double* b = B + (size_t)(tj * 16 + li) * np + lk;
+    for (int k0 = 0; k0 < np; k0 += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[(size_t)k0 * np], b[k0], acc, 0, 0, 0);
+    const int col = tj * 16 + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const size_t t = (size_t)col * np + ti * 16 + lk + 4 * r;
+      C[t] = D ? acc[r] + D[t] : acc[r];
+    }
   }
   __syncthreads();
 }
 
-// C = A * B + D  (D may alias neither A nor B nor C)
-__device__ void mat_mul_add(const double* A, const double* B, const double* D, double* C, int n) {
-  for (int t = threadIdx.x; t < n * n; t += PHI_T) {
-    const int i = t % n, jj = t / n;
-    double s = D[t];
-    for (int l = 0; l < n; ++l) s += A[l * n + i] * B[jj * n + l];
-    C[jj * n + i] = s;
-  }
-  __syncthreads();
-}
-
-// exp(X) for the n x n matrix X = mem[0, n^2) (column-major), n <= 2 KMAX + 2;
-// mem holds 7 n^2 doubles.  Returns a pointer to the result inside mem.
-__device__ double* expm_core(double* mem, int n) {
+// exp(X) for the n x n matrix X = mem[0, n^2) (column-major, leading
+// dimension n), n <= 2 KMAX + 2.  The matrix is zero-padded to np = pad16(n)
+// (exp of [X 0; 0 0] is [exp(X) 0; 0 I]); mem holds 7 np^2 doubles.  Returns
+// a pointer to the result inside mem, with leading dimension *ld = np.
+__device__ double* expm_core(double* mem, int n, int* ld) {
   const int tid = threadIdx.x;
-  const int nn = n * n;
-  double* X = mem;          // scaled A
-  double* X2 = X + nn;
+  const int np = pad16(n);
+  const int nn = np * np;
+  double* X = mem + (size_t)6 * nn;   // scaled, padded A (the input region is read first)
+  double* X2 = mem;
   double* X3 = X2 + nn;
   double* X4 = X3 + nn;
   double* Bq = X4 + nn;     // current block polynomial
   double* T0 = Bq + nn;     // ping-pong accumulators
   double* T1 = T0 + nn;
-  __shared__ double colsum[2 * KMAX + 4];
+  __shared__ double colsum[pad16(2 * KMAX + 2)];
   __shared__ int s_sq;
-  for (int jj = tid; jj < n; jj += PHI_T) {
+  for (int t = tid; t < nn; t += PHI_T) {
+    const int i = t % np, jj = t / np;
+    X[t] = (i < n && jj < n) ? mem[jj * n + i] : 0.0;
+  }
+  __syncthreads();
+  for (int jj = tid; jj < np; jj += PHI_T) {
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += fabs(X[jj * n + i]);
+    for (int i = 0; i < np; ++i) s += fabs(X[jj * np + i]);
     colsum[jj] = s;
   }
   __syncthreads();
   if (tid == 0) {
     double nrm = 0.0;
-    for (int jj = 0; jj < n; ++jj) nrm = fmax(nrm, colsum[jj]);
+    for (int jj = 0; jj < np; ++jj) nrm = fmax(nrm, colsum[jj]);
     // an infinite norm (overflow in H or dt) gets the largest exponent a
     // finite one can have, so the squaring loop stays bounded
     int s = 0;
@@ -741,9 +755,9 @@ __device__ double* expm_core(double* mem, int n) {
   const double sc = ldexp(1.0, -s);
   for (int t = tid; t < nn; t += PHI_T) X[t] *= sc;
   __syncthreads();
-  mat_mul(X, X, X2, n);
-  mat_mul(X2, X, X3, n);
-  mat_mul(X2, X2, X4, n);
+  mat_mul_mfma(X, X, nullptr, X2, np);
+  mat_mul_mfma(X2, X, nullptr, X3, np);
+  mat_mul_mfma(X2, X2, nullptr, X4, np);
   // Taylor coefficients c_k = 1/k!, k = 0..18; blocks B_i = sum_{r<4} c_{4i+r} X^r,
   // T(X) = B_0 + X^4 (B_1 + X^4 (B_2 + X^4 (B_3 + X^4 B_4))), B_4 = c_16 + c_17 X + c_18 X^2
   double c[19];
@@ -753,26 +767,27 @@ __device__ double* expm_core(double* mem, int n) {
     const double a0 = c[4 * i], a1 = (4 * i + 1 < 19) ? c[4 * i + 1] : 0.0;
     const double a2 = (4 * i + 2 < 19) ? c[4 * i + 2] : 0.0, a3 = (4 * i + 3 < 19) ? c[4 * i + 3] : 0.0;
     for (int t = tid; t < nn; t += PHI_T) {
-      const int r = t % n, jj = t / n;
+      const int r = t % np, jj = t / np;
       dst[t] = a1 * X[t] + a2 * X2[t] + a3 * X3[t] + (r == jj ? a0 : 0.0);
     }
     __syncthreads();
   };
-  block(4, T0);                      // T0 = B_4
+  block(4, T0);                          // T0 = B_4
   block(3, Bq);
-  mat_mul_add(X4, T0, Bq, T1, n);    // T1 = B_3 + X^4 B_4
+  mat_mul_mfma(X4, T0, Bq, T1, np);      // T1 = B_3 + X^4 B_4
   block(2, Bq);
-  mat_mul_add(X4, T1, Bq, T0, n);    // T0 = B_2 + X^4 T1
+  mat_mul_mfma(X4, T1, Bq, T0, np);      // T0 = B_2 + X^4 T1
   block(1, Bq);
-  mat_mul_add(X4, T0, Bq, T1, n);    // T1 = B_1 + X^4 T0
+  mat_mul_mfma(X4, T0, Bq, T1, np);      // T1 = B_1 + X^4 T0
   block(0, Bq);
-  mat_mul_add(X4, T1, Bq, T0, n);    // T0 = B_0 + X^4 T1 = T(X)
+  mat_mul_mfma(X4, T1, Bq, T0, np);      // T0 = B_0 + X^4 T1 = T(X)
   double* P = T0;
   double* Q = T1;
   for (int it = 0; it < s; ++it) {
-    mat_mul(P, P, Q, n);
+    mat_mul_mfma(P, P, nullptr, Q, np);
     double* t = P; P = Q; Q = t;
   }
+  *ld = np;
   return P;
 }
 
@@ -800,10 +815,11 @@ __device__ void phi_body(KState* ks, const double* dtp, int k, double* mem) {
     X[t] = v;
   }
   __syncthreads();
-  const double* P = expm_core(mem, n);
+  int ld;
+  const double* P = expm_core(mem, n, &ld);
   const int col = (k >= 1) ? n - 1 : 0;
   const double beta = ks->beta;
-  for (int i = tid; i < KMAX + 4; i += PHI_T) ks->y[i] = (i < m) ? beta * P[col * n + i] : 0.0;
+  for (int i = tid; i < KMAX + 4; i += PHI_T) ks->y[i] = (i < m) ? beta * P[col * ld + i] : 0.0;
 }
 
 // Step-size control by the a-posteriori error of the Krylov approximation of
@@ -819,9 +835,10 @@ __device__ void phi_body(KState* ks, const double* dtp, int k, double* mem) {
 // Saad's a-posteriori estimate of the Krylov approximation of phi_1(dt J) b
 // with dimension m: err = dt h_{m+1,m} |[phi_2(dt H_m) e_1]_m| / |phi_1(dt H_m) e_1|,
 // both phi from the exponential of the augmented (m+2) x (m+2) matrix, which
-// is left in *P (phi_1(dt H_m) e_1 is its column m, rows < m).  Every thread
-// returns err.
-__device__ double krylov_estimate(const KState* ks, double dt, int m, double hnext, double* mem, const double** P) {
+// is left in *P with leading dimension *ldp (phi_1(dt H_m) e_1 is its column
+// m, rows < m).  Every thread returns err.
+__device__ double krylov_estimate(const KState* ks, double dt, int m, double hnext, double* mem, const double** P,
+                                  int* ldp) {
   const int tid = threadIdx.x;
   __shared__ double red[PHI_T / 64];
   const int n = m + 2, nn = n * n;
@@ -838,10 +855,11 @@ __device__ double krylov_estimate(const KState* ks, double dt, int m, double hne
     mem[t] = v;
   }
   __syncthreads();
-  const double* Q = expm_core(mem, n);
+  int ld;
+  const double* Q = expm_core(mem, n, &ld);
   double sq = 0.0;
   for (int i = tid; i < m; i += PHI_T) {
-    const double x = Q[(size_t)m * n + i];
+    const double x = Q[(size_t)m * ld + i];
     sq += x * x;
   }
   sq = wave_sum(sq);
@@ -850,13 +868,14 @@ __device__ double krylov_estimate(const KState* ks, double dt, int m, double hne
   if (tid == 0) {
     double t = 0.0;
     for (int w = 0; w < PHI_T / 64; ++w) t += red[w];
-    const double phi2m = fabs(Q[(size_t)(m + 1) * n + (m - 1)]);
+    const double phi2m = fabs(Q[(size_t)(m + 1) * ld + (m - 1)]);
     red[0] = t > 0.0 ? dt * hnext * phi2m / sqrt(t) : 0.0;
   }
   __syncthreads();
   const double err = red[0];
   __syncthreads();
   *P = Q;
+  *ldp = ld;
   return err;
 }
 
@@ -868,20 +887,20 @@ __device__ void phi_adapt_body(KState* ks, double* dtp, double tol, double* mem)
     if (tid == 0) { ks->norm_tmp[2] = 0.0; ks->norm_tmp[3] = 0.0; }
     return;
   }
-  const int n = m + 2;
   const double hnext = ks->breakdown ? 0.0 : ks->hlast;
   double dt = *dtp;
   int halvings = 0;
   double err = 0.0;
   const double* P = nullptr;
+  int ld = 0;
   for (;;) {
-    err = krylov_estimate(ks, dt, m, hnext, mem, &P);
+    err = krylov_estimate(ks, dt, m, hnext, mem, &P, &ld);
     if (err <= tol || halvings >= 40) break;
     dt *= 0.5;
     ++halvings;
   }
   const double beta = ks->beta;
-  for (int i = tid; i < KMAX + 4; i += PHI_T) ks->y[i] = (i < m) ? beta * P[(size_t)m * n + i] : 0.0;
+  for (int i = tid; i < KMAX + 4; i += PHI_T) ks->y[i] = (i < m) ? beta * P[(size_t)m * ld + i] : 0.0;
   if (tid == 0) {
     *dtp = dt;
     ks->norm_tmp[2] = err;
@@ -898,7 +917,8 @@ __device__ void krylov_check_body(KState* ks, const double* dtp, double tol, int
   if (ks->done) return;
   const double hnext = ks->H[(size_t)(j - 1) * KLD + j];
   const double* P = nullptr;
-  const double err = krylov_estimate(ks, *dtp, j, hnext, mem, &P);
+  int ld;
+  const double err = krylov_estimate(ks, *dtp, j, hnext, mem, &P, &ld);
   if (threadIdx.x == 0 && err <= tol) {
     ks->m_eff = j;
     ks->hlast = hnext;
@@ -919,7 +939,7 @@ __global__ __launch_bounds__(PHI_T) void krylov_check_glb(KState* ks, const doub
 
 void k_krylov_check(KState* ks, const double* dt, double tol, int j, double* scratch, hipStream_t st) {
   const int n = j + 2;
-  const size_t bytes = (size_t)7 * n * n * sizeof(double);
+  const size_t bytes = (size_t)7 * pad16(n) * pad16(n) * sizeof(double);
   if (bytes <= 60 * 1024) launch(krylov_check_lds, dim3(1), dim3(PHI_T), bytes, st, ks, dt, tol, j);
   else launch(krylov_check_glb, dim3(1), dim3(PHI_T), 0, st, ks, dt, tol, j, scratch);
 }
@@ -934,7 +954,7 @@ __global__ __launch_bounds__(PHI_T) void hess_phi_adapt_glb(KState* ks, double* 
 
 void k_hess_phi_adapt(KState* ks, double* dt, double tol, int m, double* scratch, hipStream_t st) {
   const int n = m + 2;
-  const size_t bytes = (size_t)7 * n * n * sizeof(double);
+  const size_t bytes = (size_t)7 * pad16(n) * pad16(n) * sizeof(double);
   if (bytes <= 60 * 1024) launch(hess_phi_adapt_lds, dim3(1), dim3(PHI_T), bytes, st, ks, dt, tol);
   else launch(hess_phi_adapt_glb, dim3(1), dim3(PHI_T), 0, st, ks, dt, tol, scratch);
 }
@@ -949,7 +969,7 @@ __global__ __launch_bounds__(PHI_T) void hess_phi_glb(KState* ks, const double* 
 
 void k_hess_phi(KState* ks, const double* dt, int k, int m, double* scratch, hipStream_t st) {
   const int n = m + (k >= 1 ? k : 0);
-  const size_t bytes = (size_t)7 * n * n * sizeof(double);
+  const size_t bytes = (size_t)7 * pad16(n) * pad16(n) * sizeof(double);
   if (bytes <= 60 * 1024) {
     launch(hess_phi_lds, dim3(1), dim3(PHI_T), bytes, st, ks, dt, k);
   } else {
@@ -1249,10 +1269,11 @@ __global__ __launch_bounds__(PHI_T) void rv_phi_adjoint_kernel(const KState* ks,
     X[t] = v;
   }
   __syncthreads();
-  const double* P = expm_core(mem, n);
+  int ld;
+  const double* P = expm_core(mem, n, &ld);
   for (int t = tid; t < M * M; t += PHI_T) {
     const int i = t % M, jj = t / M;
-    if (i <= jj + 1) rs->Hbar[(size_t)jj * KLD + i] = dt * P[(size_t)(n1 + jj) * n + i];
+    if (i <= jj + 1) rs->Hbar[(size_t)jj * KLD + i] = dt * P[(size_t)(n1 + jj) * ld + i];
   }
 }
 
