@@ -66,7 +66,8 @@ typedef enum { PCEXP_PREC_F64 = 0, PCEXP_PREC_MIXED = 1 } pcexp_prec_kind;
 typedef enum { PCEXP_JVP_TANGENT = 0, PCEXP_JVP_FD = 1, PCEXP_JVP_ZERO = 2 } pcexp_jvp_kind;
 
 /* PCEXP: eqs. (s9)-(s10).  EXP1: first stage only, eq. (s8). */
-typedef enum { PCEXP_SCHEME_PCEXP = 0, PCEXP_SCHEME_EXP1 = 1 } pcexp_scheme_kind;
+typedef enum { PCEXP_SCHEME_PCEXP = 0, PCEXP_SCHEME_EXP1 = 1, PCEXP_SCHEME_ETD2 = 2 /* pcexp_step_etd2 only */ }
+    pcexp_scheme_kind;
 
 /* Boundary tags: slip wall (mirror ghost state), Riemann-invariant far field. */
 typedef enum { PCEXP_BC_SLIP = 1, PCEXP_BC_FARFIELD = 2 } pcexp_bc_kind;
@@ -200,6 +201,25 @@ pcexp_status pcexp_arnoldi_phi(pcexp_ctx* ctx, const double* u_lin, const double
 pcexp_status pcexp_step(pcexp_ctx* ctx, double* u, double dt, double cfl, int32_t m,
                         int32_t scheme, int32_t prec, int32_t jvp, void* ws, size_t ws_bytes,
                         pcexp_step_info* info, void* stream);
+
+/* ETD2 step, eq. (s7) (the second-order exponential time differencing
+ * variant of Sec. 2, not the PCEXP scheme):
+ *   u_{n+1} = u_n + dt Phi_1(dt J_n) R_n + dt Phi_2(dt J_n) (N_n - N_{n-1}),
+ * with N = R - J_n u on the step (the split of eq. (s3)), so
+ * N_n - N_{n-1} = R_n - R_{n-1} - J_n (u_n - u_{n-1}): two Arnoldi runs (phi_1
+ * of R_n, phi_2 of the difference) and one JVP.  u (in/out), u_prev and
+ * r_prev are device FP64 arrays in ABI layout, K entries each, caller-owned
+ * and distinct.  With have_prev != 0 they hold u_{n-1} and R(u_{n-1}) on entry;
+ * with have_prev == 0 the step is ETD1, eq. (s8).  On return they hold u_n and
+ * R(u_n) for the next call.  dt > 0 fixed (the difference quotient assumes a
+ * constant step); FP64 only (prec is implied); jvp as for pcexp_step.
+ * Workspace as for pcexp_step with the same m (pcexp_workspace_bytes with
+ * k = 1, FP64).  info (optional): k1 the phi_1 run, k2 the phi_2 run (zero
+ * without history); synchronises when given.  Errors: PCEXP_E_ARG for
+ * missing, aliased or bad arguments, PCEXP_E_WORKSPACE as pcexp_step. */
+pcexp_status pcexp_step_etd2(pcexp_ctx* ctx, double* u, double* u_prev, double* r_prev, int32_t have_prev,
+                             double dt, int32_t m, int32_t jvp, void* ws, size_t ws_bytes,
+                             pcexp_step_info* info, void* stream);
 
 /* Objective for reverse-mode tests: value_host = int_Omega (p_h - p_ref)^2 dx
  * by the volume quadrature rule, p = (gamma-1)(rho E - |rho v|^2 / (2 rho))

@@ -90,6 +90,29 @@ def pcexp_step(op, u, dt, m, scheme="pcexp", eta=1e-12, info=None, krylov_tol=0.
     return unext
 
 
+def etd2_step(op, u, u_prev, R_prev, dt, m, eta=1e-12, info=None):
+    """One ETD2 step, eq. (s7): u_{n+1} = u_n + dt Phi_1(dt J_n) R_n
+    + dt Phi_2(dt J_n)(N_n - N_{n-1}) with N = R - J_n u on the step (the
+    split of eq. (s3)), so N_n - N_{n-1} = R_n - R_{n-1} - J_n (u_n - u_{n-1}).
+    Without history (u_prev None) the step is ETD1, eq. (s8).  Returns
+    (u_{n+1}, R_n) so that the caller can pass (u_n, R_n) as the next history."""
+    u = np.asarray(u)
+    shape = u.shape
+    Rn = op.residual(u)
+    mv = lambda v: op.jvp(u, np.reshape(v, shape), Rn)
+    x1, i1 = krylov.arnoldi_phi(mv, Rn, dt, 1, m, eta, return_info=True)
+    unext = u + dt * x1
+    if info is not None:
+        info["k1"] = i1
+    if u_prev is None:
+        return unext, Rn
+    d = Rn - R_prev - op.jvp(u, u - u_prev, Rn)
+    x2, i2 = krylov.arnoldi_phi(mv, d, dt, 2, m, eta, return_info=True)
+    if info is not None:
+        info["k2"] = i2
+    return unext + dt * x2, Rn
+
+
 def heun_step(op, u, dt):
     """Second-order Runge-Kutta (Heun): the J -> 0 limit of PCEXP (eq. (rk2))."""
     Rn = op.residual(u)

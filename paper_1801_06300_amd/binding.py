@@ -92,6 +92,8 @@ _SIGS = {
     "pcexp_profile": (ctypes.c_int, [_VP, ctypes.c_int32, c_double_p]),
     "pcexp_set_krylov_tol": (ctypes.c_int, [_VP, ctypes.c_double]),
     "pcexp_set_krylov_adapt": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "pcexp_step_etd2": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                       ctypes.c_int32, _VP, ctypes.c_size_t, _VP, _VP]),
     "pcexp_steady": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
                                     ctypes.c_size_t, ctypes.POINTER(SteadyInfo), _VP]),
@@ -358,6 +360,20 @@ class PCEXP:
                                           int(check_every), m, SCHEME[scheme], PREC[prec], JVP[jvp], _ptr(ws),
                                           nbytes, ctypes.byref(inf), self._stream()), "steady")
         return inf.as_dict()
+
+    def step_etd2(self, u, u_prev, r_prev, have_prev, dt, m=30, jvp="tangent", info=False):
+        """ETD2 step (eq. (s7)) in place; u_prev / r_prev hold u_{n-1}, R(u_{n-1})
+        when have_prev and are refreshed with u_n, R(u_n) (all contiguous FP64
+        device tensors of the state's shape)."""
+        for t in (u, u_prev, r_prev):
+            if not (t.is_cuda and t.dtype == self.torch.float64 and t.is_contiguous()):
+                raise ValueError("step_etd2: pass contiguous float64 device tensors")
+        ws, nbytes = self.workspace(m, 1, "f64", jvp)
+        inf = StepInfo()
+        self._check(self.lib.pcexp_step_etd2(self.ctx, _ptr(u), _ptr(u_prev), _ptr(r_prev), int(bool(have_prev)),
+                                             float(dt), m, JVP[jvp], _ptr(ws), nbytes,
+                                             ctypes.byref(inf) if info else None, self._stream()), "step_etd2")
+        return inf.as_dict() if info else None
 
     def step(self, u, dt=0.0, cfl=0.0, m=30, scheme="pcexp", prec="f64", jvp="tangent", info=False):
         """u_n -> u_{n+1} in place (u must be a contiguous FP64 device tensor)."""

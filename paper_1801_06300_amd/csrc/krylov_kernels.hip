@@ -1061,7 +1061,7 @@ void k_fd_eps(const double* unorm, const double* vnorm, double c0, double* eps, 
 template <typename TC>
 __global__ void glue_kernel(const double* a, const double* b, const TC* c, double* out, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    out[i] = a[i] - b[i] - (double)c[i];
+    out[i] = a[i] - b[i] - (c ? (double)c[i] : 0.0);
 }
 template <typename TC>
 void k_glue_d(const double* a, const double* b, const TC* c, double* out, size_t n, hipStream_t st) {

@@ -124,7 +124,7 @@ void k_sumsq(const double* x, size_t n, double* out, int mode, double* part, uns
              hipStream_t st);
 // eps = c0 * (1 + *unorm) / *vnorm, or c0*(1 + *unorm) if vnorm == NULL
 void k_fd_eps(const double* unorm, const double* vnorm, double c0, double* eps, hipStream_t st);
-// out = a - b - c  (double a, b; c of type TC)
+// out = a - b - c  (double a, b; c of type TC, or NULL for 0)
 template <typename TC>
 void k_glue_d(const double* a, const double* b, const TC* c, double* out, size_t n, hipStream_t st);
 void k_set_scalar(double* p, double v, hipStream_t st);

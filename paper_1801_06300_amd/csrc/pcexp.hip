@@ -780,10 +780,18 @@ __global__ void cfl_ramp_kernel(const double* rsqrt, double inv_vol, int n, int 
   *rnorm = r;
 }
 
+// History of an ETD2 step (ABI layout, caller-owned): u_{n-1} and R(u_{n-1}),
+// read when have_prev, then overwritten with u_n and R(u_n).
+struct Etd2Hist {
+  double* u_prev;
+  double* r_prev;
+  int have_prev;
+};
+
 // One step on internal vectors: un (u_n) is replaced by u_{n+1}.  scal[0] = dt,
 // scal[4] = ||R(rho_n)|| (ramp mode), scal[5] = CFL used (ramp mode).
 pcexp_status step_core(pcexp_ctx* c, double* un, const DtMode& dm, int m, int scheme, int prec, int jvp, char* w,
-                       const WsLayout& L, hipStream_t st) {
+                       const WsLayout& L, hipStream_t st, const Etd2Hist* hist = nullptr) {
   KState* ks1 = (KState*)(w + L.ks1);
   KState* ks2 = (KState*)(w + L.ks2);
   double* part = (double*)(w + L.part);
@@ -813,6 +821,19 @@ pcexp_status step_core(pcexp_ctx* c, double* un, const DtMode& dm, int m, int sc
   const bool mixed = (prec == PCEXP_PREC_MIXED);
   if (mixed) k_cast<double, float>(un, un32, n, st);
 
+  // ETD2 (eq. (s7)): take u_{n-1}, R_{n-1} into internal storage (x1 is not
+  // needed by the predictor of this scheme), then leave u_n, R_n as history
+  const bool etd2 = scheme == PCEXP_SCHEME_ETD2;
+  double* up = (double*)x1;
+  if (etd2) {
+    if (hist->have_prev) {
+      to_int(c, hist->u_prev, up, st);
+      to_int(c, hist->r_prev, Rs, st);
+    }
+    to_abi(c, un, hist->u_prev, st);
+    to_abi(c, Rn, hist->r_prev, st);
+  }
+
   // stage 1: x1 = dt Phi_1(dt J_n) R_n; u* = u_n + x1 (EXP1: the result, written over u_n)
   double* out1 = exp1 ? un : us;
   if (mixed) {
@@ -820,15 +841,41 @@ pcexp_status step_core(pcexp_ctx* c, double* un, const DtMode& dm, int m, int sc
     arnoldi_run<float>(c, jvp, prec, un, un32, Rn, Rn, dtp, 1, m, ks1, part, phi, V, st, c->krylov_tol, true,
                        c->krylov_every);
     Prof pr(c, st, PC_COMB, (double)c->K * (m * 4.0 + 8 + 8 + 4));
-    k_combine<float, float>(V, c->Kld, ks1, un, out1, exp1 ? (float*)nullptr : (float*)x1, 1.0, dtp, n, st);
+    k_combine<float, float>(V, c->Kld, ks1, un, out1, (exp1 || etd2) ? (float*)nullptr : (float*)x1, 1.0, dtp, n,
+                            st);
   } else {
     double* V = (double*)(w + L.V);
     arnoldi_run<double>(c, jvp, prec, un, nullptr, Rn, Rn, dtp, 1, m, ks1, part, phi, V, st, c->krylov_tol, true,
                         c->krylov_every);
     Prof pr(c, st, PC_COMB, (double)c->K * (m * 8.0 + 8 + 8 + 8));
-    k_combine<double, double>(V, c->Kld, ks1, un, out1, exp1 ? (double*)nullptr : (double*)x1, 1.0, dtp, n, st);
+    k_combine<double, double>(V, c->Kld, ks1, un, out1, (exp1 || etd2) ? (double*)nullptr : (double*)x1, 1.0,
+                              dtp, n, st);
   }
   if (exp1) return PCEXP_OK;
+
+  if (etd2) {
+    if (!hist->have_prev) {   // first step: ETD1, eq. (s8)
+      if (hipMemcpyAsync(un, us, n * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return fail(c, PCEXP_E_HIP, "copy failed");
+      return PCEXP_OK;
+    }
+    // N_n - N_{n-1} = R_n - R_{n-1} - J_n (u_n - u_{n-1}) (N = R - J_n u on this step)
+    k_glue_d<double>(un, up, (const double*)nullptr, up, n, st);
+    double* jx = (double*)(w + L.V);
+    if (jvp == PCEXP_JVP_FD) {
+      k_sumsq(un, n, &scal[1], 1, part, &cnt[1], st);
+      k_sumsq(up, n, &scal[2], 1, part, &cnt[2], st);
+      k_fd_eps(&scal[1], &scal[2], kSqrtEps, &scal[3], st);
+    }
+    jvp_int(c, jvp, prec, un, nullptr, up, jx, nullptr, nullptr, Rn, &scal[3], st);
+    k_glue_d<double>(Rn, Rs, jx, Rs, n, st);
+    // u_{n+1} = u* + dt Phi_2(dt J_n)(N_n - N_{n-1})
+    double* V = (double*)(w + L.V);
+    arnoldi_run<double>(c, jvp, prec, un, nullptr, Rs, Rn, dtp, 2, m, ks2, part, phi, V, st);
+    Prof pr(c, st, PC_COMB, (double)c->K * (m * 8.0 + 8 + 8));
+    k_combine<double, double>(V, c->Kld, ks2, us, un, (double*)nullptr, 1.0, dtp, n, st);
+    return PCEXP_OK;
+  }
 
   // N* - N_n = R(u*) - R_n - J_n x1
   if (!residual_int(c, us, Rs, st)) return fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
@@ -928,6 +975,46 @@ pcexp_status pcexp_step(pcexp_ctx* c, double* u, double dt, double cfl, int32_t 
     if (scheme == PCEXP_SCHEME_PCEXP) fill_info(&info->k2, h2);
     info->dt = sc[0];
     info->res_rho_norm = c->dense ? 0.0 : sc[4] / c->volume_total;
+    return report_flags(c, &info->flags);
+  }
+  return PCEXP_OK;
+}
+
+pcexp_status pcexp_step_etd2(pcexp_ctx* c, double* u, double* u_prev, double* r_prev, int32_t have_prev, double dt,
+                             int32_t m, int32_t jvp, void* ws, size_t ws_bytes, pcexp_step_info* info, void* stream) {
+  pcexp_status s = check_common(c, m, 1, PCEXP_PREC_F64, jvp, ws, ws_bytes);
+  if (s != PCEXP_OK) return s;
+  if (!u || !u_prev || !r_prev) return fail(c, PCEXP_E_ARG, "u, u_prev and r_prev are required");
+  if (u == u_prev || u == r_prev || u_prev == r_prev) return fail(c, PCEXP_E_ARG, "u, u_prev, r_prev must differ");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, PCEXP_E_ARG, "ETD2 needs a fixed dt > 0");
+  hipStream_t st = (hipStream_t)stream;
+  const WsLayout L = ws_layout(c, m, 1, PCEXP_PREC_F64);
+  char* w = (char*)ws;
+  double* scal = (double*)(w + L.scal);
+  double* un = (double*)(w + L.un);
+  unsigned* cnt = (unsigned*)(w + L.cnt);
+  k_fill<unsigned>(cnt, 0u, 64, nullptr, st);
+  to_int(c, u, un, st);
+  DtMode dm;
+  dm.dt = dt;
+  const Etd2Hist hist{u_prev, r_prev, have_prev != 0};
+  s = step_core(c, un, dm, m, PCEXP_SCHEME_ETD2, PCEXP_PREC_F64, jvp, w, L, st, &hist);
+  if (s != PCEXP_OK) return s;
+  to_abi(c, un, u, st);
+  s = hip_check(c, "step_etd2");
+  if (s != PCEXP_OK) return s;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    KState h1, h2;
+    double sc[8];
+    if (hipMemcpyAsync(&h1, (KState*)(w + L.ks1), sizeof(KState), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&h2, (KState*)(w + L.ks2), sizeof(KState), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(sc, scal, sizeof(sc), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return fail(c, PCEXP_E_HIP, "info sync failed");
+    fill_info(&info->k1, h1);
+    if (have_prev) fill_info(&info->k2, h2);
+    info->dt = sc[0];
     return report_flags(c, &info->flags);
   }
   return PCEXP_OK;

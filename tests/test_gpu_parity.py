@@ -309,3 +309,47 @@ def test_unphysical_flag():
     R = ctx.residual(_t(bad))
     with pytest.raises(PcexpError):
         ctx.step(_t(bad), dt=0.01, m=4, info=True)
+
+
+# ------------------------------------------------------------------ ETD2
+def _etd2_oracle(op, u0, dt, m, nsteps):
+    from oracle.integrators import etd2_step
+    u, up, Rp = np.array(u0), None, None
+    for _ in range(nsteps):
+        unew, Rn = etd2_step(op, u, up, Rp, dt, m)
+        up, Rp, u = u, Rn, unew
+    return u, up, Rp
+
+
+def test_step_etd2_parity_dense():
+    """Three ETD2 steps (eq. (s7); the first is ETD1) on a split operator whose
+    part outside J makes the scheme inexact; the history buffers hold u_n and
+    R(u_n) afterwards."""
+    PCEXP = _dev()
+    print("\n[case] etd2 dense n=24", flush=True)
+    rng = np.random.default_rng(31)
+    n = 24
+    A = rng.standard_normal((n, n)) / np.sqrt(n) - 2.0 * np.eye(n)
+    B = 0.3 * rng.standard_normal((n, n)) / np.sqrt(n)
+    u0 = rng.standard_normal(n)
+    ctx = PCEXP.dense(A, A + B)
+    u, up, rp = _t(u0), _t(np.zeros(n)), _t(np.zeros(n))
+    for i in range(3):
+        ctx.step_etd2(u, up, rp, i > 0, 0.25, m=20)
+    want, wup, wrp = _etd2_oracle(DenseSplit(A, A + B), u0, 0.25, 20, 3)
+    assert rel(_n(u), want) < 1e-12
+    assert rel(_n(up), wup) < 1e-13 and rel(_n(rp), wrp) < 1e-12
+
+
+def test_step_etd2_parity_dg():
+    """Three ETD2 steps with the tangent JVP on the jittered 4x4 P2 Roe vortex."""
+    from oracle.integrators import stable_dt
+    g, ctx, u = _pair("sq4j", 2, "roe", amp=1e-3)
+    dt = stable_dt(g, u, 5.0)
+    ud, up, rp = _t(u), _t(np.zeros_like(u)), _t(np.zeros_like(u))
+    for i in range(3):
+        info = ctx.step_etd2(ud, up, rp, i > 0, dt, m=30, info=True)
+    print(f"[etd2] m_eff {info['k1']['m_eff']}/{info['k2']['m_eff']}", flush=True)
+    want, wup, wrp = _etd2_oracle(ExactJacobian(g), u, dt, 30, 3)
+    assert rel(_n(ud), want) < 1e-10
+    assert rel(_n(up), wup) < 1e-12 and rel(_n(rp), wrp) < 1e-10

@@ -335,3 +335,79 @@ def test_pcexp_step_adaptive_dimension_close_to_fixed():
     assert info["k1"]["m_eff"] < 45 and info["k2"]["m_eff"] < 45
     exact = expm(0.3 * A) @ u0
     assert np.linalg.norm(u1 - exact) / np.linalg.norm(exact) < 1e-7
+
+
+class _Quadratic:
+    """u' = A u + c * u * u (elementwise) with J = A: the linear part is treated
+    exponentially and N = c u * u explicitly (the classical exponential time
+    differencing setting, where ETD1 is first order and ETD2 second)."""
+
+    def __init__(self, A, c):
+        self.A, self.c = np.asarray(A, float), float(c)
+
+    def residual(self, u):
+        return self.A @ u + self.c * u * u
+
+    def jvp(self, u, v, R=None):
+        return self.A @ v
+
+
+def _etd2_run(op, u0, dt, nsteps, m):
+    from oracle.integrators import etd2_step
+    u, up, Rp = np.array(u0, float), None, None
+    for _ in range(nsteps):
+        unew, Rn = etd2_step(op, u, up, Rp, dt, m)
+        up, Rp, u = u, Rn, unew
+    return u
+
+
+def test_etd2_exact_on_linear_systems():
+    """Eq. (s7) with no nonlinear part (N_n - N_{n-1} = 0): ETD2 is exact."""
+    rng = np.random.default_rng(21)
+    n = 16
+    A = rng.standard_normal((n, n)) - 4 * np.eye(n)
+    u0 = rng.standard_normal(n)
+    got = _etd2_run(DenseSplit(A, A), u0, 0.3, 3, n)
+    want = expm(0.9 * A) @ u0
+    assert np.linalg.norm(got - want) < 1e-12 * np.linalg.norm(want)
+
+
+def test_etd2_first_step_is_etd1():
+    """Without history the step is ETD1, eq. (s8) (the EXP1 predictor)."""
+    from oracle.integrators import etd2_step
+    g, u = _tiny("roe", 1, 3)
+    op = ExactJacobian(g)
+    dt = stable_dt(g, u, 2.0)
+    got, _ = etd2_step(op, u, None, None, dt, 12)
+    want = pcexp_step(op, u, dt, 12, scheme="exp1")
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("case", ["scalar", "system"])
+def test_etd2_temporal_order_two(case):
+    """With J the linear part and N = c u * u explicit, ETD2 converges like
+    dt^2 and ETD1 like dt: u' = -u/2 - u^2 (exact: the logistic solution
+    a u0 e^{-at} / (a + u0 (1 - e^{-at})), a = 1/2) and a 4 x 4 system
+    (reference: ETD2 at a 32x smaller step).  A missing or sign-flipped
+    difference term would leave first order."""
+    T = 2.0
+    if case == "scalar":
+        a = 0.5
+        op, u0, m = _Quadratic([[-a]], -1.0), np.array([1.0]), 1
+        ref = a * u0 * np.exp(-a * T) / (a + u0 * (1.0 - np.exp(-a * T)))
+    else:
+        rng = np.random.default_rng(22)
+        A = rng.standard_normal((4, 4)) * 0.5 - 1.0 * np.eye(4)
+        op, u0, m = _Quadratic(A, 0.3), rng.standard_normal(4), 4
+        ref = _etd2_run(op, u0, T / 2048, 2048, m)
+    e2, e1 = [], []
+    for nsteps in (16, 32, 64):
+        dt = T / nsteps
+        e2.append(np.linalg.norm(_etd2_run(op, u0, dt, nsteps, m) - ref))
+        u = u0.copy()
+        for _ in range(nsteps):
+            u = pcexp_step(op, u, dt, m, scheme="exp1")
+        e1.append(np.linalg.norm(u - ref))
+    r2 = np.log2(np.array(e2[:-1]) / np.array(e2[1:]))
+    r1 = np.log2(np.array(e1[:-1]) / np.array(e1[1:]))
+    assert np.all(r2 > 1.8) and np.all(r1 < 1.3) and np.all(r1 > 0.8), (e2, r2, e1, r1)
