@@ -623,6 +623,10 @@ struct VjpTile {
   using Sh = Shape<D, P>;
   static constexpr int NX = (Sh::NQ > Sh::NF * Sh::NFQ ? Sh::NQ : Sh::NF * Sh::NFQ) * Sh::NV;
   static constexpr int per_elem = (int)sizeof(ST) * (Sh::NVB + NX) + 8 * Sh::NVB + Sh::NF;
+  // derivative directions per flux evaluation: the whole Jacobian at once
+  // for first order; one column at a time for the nested second-order
+  // scalars, whose NV-direction form does not fit the register file
+  static constexpr int NC = std::is_same<ST, double>::value ? Sh::NV : 1;
   static constexpr int TE = (64 * per_elem <= kLdsBudget) ? 64
                             : (32 * per_elem <= kLdsBudget) ? 32
                             : (16 * per_elem <= kLdsBudget) ? 16
@@ -643,7 +647,24 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
   constexpr int NX = VjpTile<D, P, FLUX, ST>::NX;
   constexpr int NT = 256;
   constexpr int NOUT = (NVB * TE + NT - 1) / NT;
-  using SD = Dual<ST, NV>;
+  constexpr int NC = VjpTile<D, P, FLUX, ST>::NC;
+  using SD = Dual<ST, NC>;
+  // The passes over the derivative directions are kept apart (not unrolled)
+  // so that only one pass's duals are live; Ub is indexed through selects.
+  auto add_dir = [](ST* Ub, int j, ST x) {
+#pragma unroll
+    for (int jj = 0; jj < NV; ++jj)
+      if (jj == j) Ub[jj] = Ub[jj] + x;
+  };
+  // U_k with derivative directions j0 .. j0 + NC - 1 seeded on the state
+  auto seed = [](const ST* val, int j0, SD* U) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      U[k].v = val[k];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) U[k].d[c] = ST((k == j0 + c) ? 1.0 : 0.0);
+    }
+  };
 
   __shared__ ST su[NVB * TE];
   __shared__ T sw[NVB * TE];
@@ -671,34 +692,45 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
     const int q = t / TE, e = t % TE, ge = e0 + e;
     if (ge >= nE) continue;
     const T sd = prm.sdet[ge], rs = T(1) / sd;
-    SD U[NV];
+    ST Uv[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       ST a = ST(0);
 #pragma unroll
       for (int i = 0; i < NB; ++i) a = a + su[(k * NB + i) * TE + e] * prm.B[q * NB + i];
-      U[k].v = a * rs;
-#pragma unroll
-      for (int j = 0; j < NV; ++j) U[k].d[j] = ST((j == k) ? 1.0 : 0.0);
+      Uv[k] = a * rs;
     }
+    T gb[D][NV];   // test-function weights of the volume term
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        T g = T(0);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) g += sw[(k * NB + i) * TE + e] * prm.Dg[(q * NB + i) * D + r];
+        gb[r][k] = g * sd * prm.wq[q];
+      }
     ST Ub[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) Ub[j] = ST(0);
+#pragma unroll 1
+    for (int j0 = 0; j0 < NV; j0 += NC) {
+      SD U[NV];
+      seed(Uv, j0, U);
 #pragma unroll
-    for (int r = 0; r < D; ++r) {
-      T a[D];
+      for (int r = 0; r < D; ++r) {
+        T a[D];
 #pragma unroll
-      for (int c = 0; c < D; ++c) a[c] = prm.ainv[(size_t)(r * D + c) * Epad + ge];
-      SD F[NV];
-      normal_flux<D>(U, a, gm1, F);
+        for (int c = 0; c < D; ++c) a[c] = prm.ainv[(size_t)(r * D + c) * Epad + ge];
+        SD F[NV];
+        normal_flux<D>(U, a, gm1, F);
 #pragma unroll
-      for (int k = 0; k < NV; ++k) {
-        T gb = T(0);
+        for (int c = 0; c < NC; ++c) {
+          ST x = ST(0);
 #pragma unroll
-        for (int i = 0; i < NB; ++i) gb += sw[(k * NB + i) * TE + e] * prm.Dg[(q * NB + i) * D + r];
-        gb *= sd * prm.wq[q];
-#pragma unroll
-        for (int j = 0; j < NV; ++j) Ub[j] = Ub[j] + F[k].d[j] * gb;
+          for (int k = 0; k < NV; ++k) x = x + F[k].d[c] * gb[r][k];
+          add_dir(Ub, j0 + c, x);
+        }
       }
     }
 #pragma unroll
@@ -728,7 +760,7 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
     if (r == 0) sori[f * TE + e] = (unsigned char)oE;
     const T sd = prm.sdet[ge], rs = T(1) / sd;
     const T* bl = prm.Bf + ((f * NORI + oE) * NFQ + r) * NB;
-    SD UE[NV];
+    ST UEv[NV];
     T wl[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -739,9 +771,7 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
         a = a + su[(k * NB + i) * TE + e] * bl[i];
         b += sw[(k * NB + i) * TE + e] * bl[i];
       }
-      UE[k].v = a * rs;
-#pragma unroll
-      for (int j = 0; j < NV; ++j) UE[k].d[j] = ST((j == k) ? 1.0 : 0.0);
+      UEv[k] = a * rs;
       wl[k] = b;
     }
     T nl[D], len2 = T(0);
@@ -758,12 +788,14 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
 #pragma unroll
     for (int c = 0; c < D; ++c) n[c] = nl[c] / len;
     ST Ub[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) Ub[j] = ST(0);
     const T cs = -prm.wf[r] * len * rs;   // seed scale of the own face term
     if (nb >= 0) {
       const int fN = info & 3, oN = (info >> 2) & 7;
       const T* br = prm.Bf + ((fN * NORI + oN) * NFQ + r) * NB;
       const T sN = prm.sdet[nb], rsN = T(1) / sN;
-      SD UN[NV];
+      ST UNv[NV];
       T wn[NV];
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
@@ -775,17 +807,8 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
           a = a + SS::make(u[g], SS::SECOND ? vdir[g] : T(0)) * br[i];
           b += w[g] * br[i];
         }
-        UN[k] = mkconst<ST, NV>(a * rsN);
+        UNv[k] = a * rsN;
         wn[k] = b;
-      }
-      SD F[NV];
-      num_flux<D, FLUX>(UE, UN, n, prm.gamma, F);
-#pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        ST s = ST(0);
-#pragma unroll
-        for (int k = 0; k < NV; ++k) s = s + F[k].d[j] * (cs * wl[k]);
-        Ub[j] = s;
       }
       // neighbour's own geometry: |f|_N n_N = det(A_N) A_N^{-T} nref_{fN}
       T nN[D], l2N = T(0);
@@ -800,26 +823,45 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
       const T lenN = s_sqrt(l2N);
 #pragma unroll
       for (int c = 0; c < D; ++c) nN[c] = nN[c] / lenN;
-      num_flux<D, FLUX>(UN, UE, nN, prm.gamma, F);
       const T cn = -prm.wf[r] * lenN * rsN;
+#pragma unroll 1
+      for (int j0 = 0; j0 < NV; j0 += NC) {
+        SD UE[NV], UN[NV], F[NV];
+        seed(UEv, j0, UE);
 #pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        ST s = ST(0);
+        for (int k = 0; k < NV; ++k) UN[k] = mkconst<ST, NC>(UNv[k]);
+        num_flux<D, FLUX>(UE, UN, n, prm.gamma, F);
 #pragma unroll
-        for (int k = 0; k < NV; ++k) s = s + F[k].d[j] * (cn * wn[k]);
-        Ub[j] = Ub[j] + s;
+        for (int c = 0; c < NC; ++c) {
+          ST x = ST(0);
+#pragma unroll
+          for (int k = 0; k < NV; ++k) x = x + F[k].d[c] * (cs * wl[k]);
+          add_dir(Ub, j0 + c, x);
+        }
+        num_flux<D, FLUX>(UN, UE, nN, prm.gamma, F);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          ST x = ST(0);
+#pragma unroll
+          for (int k = 0; k < NV; ++k) x = x + F[k].d[c] * (cn * wn[k]);
+          add_dir(Ub, j0 + c, x);
+        }
       }
     } else {
-      SD G[NV], F[NV];
-      if (((info >> 8) & 3) == 1) ghost_slip<D>(UE, n, G);
-      else ghost_farfield<D>(UE, n, prm.ff, prm.gamma, G);
-      num_flux<D, FLUX>(UE, G, n, prm.gamma, F);
+#pragma unroll 1
+      for (int j0 = 0; j0 < NV; j0 += NC) {
+        SD UE[NV], G[NV], F[NV];
+        seed(UEv, j0, UE);
+        if (((info >> 8) & 3) == 1) ghost_slip<D>(UE, n, G);
+        else ghost_farfield<D>(UE, n, prm.ff, prm.gamma, G);
+        num_flux<D, FLUX>(UE, G, n, prm.gamma, F);
 #pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        ST s = ST(0);
+        for (int c = 0; c < NC; ++c) {
+          ST x = ST(0);
 #pragma unroll
-        for (int k = 0; k < NV; ++k) s = s + F[k].d[j] * (cs * wl[k]);
-        Ub[j] = s;
+          for (int k = 0; k < NV; ++k) x = x + F[k].d[c] * (cs * wl[k]);
+          add_dir(Ub, j0 + c, x);
+        }
       }
     }
 #pragma unroll
