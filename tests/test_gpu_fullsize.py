@@ -1,0 +1,171 @@
+"""Forward parity at the full 2D workload size, in the launch configuration
+the throughput benchmark times: isentropic vortex on the 128 x 128 x 2
+jittered periodic triangle mesh, DG P2, Roe flux, m = 30, CFL 20, FP64
+tangent JVP (the variants: FD JVP and FP32 tangent).
+
+At this size the oracle needs about 1 s per residual and 1.5 s per JVP, so
+the residual and JVP are compared over the whole vector, and one PCEXP step
+(61 oracle JVPs, about 80 s on one core) is compared over the whole vector
+too.  The oracle's initial state is handed to the device, never the other way
+round.  Tolerances: 1e-11 relative for FP64 JVPs and the step (the
+small-mesh bar).  The residual of this smooth, nearly steady vortex is a small
+difference of flux terms, so summation-order rounding is large relative to it:
+the residual of the uniform free stream (zero in exact arithmetic, same flux
+magnitudes) measures that noise on this mesh (4e-11 of the vortex residual in
+the 2-norm), and the residual bar is ten times that ratio.  The FD
+and FP32 variants against the exact-Jacobian oracle step use 1e-4 relative on
+the increment u_{n+1} - u_n, the bar the small-mesh variant tests use for
+FP32, which also bounds the FD JVP's O(sqrt(eps)) error after it passes
+through phi_1.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.dg import DG
+from oracle.derivatives import jvp_cs, jvp_fd
+from oracle.integrators import pcexp_step, ExactJacobian, stable_dt
+from oracle.diagnostics import conserved_totals
+from tests.helpers import rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+_CACHE = {}
+
+
+def _full():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    if "g" not in _CACHE:
+        from paper_1801_06300_amd import PCEXP
+        cfg = W.get_config(2)
+        print(f"\n[case] {cfg['name']} m={cfg['m']} cfl={cfg['cfl']}", flush=True)
+        mesh = W.build_mesh(cfg)
+        g = DG(mesh, cfg["p"], cfg["flux"])
+        c = cfg["vortex_center"]
+        u0 = g.project(lambda x: W.isentropic_vortex(x, center=c, period=mesh.period))
+        u0 = u0 + W.perturbation(u0.shape, cfg["pert_seed"])
+        R0 = g.residual(u0)
+        u_fs = g.project(lambda x: W.uniform_state(x, W.freestream_prim(2)))
+        R_fs = g.residual(u_fs)
+        floor2 = np.linalg.norm(R_fs) / np.linalg.norm(R0)
+        floorm = np.abs(R_fs).max() / np.abs(R0).max()
+        _CACHE.update(cfg=cfg, g=g, u0=u0, R0=R0, ctx=PCEXP(mesh, cfg["p"], cfg["flux"]),
+                      dt=stable_dt(g, u0, cfg["cfl"]), tol_r=max(1e-11, 10 * floor2),
+                      tol_rmax=max(1e-11, 10 * floorm))
+    return _CACHE
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+class _Progress(ExactJacobian):
+    """The oracle's exact-Jacobian operator, printing a line every ten JVPs so
+    that the long oracle step shows it is running."""
+
+    def __init__(self, dg):
+        super().__init__(dg)
+        self.calls = 0
+
+    def jvp(self, u_lin, v, R_lin=None):
+        self.calls += 1
+        if self.calls % 10 == 0:
+            print(f"[oracle] {self.calls} JVPs", flush=True)
+            sys.stdout.flush()
+        return super().jvp(u_lin, v, R_lin)
+
+
+def _oracle_step():
+    c = _full()
+    if "step" not in c:
+        info = {}
+        c["step"] = pcexp_step(_Progress(c["g"]), c["u0"], c["dt"], c["cfg"]["m"], info=info)
+        c["step_info"] = info
+    return c["step"], c["step_info"]
+
+
+def test_fullsize_residual_and_jvps():
+    c = _full()
+    g, ctx, u0 = c["g"], c["ctx"], c["u0"]
+    assert ctx.nE == g.nE == 32768
+    ud = _t(u0)
+    Ro = c["R0"]
+    R = _n(ctx.residual(ud))
+    print(f"[full] residual rel {rel(R, Ro):.3e} (bar {c['tol_r']:.2e}), max "
+          f"{np.max(np.abs(R - Ro)) / np.max(np.abs(Ro)):.3e} (bar {c['tol_rmax']:.2e})", flush=True)
+    assert rel(R, Ro) < c["tol_r"]
+    assert np.max(np.abs(R - Ro)) < c["tol_rmax"] * np.max(np.abs(Ro))
+    v = W.random_unit_vector(u0.shape, 7)
+    vd = _t(v)
+    Jo = jvp_cs(g, u0, v)
+    Jt = _n(ctx.jvp(ud, vd, "tangent", "f64"))
+    print(f"[full] tangent JVP rel {rel(Jt, Jo):.3e}", flush=True)
+    assert rel(Jt, Jo) < 1e-11
+    Jm = _n(ctx.jvp(ud, vd, "tangent", "mixed"))
+    print(f"[full] FP32 tangent JVP rel {rel(Jm, Jo):.3e}", flush=True)
+    assert rel(Jm, Jo) < 1e-5
+    Jf = _n(ctx.jvp(ud, vd, "fd", "f64"))
+    Jfo = jvp_fd(g, u0, v)
+    print(f"[full] FD JVP rel {rel(Jf, Jfo):.3e} (vs exact {rel(Jf, Jo):.3e})", flush=True)
+    assert rel(Jf, Jfo) < 1e-7
+    assert rel(Jf, Jo) < 1e-5
+
+
+def test_fullsize_stable_dt():
+    c = _full()
+    dt = c["ctx"].stable_dt(_t(c["u0"]), c["cfg"]["cfl"])
+    assert abs(dt - c["dt"]) < 1e-14 * c["dt"]
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_pcexp_step():
+    """One PCEXP step, FP64 tangent JVP, m = 30: whole-vector parity, the
+    Krylov dimensions and flags, and conservation of the totals."""
+    c = _full()
+    want, oinfo = _oracle_step()
+    ctx, u0 = c["ctx"], c["u0"]
+    u = _t(u0)
+    info = ctx.step(u, dt=c["dt"], m=c["cfg"]["m"], info=True)
+    got = _n(u)
+    print(f"[full] step rel {rel(got, want):.3e}, increment rel {rel(got - u0, want - u0):.3e}", flush=True)
+    assert rel(got, want) < 1e-11
+    assert rel(got - u0, want - u0) < 1e-9
+    assert info["flags"] == 0
+    assert info["k1"]["m_eff"] == oinfo["k1"]["m_eff"] == c["cfg"]["m"]
+    q0 = conserved_totals(c["g"], u0)
+    q1 = conserved_totals(c["g"], got)
+    assert np.max(np.abs(q1 - q0)) < 1e-12 * np.abs(q0).max()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("jvp,prec", [("fd", "f64"), ("tangent", "mixed")])
+def test_fullsize_step_variants(jvp, prec):
+    c = _full()
+    want, _ = _oracle_step()
+    u0 = c["u0"]
+    u = _t(u0)
+    c["ctx"].step(u, dt=c["dt"], m=c["cfg"]["m"], prec=prec, jvp=jvp)
+    got = _n(u)
+    r = rel(got - u0, want - u0)
+    print(f"[full] {jvp}/{prec} step: increment rel {r:.3e}", flush=True)
+    assert r < 1e-4
+
+
+def test_fullsize_step_determinism():
+    """Two runs of the same step on the device agree bit for bit."""
+    c = _full()
+    a, b = _t(c["u0"]), _t(c["u0"])
+    for x in (a, b):
+        c["ctx"].step(x, dt=c["dt"], m=c["cfg"]["m"])
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
