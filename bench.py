@@ -27,12 +27,14 @@ HBM_PEAK_GBS = 8000.0
 HIP_KERNELS = {
     "residual": "pcexp::dg_apply<2, 2, 1, double, 0, 28, 256>",
     "jvp": "pcexp::dg_apply<2, 2, 1, double, 1, 28, 256>",
-    "gs_reduce": "pcexp::dcgs_reduce<double, NV, PW, CLOSE> (all vector-count buckets)",
+    "gs_reduce": "pcexp::gs_colsum_kernel (each Arnoldi iteration; its dot products run inside the JVP launch) "
+                 "and pcexp::dcgs_reduce<double, NV, PW, true> (closing pass)",
     "gs_update": "pcexp::dcgs_fin_update<double, NV, PW, CV> (all vector-count buckets)",
     "gs_close": "pcexp::dcgs_close_finalize",
     "combine": "pcexp::combine_kernel<double, double>",
 }
-KERNEL_SOURCES = ("dg_kernels.hpp", "dg_physics.hpp", "dg2.hip", "krylov_kernels.hip", "krylov_kernels.hpp")
+KERNEL_SOURCES = ("dg_kernels.hpp", "dg_physics.hpp", "dg2.hip", "krylov_kernels.hip", "krylov_kernels.hpp",
+                  "wave_reduce.hpp", "pcexp.hip")
 
 
 def kernel_source_hash():

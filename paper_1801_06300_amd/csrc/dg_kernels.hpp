@@ -24,6 +24,7 @@
 
 #include "dg_physics.hpp"
 #include "launch.hpp"
+#include "wave_reduce.hpp"
 
 namespace pcexp {
 
@@ -69,6 +70,17 @@ struct DGIO {
   const T* rbase;        // FD: R(u)
   const double* fd_eps;  // FD: increment eps for the (scaled) direction
   unsigned* flags;       // RES: PCEXP_FLAG_* bits
+  // Optional (TAN, FD): the reduction pass of the Arnoldi iteration fused
+  // into this launch.  With gsV set, the block that handles tile b also sums,
+  // over its tile's live elements, V_i.U and V_i.W for the gsj basis vectors
+  // V_i = gsV + i gsld, and U.U, U.W, W.W, where U = v (unscaled) and W = out,
+  // and writes them to gspart[col * gspld + b]: columns [0, gsj) V.U,
+  // [gsj, 2 gsj) V.W, then U.U, U.W, W.W.  gspld >= the launch's block count.
+  const T* gsV;
+  size_t gsld;
+  int gsj;
+  double* gspart;
+  int gspld;
 };
 
 // LDS budget per workgroup (bytes) used to choose the tile size.
@@ -161,6 +173,73 @@ template <> struct Mfma16<float> {
   __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
+// The fused Arnoldi reduction of one tile (see DGIO::gsV).  Thread entries
+// e < NE sit at offsets ix[e] of every vector, with U values u[e] and W
+// values w[e] (zero for entries outside the tile's live elements).  Basis
+// vectors go in chunks of CB: each lane loads its entries of the chunk's
+// vectors together and the wave sums the 2 CB products by the butterfly into
+// its own LDS row (red: NT / 64 rows of GS_ROW slots), so the chunk loop has
+// no barrier; after one barrier, thread c sums column c over the rows in wave
+// order and writes the block's partial.  Row slots: V.U of vector i at i,
+// V.W at GS_SW + i (a chunk past nq writes up to 7 slots beyond, never read),
+// then U.U, U.W, W.W.
+constexpr int GS_MAXQ = 64;   // basis vectors before U, at most (the Krylov dimension bound)
+constexpr int GS_SW = GS_MAXQ + 8;
+constexpr int GS_ROW = 2 * GS_SW + 4;
+template <int NT, int NE, int CB, typename T>
+__device__ __forceinline__ void gs_tile_dots(const T* __restrict__ V, size_t ld, int nq, const int* ix,
+                                             const double* u, const double* w, double* __restrict__ part,
+                                             int pld, double* red) {
+  constexpr int NC = 2 * CB, NWV = NT / 64, RL = GS_ROW;
+  static_assert(CB <= 8, "chunk overhang within the row's slack");
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double* row = red + wid * RL;
+  for (int i0 = 0; i0 < nq; i0 += CB) {
+    T x[CB][NE];
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const int vi = i0 + i < nq ? i0 + i : nq - 1;   // past the last vector: re-read it, result dropped
+      const T* Vi = V + (size_t)vi * ld;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) x[i][e] = Vi[ix[e]];
+    }
+    double a[NC];
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      double su = 0.0, sw = 0.0;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        su += (double)x[i][e] * u[e];
+        sw += (double)x[i][e] * w[e];
+      }
+      a[i] = su;
+      a[CB + i] = sw;
+    }
+    int col = 0;
+    Bfly<NC / 2, 32>::run(a, lane, col);
+    if ((lane & (64 / NC - 1)) == 0) row[(col < CB ? 0 : GS_SW - CB) + i0 + col] = a[0];
+  }
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    a[0] += u[e] * u[e];
+    a[1] += u[e] * w[e];
+    a[2] += w[e] * w[e];
+  }
+  int col = 0;
+  Bfly<2, 32>::run(a, lane, col);
+  if ((lane & 15) == 0) row[2 * GS_SW + col] = a[0];
+  __syncthreads();
+  for (int c = threadIdx.x; c < 2 * nq + 3; c += NT) {
+    // partial column c: [0, nq) V.U, [nq, 2 nq) V.W, then U.U, U.W, W.W
+    const int src = c < nq ? c : c < 2 * nq ? GS_SW + (c - nq) : 2 * GS_SW + (c - 2 * nq);
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < NWV; ++q) s += red[q * RL + src];
+    part[(size_t)c * pld + blockIdx.x] = s;
+  }
+}
+
 template <int D, int P, int FLUX, typename T, int MODE, int TE, int NT>
 __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   using Sh = Shape<D, P>;
@@ -176,7 +255,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
 
   __shared__ T su[NVB * TE];
   __shared__ T sv[DUAL ? NVB * TE : 1];
-  __shared__ T sw[Tl::NW * TE];
+  __shared__ __attribute__((aligned(16))) T sw[Tl::NW * TE];
   __shared__ unsigned char sori[NF * TE];
   __shared__ T stab[Tl::STAGE_TAB ? Tl::NTAB : 1];
   // Per-element geometry.  Neighbours and face codes are staged in LDS.
@@ -568,9 +647,12 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   }
 
   // ---- write (padding elements get zeros)
+  T wo[NOUT][NI];
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
     const int t = tid + o * NT;
+#pragma unroll
+    for (int c = 0; c < NI; ++c) wo[o][c] = T(0);
     if (t < NITEM) {
       const int kg = t / TE, e = t % TE, k = kg / NG, g = kg % NG, ge = e0 + e;
       if (ge < Epad) {
@@ -580,8 +662,39 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
           T v = ge < nE ? acc[o][c] : T(0);
           if (MODE == MODE_FD && ge < nE) v = (v - io.rbase[(size_t)ki * Epad + ge]) / eps;
           io.out[(size_t)ki * Epad + ge] = v;
+          wo[o][c] = v;
         }
       }
+    }
+  }
+
+  // ---- the Arnoldi reduction over this tile (DGIO::gsV)
+  if constexpr (MODE != MODE_RES) {
+    if (io.gsV != nullptr) {
+      constexpr int NE = NOUT * NI;
+      // chunk width: as wide as the epilogue's registers stay within the body's
+      constexpr int GS_CB = (MODE == MODE_TAN && sizeof(T) == 8 && NE <= 3) ? 8 : NE >= 8 ? 2 : 4;
+      // the per-wave rows reuse the flux scratch, free once every wave has left the lift
+      static_assert(sizeof(sw) >= (NT / 64) * GS_ROW * sizeof(double), "flux scratch holds the reduction rows");
+      double* gsred = reinterpret_cast<double*>(sw);
+      __syncthreads();
+      int gix[NE];
+      double gu[NE], gw[NE];
+#pragma unroll
+      for (int o = 0; o < NOUT; ++o) {
+        const int t = tid + o * NT;
+        const int tc = t < NITEM ? t : 0;
+        const int kg = tc / TE, e = tc % TE, k = kg / NG, g = kg % NG, ge = e0 + e;
+        const bool live = t < NITEM && ge < nE;
+#pragma unroll
+        for (int c = 0; c < NI; ++c) {
+          const int ix = live ? (k * NB + g + NG * c) * Epad + ge : 0;
+          gix[o * NI + c] = ix;
+          gu[o * NI + c] = live ? (double)io.v[ix] : 0.0;
+          gw[o * NI + c] = live ? (double)wo[o][c] : 0.0;
+        }
+      }
+      gs_tile_dots<NT, NE, GS_CB>(io.gsV, io.gsld, io.gsj, gix, gu, gw, io.gspart, io.gspld, gsred);
     }
   }
 }

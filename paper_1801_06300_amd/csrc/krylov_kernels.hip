@@ -1,6 +1,7 @@
 // Krylov / Arnoldi and utility kernels (see krylov_kernels.hpp).
 #include "krylov_kernels.hpp"
 #include "launch.hpp"
+#include "wave_reduce.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -205,7 +206,9 @@ __device__ __forceinline__ int clampv(int i, int nq) { return i < nq ? i : (nq >
 // Iteration j.  Final vectors q_i = sigma_i V_i (i < j) are orthonormal; slot j
 // holds U, the once-orthogonalised next vector with tentative scale sigma_j
 // (u = sigma_j U, |u| ~ 1); slot j+1 holds W = J u.
-//   reduce:    V_i.U, V_i.W (i < j), U.U, U.W, W.W             (one pass)
+//   reduce:    V_i.U, V_i.W (i < j), U.U, U.W, W.W             (one pass, or
+//              per tile in the DG tangent kernel that made W, whose
+//              partials gs_colsum_kernel then sums)
 //   finalize:  s = Q^T u, rho^2 = |u|^2 - |s|^2, q_j = (u - Q s)/rho;
 //              column j-1 of H corrected by nu s and nu rho (nu = |U|
 //              estimate of the previous iteration); J q_j = (W - J Q s)/rho
@@ -216,37 +219,7 @@ __device__ __forceinline__ int clampv(int i, int nq) { return i < nq ? i : (nq >
 //              (one pass, both vectors from the same loads)
 // Column j of H stays tentative until the next iteration (or the closing
 // pass) adds nu' s'.
-// Reduce-scatter butterfly over one wave: step (H, O) halves the values a
-// lane holds, sending H of them to lane ^ O and adding the H it receives.
-// After log2(N) steps (N <= 64) a lane holds one column sum; N - 1 shuffles
-// in all instead of 6 per column.  All indices are compile-time constants.
-template <int H, int O>
-struct Bfly {
-  static __device__ __forceinline__ void run(double* a, int lane, int& col) {
-    const bool up = (lane & O) != 0;
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-      const double send = up ? a[i] : a[i + H];
-      const double keep = up ? a[i + H] : a[i];
-      a[i] = keep + __shfl_xor(send, O, 64);
-    }
-    if (up) col += H;
-    Bfly<H / 2, O / 2>::run(a, lane, col);
-  }
-};
-template <int O> struct Bfly<0, O> {          // fewer columns than lanes: finish with plain shuffles
-  static __device__ __forceinline__ void run(double* a, int, int&) {
-#pragma unroll
-    for (int o = O; o >= 1; o /= 2) a[0] += __shfl_xor(a[0], o, 64);
-  }
-};
-template <int H> struct Bfly<H, 0> {
-  static __device__ __forceinline__ void run(double*, int, int&) {}
-};
-template <> struct Bfly<0, 0> {
-  static __device__ __forceinline__ void run(double*, int, int&) {}
-};
-
+// Column sums over a wave use the butterfly of wave_reduce.hpp.
 constexpr int pow2_ceil(int x) { return x <= 4 ? 4 : 2 * pow2_ceil((x + 1) / 2); }
 
 // Largest number of basis vectors one reduction block handles; more live
@@ -642,10 +615,10 @@ static void launch_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, d
 }
 
 template <typename TV>
-static void launch_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st) {
+static void launch_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, int nb,
+                          hipStream_t st) {
   const int nq = j > 0 ? j : 1;
   const dim3 g((unsigned)gs_blocks(n)), b(RT);
-  const int nb = red_blocks(n, nq);
   if (nq <= 4) launch((dcgs_fin_update<TV, 4, 2, 4>), g, b, 0, st, V, ld, j, n, ks, part, nb);
   else if (nq <= 8) launch((dcgs_fin_update<TV, 8, 2, 8>), g, b, 0, st, V, ld, j, n, ks, part, nb);
   else if (nq <= 12) launch((dcgs_fin_update<TV, 12, 2, 12>), g, b, 0, st, V, ld, j, n, ks, part, nb);
@@ -668,7 +641,32 @@ void k_gs_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, double* pa
 
 template <typename TV>
 void k_gs_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st) {
-  launch_update<TV>(V, ld, j, n, ks, part, st);
+  launch_update<TV>(V, ld, j, n, ks, part, red_blocks(n, j > 0 ? j : 1), st);
+}
+
+template <typename TV>
+void k_gs_update_one(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st) {
+  launch_update<TV>(V, ld, j, n, ks, part, 1, st);
+}
+
+// Column c < ncol of fp (nblk partials at stride pld) summed in a fixed order
+// (thread t takes partials t, t + 256, ..., then waves in order) into
+// part[c * PLD]: the one partial per column that k_gs_update_one reads.
+__global__ __launch_bounds__(256) void gs_colsum_kernel(const double* __restrict__ fp, int pld, int nblk,
+                                                        const KState* ks, double* __restrict__ part) {
+  if (ks->done) return;
+  const int c = blockIdx.x;
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256) a += fp[(size_t)c * pld + b];
+  a = wave_sum(a);
+  __shared__ double r[4];
+  if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)c * PLD] = ((r[0] + r[1]) + r[2]) + r[3];
+}
+
+void k_gs_colsum(const double* fp, int pld, int nblk, int ncol, const KState* ks, double* part, hipStream_t st) {
+  launch(gs_colsum_kernel, dim3(ncol), dim3(256), 0, st, fp, pld, nblk, ks, part);
 }
 
 void k_gs_close(KState* ks, const double* part, int m, size_t n, hipStream_t st) {
@@ -1339,6 +1337,8 @@ template void k_gs_reduce<double>(const double*, size_t, int, size_t, KState*, d
 template void k_gs_reduce<float>(const float*, size_t, int, size_t, KState*, double*, bool, hipStream_t);
 template void k_gs_update<double>(double*, size_t, int, size_t, KState*, const double*, hipStream_t);
 template void k_gs_update<float>(float*, size_t, int, size_t, KState*, const double*, hipStream_t);
+template void k_gs_update_one<double>(double*, size_t, int, size_t, KState*, const double*, hipStream_t);
+template void k_gs_update_one<float>(float*, size_t, int, size_t, KState*, const double*, hipStream_t);
 template void k_combine<double, double>(const double*, size_t, const KState*, const double*, double*, double*,
                                         double, const double*, size_t, hipStream_t);
 template void k_combine<float, float>(const float*, size_t, const KState*, const double*, double*, float*,

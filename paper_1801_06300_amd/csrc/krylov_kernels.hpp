@@ -74,6 +74,12 @@ template <typename TV>
 void k_gs_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, double* part, bool close, hipStream_t st);
 template <typename TV>
 void k_gs_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st);
+// The same pass when the reduction left one partial per column (part[c * 512]).
+template <typename TV>
+void k_gs_update_one(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st);
+// Fixed-order sums of columns [0, ncol) of fp (nblk partials each, stride pld)
+// into part[c * 512]; a no-op once ks->done is set.
+void k_gs_colsum(const double* fp, int pld, int nblk, int ncol, const KState* ks, double* part, hipStream_t st);
 void k_gs_close(KState* ks, const double* part, int m, size_t n, hipStream_t st);
 // scratch: >= 7 pad16(m + k)^2 doubles (used when that exceeds the LDS path)
 void k_hess_phi(KState* ks, const double* dt, int k, int m, double* scratch, hipStream_t st);

@@ -198,13 +198,56 @@ bool residual_int(pcexp_ctx* c, const double* u, double* R, hipStream_t st) {
   return dg_run_d(c->dim, c->p, c->flux, MODE_RES, params_d(c), io, st);
 }
 
+// Tiles (workgroups) of the DG tangent / FD launch: its partials per column
+// when the Arnoldi reduction is fused into it.
+template <int D, int P>
+int tile_elems(int jvp, int prec) {
+  if (prec == PCEXP_PREC_MIXED) return Tile<D, P, float, true>::TE;
+  return jvp == PCEXP_JVP_FD ? Tile<D, P, double, false>::TE : Tile<D, P, double, true>::TE;
+}
+template <int D>
+int tile_elems_p(int p, int jvp, int prec) {
+  switch (p) {
+    case 0: return tile_elems<D, 0>(jvp, prec);
+    case 1: return tile_elems<D, 1>(jvp, prec);
+    case 2: return tile_elems<D, 2>(jvp, prec);
+    default: return tile_elems<D, 3>(jvp, prec);
+  }
+}
+int jvp_tiles(const pcexp_ctx* c, int jvp, int prec) {
+  const int te = c->dim == 2 ? tile_elems_p<2>(c->p, jvp, prec) : tile_elems_p<3>(c->p, jvp, prec);
+  return (int)((c->Epad + te - 1) / te);
+}
+// The reduction pass of each Arnoldi iteration runs inside the DG JVP launch
+// that produced W (its tiles write partial sums, a small kernel adds them up)
+// whenever the JVP is a DG kernel and the tile offsets fit 32-bit indices.
+static_assert(KMAX <= GS_MAXQ, "the fused reduction's LDS rows hold the basis of the largest Krylov dimension");
+bool fuse_gs(const pcexp_ctx* c, int jvp) {
+  return !c->dense && jvp != PCEXP_JVP_ZERO && c->Kint < ((size_t)1 << 31);
+}
+// Partials region: the Gram-Schmidt passes' columns (3 * 512 * (KMAX + 2)
+// doubles), then the fused reduction's 2m + 3 columns of one partial per tile.
+constexpr size_t kPartStd = (size_t)3 * 512 * (KMAX + 2);
+size_t part_bytes(const pcexp_ctx* c, int m, int prec) {
+  size_t tiles = 0;
+  if (!c->dense) {
+    tiles = (size_t)jvp_tiles(c, PCEXP_JVP_TANGENT, prec);
+    if (prec != PCEXP_PREC_MIXED) tiles = std::max(tiles, (size_t)jvp_tiles(c, PCEXP_JVP_FD, prec));
+  }
+  return (kPartStd + (size_t)(2 * m + 3) * tiles) * sizeof(double);
+}
+
 // JVP on internal vectors.  F64: v, out double.  MIXED: u32/v/out float.
-// vscale/skip optional device pointers; fd_eps device pointer for FD.
+// vscale/skip optional device pointers; fd_eps device pointer for FD.  With
+// gsV set (a DG context), the launch also forms the Arnoldi reduction of
+// iteration gsj over the basis gsV (stride Kld) into gspart (DGIO::gsV).
 bool jvp_int(pcexp_ctx* c, int jvp, int prec, const double* u, const float* u32, const void* v, void* out,
-             const double* vscale, const int* skip, const double* Rbase, const double* fd_eps, hipStream_t st) {
+             const double* vscale, const int* skip, const double* Rbase, const double* fd_eps, hipStream_t st,
+             const void* gsV = nullptr, int gsj = 0, double* gspart = nullptr, int gspld = 0) {
   const size_t n = c->Kint;
   const size_t w = (prec == PCEXP_PREC_MIXED) ? 4 : 8;
-  Prof pr(c, st, PC_JVP, (jvp == PCEXP_JVP_FD ? 4.0 : 3.0) * c->K * w + (c->dense ? 0.0 : geo_bytes(c, w)));
+  Prof pr(c, st, PC_JVP, (jvp == PCEXP_JVP_FD ? 4.0 : 3.0) * c->K * w + (c->dense ? 0.0 : geo_bytes(c, w)) +
+                             (gsV ? (double)gsj * c->K * w : 0.0));
   if (jvp == PCEXP_JVP_ZERO) {
     if (prec == PCEXP_PREC_MIXED) k_fill<float>((float*)out, 0.0f, n, skip, st);
     else k_fill<double>((double*)out, 0.0, n, skip, st);
@@ -218,10 +261,12 @@ bool jvp_int(pcexp_ctx* c, int jvp, int prec, const double* u, const float* u32,
   if (prec == PCEXP_PREC_MIXED) {
     DGIO<float> io{};
     io.u = u32; io.v = (const float*)v; io.out = (float*)out; io.vscale = vscale; io.skip = skip;
+    io.gsV = (const float*)gsV; io.gsld = c->Kld; io.gsj = gsj; io.gspart = gspart; io.gspld = gspld;
     return dg_run_f(c->dim, c->p, c->flux, MODE_TAN, params_f(c), io, st);
   }
   DGIO<double> io{};
   io.u = u; io.v = (const double*)v; io.out = (double*)out; io.vscale = vscale; io.skip = skip;
+  io.gsV = (const double*)gsV; io.gsld = c->Kld; io.gsj = gsj; io.gspart = gspart; io.gspld = gspld;
   if (jvp == PCEXP_JVP_FD) {
     io.rbase = Rbase;
     io.fd_eps = fd_eps;
@@ -243,7 +288,7 @@ WsLayout ws_layout(const pcexp_ctx* c, int m, int k, int prec) {
   const size_t vb = c->Kint * sizeof(double);
   L.ks1 = take(sizeof(KState));
   L.ks2 = take(sizeof(KState));
-  L.part = take((size_t)3 * 512 * (KMAX + 2) * sizeof(double));
+  L.part = take(part_bytes(c, m, prec));
   const size_t nphi = (size_t)(m + (k > 2 ? k : 2));   // k = 1 steps may use the (m+2) error-estimate matrix
   L.phi = take(7 * (size_t)pad16((int)nphi) * pad16((int)nphi) * sizeof(double));
   L.scal = take(64 * sizeof(double));
@@ -272,13 +317,25 @@ void arnoldi_run(pcexp_ctx* c, int jvp, int prec, const double* u_lin, const flo
     k_fd_eps(&ks->norm_tmp[0], nullptr, kSqrtEps, &ks->fd_eps, st);
   }
   k_start<TV>(b, V, n, ks, part, st);
+  const bool fuse = fuse_gs(c, jvp);
+  const int fpld = fuse ? jvp_tiles(c, jvp, prec) : 0;
+  double* fpart = part + kPartStd;
   for (int j = 0; j < m; ++j) {
-    jvp_int(c, jvp, prec, u_lin, u32, V + (size_t)j * ld, V + (size_t)(j + 1) * ld, &ks->sig_t[j], &ks->done,
-            Rlin, &ks->fd_eps, st);
     const double vb = (double)c->K * sizeof(TV);
-    // the reduction pass reads j + 2 vectors; the finalise-and-update pass reads j + 2 and writes 2
-    { Prof pr(c, st, PC_GSR, (j + 2.0) * vb); k_gs_reduce<TV>(V, ld, j, n, ks, part, false, st); }
-    { Prof pr(c, st, PC_GSU, (j + 4.0) * vb); k_gs_update<TV>(V, ld, j, n, ks, part, st); }
+    if (fuse) {
+      // JVP + reduction in one launch (it reads V_0..V_{j-1} besides its operands),
+      // then the column sums of its per-tile partials
+      jvp_int(c, jvp, prec, u_lin, u32, V + (size_t)j * ld, V + (size_t)(j + 1) * ld, &ks->sig_t[j], &ks->done,
+              Rlin, &ks->fd_eps, st, V, j, fpart, fpld);
+      { Prof pr(c, st, PC_GSR, (2.0 * j + 3.0) * fpld * 8.0); k_gs_colsum(fpart, fpld, fpld, 2 * j + 3, ks, part, st); }
+      { Prof pr(c, st, PC_GSU, (j + 4.0) * vb); k_gs_update_one<TV>(V, ld, j, n, ks, part, st); }
+    } else {
+      jvp_int(c, jvp, prec, u_lin, u32, V + (size_t)j * ld, V + (size_t)(j + 1) * ld, &ks->sig_t[j], &ks->done,
+              Rlin, &ks->fd_eps, st);
+      // the reduction pass reads j + 2 vectors; the finalise-and-update pass reads j + 2 and writes 2
+      { Prof pr(c, st, PC_GSR, (j + 2.0) * vb); k_gs_reduce<TV>(V, ld, j, n, ks, part, false, st); }
+      { Prof pr(c, st, PC_GSU, (j + 4.0) * vb); k_gs_update<TV>(V, ld, j, n, ks, part, st); }
+    }
     // adaptive dimension: H_j is final now; stop at m_eff = j if its estimate meets tol
     if (tol > 0.0 && check_every > 0 && k == 1 && j >= 1 && j % check_every == 0) {
       Prof pr(c, st, PC_PHI, 0.0);
@@ -407,7 +464,7 @@ RevLayout rev_layout(const pcexp_ctx* c, int m) {
   L.ks1 = take(sizeof(KState));
   L.ks2 = take(sizeof(KState));
   L.rs = take(sizeof(RState));
-  L.part = take((size_t)3 * 512 * (KMAX + 2) * sizeof(double));
+  L.part = take(part_bytes(c, m, PCEXP_PREC_F64));
   const size_t nphi = (size_t)std::max(m + 1, 2 * (m + 1));
   L.mem = take(7 * (size_t)pad16((int)nphi) * pad16((int)nphi) * sizeof(double));
   L.scal = take(64 * sizeof(double));
