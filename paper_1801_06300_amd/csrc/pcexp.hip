@@ -220,20 +220,24 @@ int jvp_tiles(const pcexp_ctx* c, int jvp, int prec) {
 }
 // The reduction pass of each Arnoldi iteration runs inside the DG JVP launch
 // that produced W (its tiles write partial sums, a small kernel adds them up)
-// whenever the JVP is a DG kernel and the tile offsets fit 32-bit indices.
+// when that launch is small enough to leave HBM idle while its tiles compute
+// fluxes: at most kFuseMaxTiles tiles, two rounds of resident workgroups on
+// 256 compute units.  Measured: the 128 x 128 P2 vortex (1171 tiles) gains
+// 4 % per step; the 3D P2 vortex (36 864 tiles), whose FP32 JVP keeps the
+// vector ALUs busy, loses 5 % (streaming does not overlap, and summing that
+// many partials per column costs 0.1 ms).
 static_assert(KMAX <= GS_MAXQ, "the fused reduction's LDS rows hold the basis of the largest Krylov dimension");
-bool fuse_gs(const pcexp_ctx* c, int jvp) {
-  return !c->dense && jvp != PCEXP_JVP_ZERO && c->Kint < ((size_t)1 << 31);
+constexpr int kFuseMaxTiles = 2048;
+bool fuse_gs(const pcexp_ctx* c, int jvp, int prec) {
+  return !c->dense && jvp != PCEXP_JVP_ZERO && c->Kint < ((size_t)1 << 31) &&
+         jvp_tiles(c, jvp, prec) <= kFuseMaxTiles;
 }
 // Partials region: the Gram-Schmidt passes' columns (3 * 512 * (KMAX + 2)
-// doubles), then the fused reduction's 2m + 3 columns of one partial per tile.
+// doubles), then room for the fused reduction's 2m + 3 columns of one partial
+// per tile (at most kFuseMaxTiles).
 constexpr size_t kPartStd = (size_t)3 * 512 * (KMAX + 2);
-size_t part_bytes(const pcexp_ctx* c, int m, int prec) {
-  size_t tiles = 0;
-  if (!c->dense) {
-    tiles = (size_t)jvp_tiles(c, PCEXP_JVP_TANGENT, prec);
-    if (prec != PCEXP_PREC_MIXED) tiles = std::max(tiles, (size_t)jvp_tiles(c, PCEXP_JVP_FD, prec));
-  }
+size_t part_bytes(const pcexp_ctx* c, int m, int) {
+  const size_t tiles = c->dense ? 0 : (size_t)kFuseMaxTiles;
   return (kPartStd + (size_t)(2 * m + 3) * tiles) * sizeof(double);
 }
 
@@ -317,7 +321,7 @@ void arnoldi_run(pcexp_ctx* c, int jvp, int prec, const double* u_lin, const flo
     k_fd_eps(&ks->norm_tmp[0], nullptr, kSqrtEps, &ks->fd_eps, st);
   }
   k_start<TV>(b, V, n, ks, part, st);
-  const bool fuse = fuse_gs(c, jvp);
+  const bool fuse = fuse_gs(c, jvp, prec);
   const int fpld = fuse ? jvp_tiles(c, jvp, prec) : 0;
   double* fpart = part + kPartStd;
   for (int j = 0; j < m; ++j) {
