@@ -130,13 +130,23 @@ def test_fullsize_stable_dt():
 @pytest.mark.timeout(900)
 def test_fullsize_pcexp_step():
     """One PCEXP step, FP64 tangent JVP, m = 30: whole-vector parity, the
-    Krylov dimensions and flags, and conservation of the totals."""
+    Krylov dimensions and flags, conservation of the totals, and that the
+    step took the fused JVP + reduction path."""
     c = _full()
     want, oinfo = _oracle_step()
     ctx, u0 = c["ctx"], c["u0"]
     u = _t(u0)
+    torch.cuda.synchronize()
+    ctx.profile("start")
     info = ctx.step(u, dt=c["dt"], m=c["cfg"]["m"], info=True)
+    torch.cuda.synchronize()
+    prof = ctx.profile("read")
+    ctx.profile("stop")
     got = _n(u)
+    # the Arnoldi reduction ran inside the JVP launches (1171 tiles): the
+    # reduction class holds only column sums and the two closing passes
+    vec = 8.0 * u0.size
+    assert prof["gs_reduce"][2] < 100 * vec and prof["jvp"][2] > 61 * 3 * vec, prof
     print(f"[full] step rel {rel(got, want):.3e}, increment rel {rel(got - u0, want - u0):.3e}", flush=True)
     assert rel(got, want) < 1e-11
     assert rel(got - u0, want - u0) < 1e-9

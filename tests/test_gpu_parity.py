@@ -162,6 +162,36 @@ def test_arnoldi_phi_long_basis(m, prec):
     assert rel(_n(out), want) < (1e-10 if prec == "f64" else 1e-5)
 
 
+def test_arnoldi_phi_large_mesh_separate_reduction():
+    """Above 2048 tiles the Arnoldi reduction is a pass of its own rather than
+    part of the JVP launch: 208 x 208 x 2 jittered triangles, P1 LF (2061 FP64
+    tangent tiles), m = 10, against the oracle; the bytes of the reduction
+    class show which path ran (the separate pass reads j + 2 vectors per
+    iteration, the column sums of the fused path a few hundred KB)."""
+    PCEXP = _dev()
+    m = W.periodic_square(208, 20.0, 0.15, 31)
+    print(f"\n[case] mesh=sq208j p=1 flux=lf nE={m.n_elem}", flush=True)
+    g = DG(m, 1, "lf")
+    ctx = PCEXP(m, 1, "lf")
+    u = vortex_state(g, m, 1e-3)
+    b = g.residual(u)
+    dt = stable_dt(g, u, 5.0)
+    ud, bd = _t(u), _t(b)
+    ctx.arnoldi_phi(ud, bd, dt, k=1, m=10)
+    torch.cuda.synchronize()
+    ctx.profile("start")
+    out, info = ctx.arnoldi_phi(ud, bd, dt, k=1, m=10, info=True)
+    torch.cuda.synchronize()
+    prof = ctx.profile("read")
+    ctx.profile("stop")
+    vec_bytes = 8.0 * u.size
+    assert prof["gs_reduce"][2] > 30 * vec_bytes, prof["gs_reduce"]
+    want, oinfo = krylov.arnoldi_phi(lambda x: jvp_cs(g, u, x.reshape(u.shape)), b, dt, 1, 10,
+                                     return_info=True)
+    assert info["m_eff"] == oinfo["m_eff"] == 10
+    assert rel(_n(out), want) < 1e-11
+
+
 def test_arnoldi_phi_zero_vector_and_mixed():
     g, ctx, u = _pair("sq4j", 2, "roe")
     out, info = ctx.arnoldi_phi(_t(u), _t(np.zeros_like(u)), 0.1, k=1, m=5, info=True)
