@@ -673,7 +673,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     if (io.gsV != nullptr) {
       constexpr int NE = NOUT * NI;
       // chunk width: as wide as the epilogue's registers stay within the body's
-      constexpr int GS_CB = (MODE == MODE_TAN && sizeof(T) == 8 && NE <= 3) ? 8 : NE >= 8 ? 2 : 4;
+      constexpr int CB = (MODE == MODE_TAN && sizeof(T) == 8 && NE <= 3) ? 8 : NE >= 8 ? 2 : 4;
       // the per-wave rows reuse the flux scratch, free once every wave has left the lift
       static_assert(sizeof(sw) >= (NT / 64) * GS_ROW * sizeof(double), "flux scratch holds the reduction rows");
       double* gsred = reinterpret_cast<double*>(sw);
@@ -694,7 +694,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
           gw[o * NI + c] = live ? (double)wo[o][c] : 0.0;
         }
       }
-      gs_tile_dots<NT, NE, GS_CB>(io.gsV, io.gsld, io.gsj, gix, gu, gw, io.gspart, io.gspld, gsred);
+      gs_tile_dots<NT, NE, CB>(io.gsV, io.gsld, io.gsj, gix, gu, gw, io.gspart, io.gspld, gsred);
     }
   }
 }
