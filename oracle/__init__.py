@@ -11,9 +11,16 @@ meet only through the seeded inputs of the ``workloads`` package.
 Functions accept complex arrays wherever the complex-step derivative needs
 them.  Each module cites the section / equation of the paper it follows.
 
-Parity-unpinned readings (no value in the paper fixes them; they are pinned
-only by free-stream, conservation and oracle/GPU agreement):
-  * the Gaussian quadrature rule (conical-product Gauss-Jacobi, q = p+1);
-  * the Roe flux without entropy fix and the local Lax-Friedrichs flux;
-  * the slip-wall and Riemann-invariant far-field ghost states.
+Readings where the paper leaves the choice open (no value in the paper fixes
+them); each is pinned by the property that defines it rather than by a
+number from the paper:
+  * the Gaussian quadrature rule (conical-product Gauss-Jacobi, q = p+1):
+    exact integrals of monomials up to its degree;
+  * the Roe flux without entropy fix: consistency, antisymmetry, Roe's
+    property against the exact flux Jacobian, supersonic upwinding;
+  * the local Lax-Friedrichs flux: consistency, antisymmetry, dissipation
+    speed equal to the largest eigenvalue magnitude of the flux Jacobians;
+  * the slip-wall and Riemann-invariant far-field ghost states: the mirror
+    relations, and the characteristic invariants, entropy and tangential
+    velocity recovered from the far-field ghost state.
 """

@@ -8,7 +8,8 @@ All functions are complex-safe for the complex-step derivative:
 Conserved variables U = (rho, rho v, rho E); p = (gamma-1)(rho E - |rho v|^2/(2 rho)),
 H = (rho E + p)/rho, c = sqrt(gamma p / rho).
 
-Readings (parity unpinned by the paper): Roe's flux is used without
+Readings where the paper leaves the choice open (pinned by their defining
+properties, not by values from the paper): Roe's flux is used without
 entropy fix; the Lax-Friedrichs flux is the local (Rusanov) form with
 alpha = max(|v_L.n| + c_L, |v_R.n| + c_R) per face point; the ghost states
 are the mirror state (slip wall) and the Riemann-invariant far field.

@@ -176,6 +176,81 @@ def test_ghost_states():
     assert np.allclose(euler.farfield_ghost(Uinf, n, prim, GAMMA), Uinf, atol=1e-13)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_lf_dissipation_is_max_wave_speed(dim):
+    """The local Lax-Friedrichs dissipation coefficient recovered from the flux,
+    (1/2)(F_L + F_R).n - F~ = (alpha/2)(U_R - U_L) in every component, equals
+    the largest |eigenvalue| of the exact flux Jacobians at U_L and U_R
+    (complex-step Jacobian, numpy eigenvalues)."""
+    UL, n = _states(40, dim, 11)
+    UR, _ = _states(40, dim, 12)
+    D = 0.5 * (euler.normal_flux(UL, n, GAMMA) + euler.normal_flux(UR, n, GAMMA)) \
+        - euler.lax_friedrichs(UL, UR, n, GAMMA)
+    alpha = 2.0 * D / (UR - UL)
+    assert np.allclose(alpha, alpha[:, :1], rtol=1e-9)
+    nv = dim + 2
+
+    def max_speed(U):
+        A = np.zeros((len(U), nv, nv))
+        for j in range(nv):
+            e = np.zeros(nv)
+            e[j] = 1e-30
+            A[:, :, j] = np.imag(euler.normal_flux(U + 1j * e, n, GAMMA)) / 1e-30
+        return np.max(np.abs(np.linalg.eigvals(A)), axis=1)
+
+    want = np.maximum(max_speed(UL), max_speed(UR))
+    assert np.allclose(alpha[:, 0], want, rtol=1e-10)
+
+
+def _prims(U):
+    rho = U[:, 0]
+    v = U[:, 1:-1] / rho[:, None]
+    p = (GAMMA - 1.0) * (U[:, -1] - 0.5 * rho * np.sum(v * v, 1))
+    return rho, v, p
+
+
+def test_farfield_characteristics():
+    """Riemann-invariant far field, checked on the ghost state it returns:
+    for subsonic normal flow the ghost carries the interior's outgoing
+    invariant v.n + 2c/(g-1) and the free stream's incoming one
+    v.n - 2c/(g-1), and the entropy p/rho^g and tangential velocity of the
+    upwind side (interior if the ghost's v.n >= 0); supersonic outflow returns
+    the interior state, supersonic inflow the free stream."""
+    rng = np.random.default_rng(21)
+    N, dim = 60, 2
+    n = rng.standard_normal((N, dim))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    rho = rng.uniform(0.7, 1.4, N)
+    p = rng.uniform(0.7, 1.4, N)
+    c = np.sqrt(GAMMA * p / rho)
+    t = np.stack([-n[:, 1], n[:, 0]], 1)
+    vn = rng.uniform(-0.8, 0.8, N) * c
+    v = vn[:, None] * n + rng.uniform(-0.5, 0.5, (N, 1)) * t
+    UL = W.prim_to_cons(np.concatenate([rho[:, None], v, p[:, None]], 1))
+    prim = W.freestream_prim(2, mach=0.5, angle_deg=30.0)
+    G = euler.farfield_ghost(UL, n, prim, GAMMA)
+    rb, vb, pb = _prims(G)
+    cb = np.sqrt(GAMMA * pb / rb)
+    vnb = np.sum(vb * n, 1)
+    vinf = np.asarray(prim[1:-1])
+    cinf = np.sqrt(GAMMA * prim[-1] / prim[0])
+    vninf = n @ vinf
+    assert np.allclose(vnb + 2 * cb / (GAMMA - 1), vn + 2 * c / (GAMMA - 1), atol=1e-12)
+    assert np.allclose(vnb - 2 * cb / (GAMMA - 1), vninf - 2 * cinf / (GAMMA - 1), atol=1e-12)
+    out = vnb >= 0
+    assert 5 < out.sum() < N - 5
+    s_up = np.where(out, p / rho ** GAMMA, prim[-1] / prim[0] ** GAMMA)
+    assert np.allclose(pb / rb ** GAMMA, s_up, rtol=1e-12)
+    vt_up = np.where(out[:, None], v - vn[:, None] * n, vinf - vninf[:, None] * n)
+    assert np.allclose(vb - vnb[:, None] * n, vt_up, atol=1e-12)
+    # supersonic outflow and inflow
+    for sgn, want in ((1.5, UL), (-1.5, np.tile(W.prim_to_cons(prim), (N, 1)))):
+        vs = (sgn * c)[:, None] * n
+        US = W.prim_to_cons(np.concatenate([rho[:, None], vs, p[:, None]], 1))
+        GS = euler.farfield_ghost(US, n, prim, GAMMA)
+        assert np.allclose(GS, US if sgn > 0 else want, atol=1e-13)
+
+
 def test_appendix_flux_jacobian():
     """Appendix eq. (dfdu) at omega = 0 with a_1 = gamma E - a_0 (= H; the printed
     'gamma e' is an erratum): grad(psi).dF/dU against the complex-step derivative."""
