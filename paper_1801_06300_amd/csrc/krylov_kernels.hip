@@ -85,13 +85,17 @@ __device__ __forceinline__ double col_sum(const double* part, int c, int nblk) {
 // buffer -- and slots at or past nblk are dropped by a select at the sum.
 constexpr int CS_PER = MAXB / 8;
 constexpr int CS_COLS = RT / 8;
-__device__ __forceinline__ void col_sums_load(const double* part, int c0, int ncol, double (&x)[CS_PER]) {
+// NR partials per lane (CS_PER covers MAXB blocks; NR = 1 covers the one
+// partial per column that the fused reduction's column sums leave).
+template <int NR = CS_PER>
+__device__ __forceinline__ void col_sums_load(const double* part, int c0, int ncol, double (&x)[NR]) {
   const int c = c0 + (threadIdx.x >> 3), sub = threadIdx.x & 7;
   const int cc = c < ncol ? c : ncol - 1;
 #pragma unroll
   for (int r = 0; r < CS_PER; ++r) x[r] = part[(size_t)cc * PLD + sub + 8 * r];
 }
-__device__ __forceinline__ void col_sums_finish(const double (&x)[CS_PER], int c0, int ncol, int nblk, double* col) {
+template <int NR = CS_PER>
+__device__ __forceinline__ void col_sums_finish(const double (&x)[NR], int c0, int ncol, int nblk, double* col) {
   const int c = c0 + (threadIdx.x >> 3), sub = threadIdx.x & 7;
   double a = 0.0;
 #pragma unroll
@@ -101,11 +105,12 @@ __device__ __forceinline__ void col_sums_finish(const double (&x)[CS_PER], int c
   a += __shfl_xor(a, 1, 64);
   if (c < ncol && sub == 0) col[c] = a;
 }
+template <int NR = CS_PER>
 __device__ __forceinline__ void block_col_sums(const double* part, int ncol, int nblk, double* col) {
   for (int c0 = 0; c0 < ncol; c0 += CS_COLS) {
-    double x[CS_PER];
-    col_sums_load(part, c0, ncol, x);
-    col_sums_finish(x, c0, ncol, nblk, col);
+    double x[NR];
+    col_sums_load<NR>(part, c0, ncol, x);
+    col_sums_finish<NR>(x, c0, ncol, nblk, col);
   }
 }
 
@@ -326,7 +331,7 @@ __global__ __launch_bounds__(RT) void dcgs_reduce(const TV* __restrict__ V, size
 // Every block computes the same algebra (same inputs, same order); block 0
 // publishes H, the scales and the stop flags, into locations no block of this
 // launch reads.
-template <typename TV, int NV, int PW, int CV>
+template <typename TV, int NV, int PW, int CV, int NR>
 __global__ __launch_bounds__(RT) void dcgs_fin_update(TV* __restrict__ V, size_t ld, int j, size_t n, KState* ks,
                                                       const double* part, int nblk) {
   if (ks->done_at < j) return;
@@ -366,8 +371,8 @@ __global__ __launch_bounds__(RT) void dcgs_fin_update(TV* __restrict__ V, size_t
   const double nu = ks->nu_t[j];
   const double wnj = ks->wn_t[j];
   const double eta = ks->eta;
-  double px[CS_PER];
-  if (ONE_ROUND) col_sums_load(part, 0, 2 * nq + 3, px);
+  double px[NR];
+  if (ONE_ROUND) col_sums_load<NR>(part, 0, 2 * nq + 3, px);
 
   // Loaded unconditionally (index clamped into the vector, n >= 1): a load
   // under a branch would make the wait for the partials wait for it as well.
@@ -382,8 +387,8 @@ __global__ __launch_bounds__(RT) void dcgs_fin_update(TV* __restrict__ V, size_t
   }
   __builtin_amdgcn_sched_barrier(0);   // keep both groups of loads ahead of the first use
 
-  if (ONE_ROUND) col_sums_finish(px, 0, 2 * nq + 3, nblk, col);
-  else block_col_sums(part, 2 * nq + 3, nblk, col);
+  if (ONE_ROUND) col_sums_finish<NR>(px, 0, 2 * nq + 3, nblk, col);
+  else block_col_sums<NR>(part, 2 * nq + 3, nblk, col);
 #pragma unroll
   for (int q = 0; q < HQ; ++q) {
     const int t = tid + q * RT;
@@ -614,23 +619,23 @@ static void launch_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, d
   }
 }
 
-template <typename TV>
+template <typename TV, int NR>
 static void launch_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, int nb,
                           hipStream_t st) {
   const int nq = j > 0 ? j : 1;
   const dim3 g((unsigned)gs_blocks(n)), b(RT);
-  if (nq <= 4) launch((dcgs_fin_update<TV, 4, 2, 4>), g, b, 0, st, V, ld, j, n, ks, part, nb);
-  else if (nq <= 8) launch((dcgs_fin_update<TV, 8, 2, 8>), g, b, 0, st, V, ld, j, n, ks, part, nb);
-  else if (nq <= 12) launch((dcgs_fin_update<TV, 12, 2, 12>), g, b, 0, st, V, ld, j, n, ks, part, nb);
-  else if (nq <= 16) launch((dcgs_fin_update<TV, 16, 2, 16>), g, b, 0, st, V, ld, j, n, ks, part, nb);
-  else if (nq <= 20) launch((dcgs_fin_update<TV, 20, 2, 20>), g, b, 0, st, V, ld, j, n, ks, part, nb);
-  else if (nq <= 24) launch((dcgs_fin_update<TV, 24, 2, 24>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  if (nq <= 4) launch((dcgs_fin_update<TV, 4, 2, 4, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 8) launch((dcgs_fin_update<TV, 8, 2, 8, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 12) launch((dcgs_fin_update<TV, 12, 2, 12, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 16) launch((dcgs_fin_update<TV, 16, 2, 16, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 20) launch((dcgs_fin_update<TV, 20, 2, 20, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 24) launch((dcgs_fin_update<TV, 24, 2, 24, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
   else if (nq <= 28) {
     constexpr int PW = sizeof(TV) == 8 ? 2 : 1;   // FP32 pairs would spill here
-    launch((dcgs_fin_update<TV, 28, PW, 28>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+    launch((dcgs_fin_update<TV, 28, PW, 28, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
   }
-  else if (nq <= 32) launch((dcgs_fin_update<TV, 32, 1, 32>), g, b, 0, st, V, ld, j, n, ks, part, nb);
-  else launch((dcgs_fin_update<TV, KMAX, 1, 16>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 32) launch((dcgs_fin_update<TV, 32, 1, 32, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else launch((dcgs_fin_update<TV, KMAX, 1, 16, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
 }
 
 template <typename TV>
@@ -641,12 +646,12 @@ void k_gs_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, double* pa
 
 template <typename TV>
 void k_gs_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st) {
-  launch_update<TV>(V, ld, j, n, ks, part, red_blocks(n, j > 0 ? j : 1), st);
+  launch_update<TV, CS_PER>(V, ld, j, n, ks, part, red_blocks(n, j > 0 ? j : 1), st);
 }
 
 template <typename TV>
 void k_gs_update_one(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st) {
-  launch_update<TV>(V, ld, j, n, ks, part, 1, st);
+  launch_update<TV, 1>(V, ld, j, n, ks, part, 1, st);
 }
 
 // Column c < ncol of fp (nblk partials at stride pld) summed in a fixed order

@@ -66,7 +66,8 @@ void k_init_state(KState* ks, double eta, hipStream_t st);
 template <typename TV>
 void k_start(const double* b, TV* V0, size_t n, KState* ks, double* part, hipStream_t st);
 // Iteration j, after the JVP has written W = J(sig_t[j] V_j) into slot j+1:
-// reduce (one pass over V_0..V_{j+1}), then the fused pass that finalises the
+// reduce (one pass over V_0..V_{j+1}; or, when the DG JVP launch formed the
+// partials per tile, k_gs_colsum), then the fused pass that finalises the
 // iteration (every block recomputes the small algebra from the partials,
 // block 0 publishes it) and rewrites V_j and V_{j+1}.  After the last
 // iteration, reduce with close = true and k_gs_close complete column m-1 of H.

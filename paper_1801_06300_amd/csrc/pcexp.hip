@@ -236,7 +236,7 @@ bool fuse_gs(const pcexp_ctx* c, int jvp, int prec) {
 // doubles), then room for the fused reduction's 2m + 3 columns of one partial
 // per tile (at most kFuseMaxTiles).
 constexpr size_t kPartStd = (size_t)3 * 512 * (KMAX + 2);
-size_t part_bytes(const pcexp_ctx* c, int m, int) {
+size_t part_bytes(const pcexp_ctx* c, int m) {
   const size_t tiles = c->dense ? 0 : (size_t)kFuseMaxTiles;
   return (kPartStd + (size_t)(2 * m + 3) * tiles) * sizeof(double);
 }
@@ -292,7 +292,7 @@ WsLayout ws_layout(const pcexp_ctx* c, int m, int k, int prec) {
   const size_t vb = c->Kint * sizeof(double);
   L.ks1 = take(sizeof(KState));
   L.ks2 = take(sizeof(KState));
-  L.part = take(part_bytes(c, m, prec));
+  L.part = take(part_bytes(c, m));
   const size_t nphi = (size_t)(m + (k > 2 ? k : 2));   // k = 1 steps may use the (m+2) error-estimate matrix
   L.phi = take(7 * (size_t)pad16((int)nphi) * pad16((int)nphi) * sizeof(double));
   L.scal = take(64 * sizeof(double));
@@ -468,7 +468,7 @@ RevLayout rev_layout(const pcexp_ctx* c, int m) {
   L.ks1 = take(sizeof(KState));
   L.ks2 = take(sizeof(KState));
   L.rs = take(sizeof(RState));
-  L.part = take(part_bytes(c, m, PCEXP_PREC_F64));
+  L.part = take(part_bytes(c, m));
   const size_t nphi = (size_t)std::max(m + 1, 2 * (m + 1));
   L.mem = take(7 * (size_t)pad16((int)nphi) * pad16((int)nphi) * sizeof(double));
   L.scal = take(64 * sizeof(double));
