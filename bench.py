@@ -8,8 +8,9 @@ re-orthogonalised Gram-Schmidt, the device-side Hessenberg phi, the corrector)
 through the C ABI.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line.  `value` is the FP64 tangent-JVP variant; the FP64
-finite-difference JVP and the mixed FP32/FP64 tangent variants are timed on
-the same workload and reported in `variants` with their solution error.
+finite-difference JVP and the mixed FP32/FP64 tangent variants, and ETD2
+(eq. (s7), FP64 tangent), are timed on the same workload and time levels and
+reported in `variants` with their solution error.
 """
 
 import argparse
@@ -376,6 +377,24 @@ def main():
             variants[name] = dict(dofs_per_s=K * steps / w_s, ms_per_step=1e3 * w_s / steps, l2_error=err(u),
                                   rel_diff_vs_t64=float((torch.linalg.norm(u - u_t64) /
                                                          torch.linalg.norm(u_t64)).item()))
+        # ETD2 (eq. (s7)) on the same time levels: the first step is ETD1, later ones use one step of history
+        def run_etd2(nsteps):
+            u = u0.clone()
+            u_prev, r_prev = torch.empty_like(u0), torch.empty_like(u0)
+            for i in range(warm):
+                ctx.step_etd2(u, u_prev, r_prev, i > 0, dt, m=m)
+            u = u0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(nsteps):
+                ctx.step_etd2(u, u_prev, r_prev, i > 0, dt, m=m)
+            torch.cuda.synchronize()
+            return u, time.perf_counter() - t0
+
+        u, w_s = run_etd2(steps)
+        variants["etd2"] = dict(dofs_per_s=K * steps / w_s, ms_per_step=1e3 * w_s / steps, l2_error=err(u),
+                                rel_diff_vs_t64=float((torch.linalg.norm(u - u_t64) /
+                                                       torch.linalg.norm(u_t64)).item()))
 
     # reverse mode (discrete adjoint of one step, fixed dt): time per step_vjp vs forward step
     reverse = None
