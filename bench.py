@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# profiling class -> HIP kernel(s) it times on the config-2 path (FP64, P2, Roe)
+# profiling class -> HIP kernel(s) it times on the 128x128 P2 Roe vortex (FP64)
 HIP_KERNELS = {
     "residual": "pcexp::dg_apply<2, 2, 1, double, 0, 28, 256>",
     "jvp": "pcexp::dg_apply<2, 2, 1, double, 1, 28, 256>",
@@ -118,7 +118,7 @@ def cpu_baseline(mesh, cfg, u0_np, K):
     s_step = 2 * t_res + (2 * m + 1) * t_jvp + 2 * t_gs
     sample_s = 2 * t_res + njvp * t_jvp + nproj * t_proj
     return dict(value=K / s_step, unit="DOF-updates/s", cores=threads, kind="oracle",
-                sample=(f"config-2 size, FP64 NumPy oracle, {sample_s:.1f} s measured: 2 residuals "
+                sample=(f"128x128 P2 vortex size, FP64 NumPy oracle, {sample_s:.1f} s measured: 2 residuals "
                         f"({t_res:.2f} s each), {njvp} complex-step JVPs ({t_jvp:.2f} s each), {nproj} MGS "
                         f"projections ({1e3 * t_proj:.1f} ms each); per step = 2 R + {2 * m + 1} JVP + "
                         f"2 Arnoldi MGS = {s_step:.1f} s extrapolated"),
@@ -137,7 +137,7 @@ def bench_channel(args, dev):
     import workloads as W
     from paper_1801_06300_amd import PCEXP, PcexpError
 
-    cfg = W.get_config(3)
+    cfg = W.get_config("channel_bump_p2_384x128")
     mesh = W.build_mesh(cfg)
     prim = W.freestream_prim(2, mach=cfg["mach"], angle_deg=cfg["angle_deg"])
     ctx = PCEXP(mesh, cfg["p"], cfg["flux"], farfield_prim=prim, device=dev)
@@ -260,7 +260,7 @@ def bench_vortex3d(args, dev):
     import workloads as W
     from paper_1801_06300_amd import PCEXP
 
-    cfg = W.get_config(4)
+    cfg = W.get_config("vortex3d_p2_48cube_lf")
     mesh = W.build_mesh(cfg)
     ctx = PCEXP(mesh, cfg["p"], cfg["flux"], device=dev)
     xq = ctx.quad_points().cpu().numpy()
@@ -303,7 +303,7 @@ def bench_vortex3d(args, dev):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
@@ -322,7 +322,7 @@ def main():
         return bench_stiffvortex(args, dev)
     if args.workload == "vortex3d":
         return bench_vortex3d(args, dev)
-    cfg = W.get_config(2)
+    cfg = W.get_config("vortex2d_p2_128x128_jitter_roe")
     mesh = W.build_mesh(cfg)
     ctx = PCEXP(mesh, cfg["p"], cfg["flux"], device=dev)
     K = ctx.K

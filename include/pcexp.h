@@ -49,7 +49,7 @@ typedef enum {
   PCEXP_E_WORKSPACE = -4,   /* workspace NULL or smaller than pcexp_workspace_bytes */
   PCEXP_E_NONFINITE = -5,   /* NaN/Inf seen by a kernel */
   PCEXP_E_UNPHYSICAL = -6,  /* rho <= 0 or p <= 0 at a quadrature point */
-  PCEXP_E_UNSUPPORTED = -7  /* valid request this build does not implement */
+  PCEXP_E_UNSUPPORTED = -7  /* valid request the library does not implement */
 } pcexp_status;
 
 typedef enum { PCEXP_FLUX_LF = 0, PCEXP_FLUX_ROE = 1 } pcexp_flux_kind;

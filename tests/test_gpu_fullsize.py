@@ -43,7 +43,7 @@ def _full():
         pytest.skip("no HIP device")
     if "g" not in _CACHE:
         from paper_1801_06300_amd import PCEXP
-        cfg = W.get_config(2)
+        cfg = W.get_config("vortex2d_p2_128x128_jitter_roe")
         print(f"\n[case] {cfg['name']} m={cfg['m']} cfl={cfg['cfl']}", flush=True)
         mesh = W.build_mesh(cfg)
         g = DG(mesh, cfg["p"], cfg["flux"])

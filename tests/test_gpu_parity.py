@@ -279,8 +279,8 @@ def test_dense_phi_closed_forms():
 
 
 # ------------------------------------------------------------------- stepping
-def test_step_parity_config1_ten_steps():
-    """Config-1 mesh (16x16 periodic, P1, LF, m = 20, CFL 5): 10 PCEXP steps."""
+def test_step_parity_16x16_p1_ten_steps():
+    """16x16 periodic mesh, P1, LF, m = 20, CFL 5: 10 PCEXP steps."""
     g, ctx, u0 = _pair("sq16", 1, "lf")
     op = ExactJacobian(g)
     u_o = u0.copy()

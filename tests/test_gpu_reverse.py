@@ -158,14 +158,14 @@ def test_trajectory_gradient_checkpointed():
 
 
 def test_step_vjp_full_size():
-    """Config-2 size (128^2 jittered, P2 Roe, m = 30, CFL 20), directions
+    """The 128^2 jittered P2 Roe vortex (m = 30, CFL 20), directions
     scaled to |d| = |u_0|: difference quotients of the GPU step against the
     reverse, for PCEXP and EXP1.  Along such directions the step is strongly
     curved (the central difference with h = 1e-6 is off by ~2e-5 relative,
     converging as h^2 down to h ~ 3e-8), so the assertion uses the
     Richardson-extrapolated central difference with h = 2e-7, 1e-7."""
     PCEXP = _dev()
-    cfg = W.get_config(2)
+    cfg = W.get_config("vortex2d_p2_128x128_jitter_roe")
     mesh = W.build_mesh(cfg)
     ctx = PCEXP(mesh, cfg["p"], cfg["flux"])
     xq = _n(ctx.quad_points())

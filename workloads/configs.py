@@ -10,21 +10,21 @@ vortex column is parallel to z through (5, 5) with w_inf = 0.
 from .meshes import periodic_square, channel_bump, periodic_cube
 
 CONFIGS = {
-    1: dict(name="vortex2d_p1_16x16_lf", mesh=("periodic_square", dict(n=16, length=10.0)),
+    "vortex2d_p1_16x16_lf": dict(name="vortex2d_p1_16x16_lf", mesh=("periodic_square", dict(n=16, length=10.0)),
             dim=2, p=1, flux="lf", m=20, cfl=5.0, steps=10, prec="f64",
             vortex_center=(5.0, 5.0), pert_seed=101),
-    2: dict(name="vortex2d_p2_128x128_jitter_roe",
+    "vortex2d_p2_128x128_jitter_roe": dict(name="vortex2d_p2_128x128_jitter_roe",
             mesh=("periodic_square", dict(n=128, length=20.0, jitter=0.15, seed=202)),
             dim=2, p=2, flux="roe", m=30, cfl=20.0, steps=50, prec="f64",
             vortex_center=(10.0, 10.0), pert_seed=201),
-    3: dict(name="channel_bump_p2_384x128",
+    "channel_bump_p2_384x128": dict(name="channel_bump_p2_384x128",
             mesh=("channel_bump", dict(nx=384, ny=128, height=0.1, jitter=0.15, seed=302)),
             dim=2, p=2, flux="roe", m=30, cfl_max=1000.0, steps=None, prec="mixed",
             mach=0.5, angle_deg=0.0, target_residual=1e-10),
-    4: dict(name="vortex3d_p2_48cube_lf", mesh=("periodic_cube", dict(n=48, length=10.0)),
+    "vortex3d_p2_48cube_lf": dict(name="vortex3d_p2_48cube_lf", mesh=("periodic_cube", dict(n=48, length=10.0)),
             dim=3, p=2, flux="lf", m=30, cfl=10.0, steps=20, prec="mixed",
             vortex_center=(5.0, 5.0), pert_seed=401),
-    5: dict(name="adjoint_vortex2d_p2_128x128_roe",
+    "adjoint_vortex2d_p2_128x128_roe": dict(name="adjoint_vortex2d_p2_128x128_roe",
             mesh=("periodic_square", dict(n=128, length=20.0, jitter=0.15, seed=202)),
             dim=2, p=2, flux="roe", m=30, cfl=20.0, steps=40, checkpoint_every=8,
             prec="f64", vortex_center=(10.0, 10.0), pert_seed=201, dir_seed=501,
@@ -35,8 +35,9 @@ _GEN = dict(periodic_square=periodic_square, channel_bump=channel_bump,
             periodic_cube=periodic_cube)
 
 
-def get_config(idx):
-    return dict(CONFIGS[idx])
+def get_config(name):
+    """A copy of the workload's parameters, by its name."""
+    return dict(CONFIGS[name])
 
 
 def build_mesh(cfg, **override):
