@@ -220,14 +220,15 @@ int jvp_tiles(const pcexp_ctx* c, int jvp, int prec) {
 }
 // The reduction pass of each Arnoldi iteration runs inside the DG JVP launch
 // that produced W (its tiles write partial sums, a small kernel adds them up)
-// when that launch is small enough to leave HBM idle while its tiles compute
-// fluxes: at most kFuseMaxTiles tiles, two rounds of resident workgroups on
-// 256 compute units.  Measured: the 128 x 128 P2 vortex (1171 tiles) gains
-// 4 % per step; the 3D P2 vortex (36 864 tiles), whose FP32 JVP keeps the
-// vector ALUs busy, loses 5 % (streaming does not overlap, and summing that
-// many partials per column costs 0.1 ms).
+// when that launch leaves HBM idle while its tiles compute fluxes: at most
+// kFuseMaxTiles tiles, about four rounds of resident workgroups on 256
+// compute units.  Measured: the 128 x 128 P2 vortex (1171 tiles) gains 4 %
+// per step and the 384 x 128 P2 channel in FP64 (3511 tiles) 7 %; the 3D P2
+// vortex (36 864 tiles), whose FP32 JVP keeps the vector ALUs busy, loses
+// 5 % (streaming does not overlap, and summing that many partials per column
+// costs 0.1 ms).
 static_assert(KMAX <= GS_MAXQ, "the fused reduction's LDS rows hold the basis of the largest Krylov dimension");
-constexpr int kFuseMaxTiles = 2048;
+constexpr int kFuseMaxTiles = 4096;
 bool fuse_gs(const pcexp_ctx* c, int jvp, int prec) {
   return !c->dense && jvp != PCEXP_JVP_ZERO && c->Kint < ((size_t)1 << 31) &&
          jvp_tiles(c, jvp, prec) <= kFuseMaxTiles;

@@ -163,32 +163,33 @@ def test_arnoldi_phi_long_basis(m, prec):
 
 
 def test_arnoldi_phi_large_mesh_separate_reduction():
-    """Above 2048 tiles the Arnoldi reduction is a pass of its own rather than
-    part of the JVP launch: 208 x 208 x 2 jittered triangles, P1 LF (2061 FP64
-    tangent tiles), m = 10, against the oracle; the bytes of the reduction
+    """Above 4096 tiles the Arnoldi reduction is a pass of its own rather than
+    part of the JVP launch: 294 x 294 x 2 jittered triangles, P1 LF (4116 FP64
+    tangent tiles), m = 8, against the oracle; the bytes of the reduction
     class show which path ran (the separate pass reads j + 2 vectors per
-    iteration, the column sums of the fused path a few hundred KB)."""
+    iteration, the column sums of the fused path about a megabyte)."""
     PCEXP = _dev()
-    m = W.periodic_square(208, 20.0, 0.15, 31)
-    print(f"\n[case] mesh=sq208j p=1 flux=lf nE={m.n_elem}", flush=True)
+    m = W.periodic_square(294, 20.0, 0.15, 31)
+    print(f"\n[case] mesh=sq294j p=1 flux=lf nE={m.n_elem}", flush=True)
     g = DG(m, 1, "lf")
     ctx = PCEXP(m, 1, "lf")
     u = vortex_state(g, m, 1e-3)
     b = g.residual(u)
     dt = stable_dt(g, u, 5.0)
     ud, bd = _t(u), _t(b)
-    ctx.arnoldi_phi(ud, bd, dt, k=1, m=10)
+    ctx.arnoldi_phi(ud, bd, dt, k=1, m=8)
     torch.cuda.synchronize()
     ctx.profile("start")
-    out, info = ctx.arnoldi_phi(ud, bd, dt, k=1, m=10, info=True)
+    out, info = ctx.arnoldi_phi(ud, bd, dt, k=1, m=8, info=True)
     torch.cuda.synchronize()
     prof = ctx.profile("read")
     ctx.profile("stop")
     vec_bytes = 8.0 * u.size
+    # separate passes: sum_{j<8} (j + 2) + 9 (closing) = 53 vectors; fused: 9 plus column sums
     assert prof["gs_reduce"][2] > 30 * vec_bytes, prof["gs_reduce"]
-    want, oinfo = krylov.arnoldi_phi(lambda x: jvp_cs(g, u, x.reshape(u.shape)), b, dt, 1, 10,
+    want, oinfo = krylov.arnoldi_phi(lambda x: jvp_cs(g, u, x.reshape(u.shape)), b, dt, 1, 8,
                                      return_info=True)
-    assert info["m_eff"] == oinfo["m_eff"] == 10
+    assert info["m_eff"] == oinfo["m_eff"] == 8
     assert rel(_n(out), want) < 1e-11
 
 
