@@ -179,3 +179,55 @@ def test_fullsize_step_determinism():
         c["ctx"].step(x, dt=c["dt"], m=c["cfg"]["m"])
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_channel():
+    """The steady bump channel at full size (384 x 128 x 2 jittered triangles,
+    P2 Roe, slip walls and Riemann-invariant far field).  Residual, the three
+    JVPs and Dt over the whole vector at the free stream plus a 1e-3 seeded
+    perturbation (a residual of O(1e3), well above its rounding level); one
+    EXP1 step with m = 10 at CFL 5 from the free stream plus a 1e-6
+    perturbation, a step that moves the state by 0.2 % and halves the
+    residual (its JVP launches, 3511 tiles, carry the fused Arnoldi
+    reduction).  That residual, O(10), is a small difference of wall flux
+    terms, so its rounding is ~1e-11 of it: the step is compared on the state
+    (1e-11) and on the increment with 1e-9."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1801_06300_amd import PCEXP
+    cfg = W.get_config("channel_bump_p2_384x128")
+    print(f"\n[case] {cfg['name']}", flush=True)
+    mesh = W.build_mesh(cfg)
+    prim = W.freestream_prim(2, mach=cfg["mach"], angle_deg=cfg["angle_deg"])
+    g = DG(mesh, cfg["p"], cfg["flux"], farfield_prim=prim)
+    ctx = PCEXP(mesh, cfg["p"], cfg["flux"], farfield_prim=prim)
+    ufs = g.project(lambda x: W.uniform_state(x, prim))
+    u0 = ufs + W.perturbation(ufs.shape, 307, 1e-3)
+    ud = _t(u0)
+    Ro = g.residual(u0)
+    R = _n(ctx.residual(ud))
+    print(f"[full] channel residual rel {rel(R, Ro):.3e}", flush=True)
+    assert rel(R, Ro) < 1e-11
+    v = W.random_unit_vector(u0.shape, 309)
+    vd = _t(v)
+    Jo = jvp_cs(g, u0, v)
+    Jt = _n(ctx.jvp(ud, vd, "tangent", "f64"))
+    Jm = _n(ctx.jvp(ud, vd, "tangent", "mixed"))
+    Jf = _n(ctx.jvp(ud, vd, "fd", "f64"))
+    print(f"[full] channel JVP rel: tangent {rel(Jt, Jo):.3e}, FP32 {rel(Jm, Jo):.3e}, "
+          f"FD {rel(Jf, jvp_fd(g, u0, v)):.3e}", flush=True)
+    assert rel(Jt, Jo) < 1e-11
+    assert rel(Jm, Jo) < 1e-5
+    assert rel(Jf, jvp_fd(g, u0, v)) < 1e-7
+    u1 = ufs + W.perturbation(ufs.shape, 311, 1e-6)
+    dt = stable_dt(g, u1, 5.0)
+    assert abs(ctx.stable_dt(_t(u1), 5.0) - dt) < 1e-14 * dt
+    want = pcexp_step(_Progress(g), u1, dt, 10, scheme="exp1")
+    u = _t(u1)
+    ctx.step(u, dt=dt, m=10, scheme="exp1")
+    got = _n(u)
+    print(f"[full] channel EXP1 step rel {rel(got, want):.3e}, increment rel {rel(got - u1, want - u1):.3e}",
+          flush=True)
+    assert rel(got, want) < 1e-11
+    assert rel(got - u1, want - u1) < 1e-9
