@@ -231,3 +231,95 @@ def test_fullsize_channel():
           flush=True)
     assert rel(got, want) < 1e-11
     assert rel(got - u1, want - u1) < 1e-9
+
+
+def test_fullsize_3d_properties():
+    """The 3D vortex column at full size (48^3 cubes x 6 tetrahedra, P2 LF),
+    in the launch configuration of the 3D benchmark, through properties that
+    hold at any size (the oracle needs minutes per residual here; parity on
+    a 16^3 mesh is test_3d_16cube_parity): free-stream preservation,
+    conservation of the residual, of both JVPs and of a mixed-precision PCEXP
+    step (m = 30, CFL 10) on the periodic mesh, exact doubling of the FP64
+    tangent under a doubled direction, and bitwise determinism of the step."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1801_06300_amd import PCEXP
+    cfg = W.get_config("vortex3d_p2_48cube_lf")
+    print(f"\n[case] {cfg['name']}", flush=True)
+    mesh = W.build_mesh(cfg)
+    ctx = PCEXP(mesh, cfg["p"], cfg["flux"])
+    xq = _n(ctx.quad_points()).reshape(-1, 3)
+    Uq = W.isentropic_vortex(xq, center=cfg["vortex_center"], period=mesh.period).reshape(ctx.nE, ctx.nq, ctx.nv)
+    u0 = ctx.project(_t(Uq))
+    u0 = (u0 + _t(W.perturbation(tuple(u0.shape), cfg["pert_seed"]))).contiguous()
+    ufs = ctx.project(_t(W.uniform_state(xq, W.freestream_prim(3)).reshape(ctx.nE, ctx.nq, ctx.nv))).contiguous()
+
+    def cons(x):
+        tot = np.asarray(ctx.conserved_totals(x.contiguous()))
+        scale = np.asarray(ctx.conserved_totals(x.abs().contiguous()))
+        return np.max(np.abs(tot) / scale)
+
+    R0 = ctx.residual(u0)
+    Rfs = ctx.residual(ufs)
+    fs = float(torch.linalg.norm(Rfs) / torch.linalg.norm(R0))
+    print(f"[full] 3d free stream |R|/|R_vortex| {fs:.2e}, residual conservation {cons(R0):.2e}", flush=True)
+    assert fs < 1e-9
+    assert cons(R0) < 1e-11
+    v = _t(W.random_unit_vector(tuple(u0.shape), 17))
+    Jt = ctx.jvp(u0, v, "tangent", "f64")
+    Jm = ctx.jvp(u0, v, "tangent", "mixed")
+    print(f"[full] 3d JVP conservation: FP64 {cons(Jt):.2e}, FP32 {cons(Jm.double()):.2e}", flush=True)
+    assert cons(Jt) < 1e-11
+    assert cons(Jm.double()) < 1e-5
+    assert rel(_n(Jm.double()), _n(Jt)) < 1e-5
+    J2 = ctx.jvp(u0, (2.0 * v).contiguous(), "tangent", "f64")
+    assert torch.equal(J2, 2.0 * Jt)
+    dt = ctx.stable_dt(u0, cfg["cfl"])
+    q0 = np.asarray(ctx.conserved_totals(u0))
+    a, b = u0.clone(), u0.clone()
+    info = ctx.step(a, dt=dt, m=cfg["m"], prec="mixed", info=True)
+    ctx.step(b, dt=dt, m=cfg["m"], prec="mixed")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert info["flags"] == 0
+    q1 = np.asarray(ctx.conserved_totals(a))
+    dq = np.max(np.abs(q1 - q0) / np.abs(q0).max())
+    print(f"[full] 3d mixed step: conserved totals drift {dq:.2e}, m_eff {info['k1']['m_eff']}", flush=True)
+    assert dq < 1e-6
+
+
+@pytest.mark.timeout(900)
+def test_3d_16cube_parity():
+    """3D vortex column on 16^3 cubes x 6 tetrahedra (24 576), P2 LF, against
+    the oracle over the whole vector: residual, FP64 and FP32 tangent JVPs,
+    and Arnoldi phi_1 with m = 5 (its JVP launches carry the fused
+    reduction: 3511 FP64 tiles).  The FP32 bar is the small-mesh one (1e-5
+    at 3 cubes per side) scaled with 1/h: the JVP is a difference of flux
+    terms of size 1/h times its result, and FP32 rounding is relative to
+    those terms."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1801_06300_amd import PCEXP
+    from tests.helpers import vortex_state
+    from oracle import krylov
+    mesh = W.periodic_cube(16, 10.0)
+    print(f"\n[case] mesh=cube16 p=2 flux=lf nE={mesh.n_elem}", flush=True)
+    g = DG(mesh, 2, "lf")
+    ctx = PCEXP(mesh, 2, "lf")
+    u = vortex_state(g, mesh, 1e-3)
+    ud = _t(u)
+    Ro = g.residual(u)
+    R = _n(ctx.residual(ud))
+    v = W.random_unit_vector(u.shape, 19)
+    Jo = jvp_cs(g, u, v)
+    Jt = _n(ctx.jvp(ud, _t(v), "tangent", "f64"))
+    Jm = _n(ctx.jvp(ud, _t(v), "tangent", "mixed"))
+    print(f"[full] cube16 residual {rel(R, Ro):.2e}, JVP FP64 {rel(Jt, Jo):.2e}, FP32 {rel(Jm, Jo):.2e}", flush=True)
+    assert rel(R, Ro) < 1e-11
+    assert rel(Jt, Jo) < 1e-11
+    assert rel(Jm, Jo) < 1e-5 * 16 / 3
+    dt = stable_dt(g, u, 5.0)
+    out = _n(ctx.arnoldi_phi(ud, _t(Ro), dt, k=1, m=5))
+    want = krylov.arnoldi_phi(lambda x: jvp_cs(g, u, x.reshape(u.shape)), Ro, dt, 1, 5)
+    print(f"[full] cube16 Arnoldi phi_1 (m = 5) {rel(out, want):.2e}", flush=True)
+    assert rel(out, want) < 1e-11
