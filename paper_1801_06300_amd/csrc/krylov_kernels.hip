@@ -614,8 +614,9 @@ static void launch_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, d
   else if (nq <= 24) launch((dcgs_reduce<TV, 24, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
   else if (nq <= 28) launch((dcgs_reduce<TV, 28, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
   else {
+    // the closing pass forms V.U only, so its registers hold two entries per lane
     const unsigned nc = (unsigned)((nq + CHUNK - 1) / CHUNK);
-    launch((dcgs_reduce<TV, CHUNK, 1, CLOSE>), dim3(nb, nc), b, 0, st, V, ld, j, n, ks, part);
+    launch((dcgs_reduce<TV, CHUNK, CLOSE ? 2 : 1, CLOSE>), dim3(nb, nc), b, 0, st, V, ld, j, n, ks, part);
   }
 }
 
