@@ -342,6 +342,39 @@ def test_unphysical_flag():
         ctx.step(_t(bad), dt=0.01, m=4, info=True)
 
 
+def test_step_argument_errors_on_a_live_context():
+    """The step entry point's argument checks on a live context: each bad
+    request is rejected on the host with its status before anything is
+    launched (the state is untouched), and the context keeps working."""
+    import ctypes
+    from paper_1801_06300_amd import PcexpError
+    g, ctx, u = _pair("sq3", 1, "lf")
+    ud = _t(u)
+    lib, st = ctx.lib, ctx._stream()
+
+    def step(m, prec=0, jvp=0, ws=None, nbytes=None, x=ud):
+        if ws is None:
+            ws, nb = ctx.workspace(min(max(m, 1), 64), 1, "f64", "tangent")
+            nbytes = nb if nbytes is None else nbytes
+        return lib.pcexp_step(ctx.ctx, ctypes.c_void_p(x.data_ptr()), ctypes.c_double(0.01), ctypes.c_double(0.0),
+                              m, 0, prec, jvp, ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(nbytes), None, st)
+
+    before = ud.clone()
+    assert step(0) == -1 and step(65) == -1                     # m outside [1, 64]
+    ws, nb = ctx.workspace(8, 1, "f64", "tangent")
+    assert step(8, ws=ws, nbytes=nb - 8) == -4                  # workspace too small
+    assert step(8, ws=ws[1:], nbytes=nb) == -4                  # misaligned workspace
+    assert step(8, prec=1, jvp=1) == -7                         # FD JVP in mixed precision
+    assert step(8, prec=5) == -1 and step(8, jvp=9) == -1       # unknown precision / JVP kind
+    torch.cuda.synchronize()
+    assert torch.equal(ud, before)
+    with pytest.raises(PcexpError):
+        ctx.step(ud, dt=0.01, m=65)
+    want = pcexp_step(ExactJacobian(g), u, 0.01, 8)
+    ctx.step(ud, dt=0.01, m=8)
+    assert rel(_n(ud), want) < 1e-11
+
+
 # ------------------------------------------------------------------ ETD2
 def _etd2_oracle(op, u0, dt, m, nsteps):
     from oracle.integrators import etd2_step
