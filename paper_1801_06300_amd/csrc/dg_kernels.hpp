@@ -89,7 +89,10 @@ constexpr int kLdsBudget = 40 * 1024;
 // Tile policy.  The two pointwise phases have NQ * TE (volume) and
 // NF * NFQ * TE (faces) work items over NT threads; a partial last round
 // leaves most lanes idle, so TE is chosen to minimise rounds per element
-// (largest TE among equals) under the LDS budget.
+// under the LDS budget, and among equals the smallest TE: more workgroups
+// per compute unit hide the phases' latency better (measured: the FP32 2D P2
+// tangent at 28 elements instead of 56 makes the mixed-precision step 11 %
+// faster on the 128 x 128 vortex).
 template <int D, int P, typename T, bool DUAL>
 struct Tile {
   using Sh = Shape<D, P>;
@@ -123,7 +126,7 @@ struct Tile {
     int best = 1;
     for (int te = 2; te <= 64; ++te) {
       if (te * per_elem + fixed_lds > budget) break;
-      if (rounds(te) * best <= rounds(best) * te) best = te;   // rounds/te no larger
+      if (rounds(te) * best < rounds(best) * te) best = te;   // rounds/te smaller
     }
     return best;
   }
