@@ -202,6 +202,19 @@ pcexp_status pcexp_step(pcexp_ctx* ctx, double* u, double dt, double cfl, int32_
                         int32_t scheme, int32_t prec, int32_t jvp, void* ws, size_t ws_bytes,
                         pcexp_step_info* info, void* stream);
 
+/* nsteps (>= 1) steps as by pcexp_step, in place, with u kept in the internal
+ * basis between them: one change of basis in and one out instead of one pair
+ * per step, so the result equals nsteps calls of pcexp_step up to the rounding
+ * of those basis changes (an orthogonal transform per element).  dt > 0 is
+ * used for every step; otherwise each step takes dt from eq. (x3d) at its own
+ * u_n with the given cfl.  Same workspace as pcexp_step.  info, if not NULL,
+ * describes the last step (its Krylov runs, dt, and ||R(rho)|| of the state it
+ * started from) and reports PCEXP_E_NONFINITE / PCEXP_E_UNPHYSICAL flags raised
+ * in any of the steps.  PCEXP_E_ARG for nsteps < 1 or as pcexp_step. */
+pcexp_status pcexp_advance(pcexp_ctx* ctx, double* u, int32_t nsteps, double dt, double cfl,
+                           int32_t m, int32_t scheme, int32_t prec, int32_t jvp, void* ws,
+                           size_t ws_bytes, pcexp_step_info* info, void* stream);
+
 /* ETD2 step, eq. (s7) (the second-order exponential time differencing
  * variant of Sec. 2, not the PCEXP scheme):
  *   u_{n+1} = u_n + dt Phi_1(dt J_n) R_n + dt Phi_2(dt J_n) (N_n - N_{n-1}),

@@ -100,6 +100,9 @@ _SIGS = {
     "pcexp_step": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_int32, ctypes.c_int32, _VP, ctypes.c_size_t,
                                   ctypes.POINTER(StepInfo), _VP]),
+    "pcexp_advance": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP, ctypes.c_size_t,
+                                     ctypes.POINTER(StepInfo), _VP]),
 }
 
 _lib = None
@@ -373,6 +376,18 @@ class PCEXP:
         self._check(self.lib.pcexp_step_etd2(self.ctx, _ptr(u), _ptr(u_prev), _ptr(r_prev), int(bool(have_prev)),
                                              float(dt), m, JVP[jvp], _ptr(ws), nbytes,
                                              ctypes.byref(inf) if info else None, self._stream()), "step_etd2")
+        return inf.as_dict() if info else None
+
+    def advance(self, u, nsteps, dt=0.0, cfl=0.0, m=30, scheme="pcexp", prec="f64", jvp="tangent", info=False):
+        """nsteps steps in place with u in the internal basis between them
+        (u must be a contiguous FP64 device tensor); info describes the last step."""
+        if not (u.is_cuda and u.dtype == self.torch.float64 and u.is_contiguous()):
+            raise ValueError("advance updates u in place: pass a contiguous float64 device tensor")
+        ws, nbytes = self.workspace(m, 1, prec, jvp)
+        inf = StepInfo()
+        self._check(self.lib.pcexp_advance(self.ctx, _ptr(u), int(nsteps), float(dt), float(cfl), m, SCHEME[scheme],
+                                           PREC[prec], JVP[jvp], _ptr(ws), nbytes,
+                                           ctypes.byref(inf) if info else None, self._stream()), "advance")
         return inf.as_dict() if info else None
 
     def step(self, u, dt=0.0, cfl=0.0, m=30, scheme="pcexp", prec="f64", jvp="tangent", info=False):

@@ -997,10 +997,14 @@ pcexp_status pcexp_set_krylov_adapt(pcexp_ctx* c, int32_t check_every) {
   return PCEXP_OK;
 }
 
-pcexp_status pcexp_step(pcexp_ctx* c, double* u, double dt, double cfl, int32_t m, int32_t scheme, int32_t prec,
-                        int32_t jvp, void* ws, size_t ws_bytes, pcexp_step_info* info, void* stream) {
+// nsteps steps with u in the internal basis between them (one basis change
+// in, one out); pcexp_step is nsteps = 1.
+static pcexp_status advance_impl(pcexp_ctx* c, double* u, int nsteps, double dt, double cfl, int32_t m,
+                                 int32_t scheme, int32_t prec, int32_t jvp, void* ws, size_t ws_bytes,
+                                 pcexp_step_info* info, void* stream) {
   pcexp_status s = check_step_args(c, m, scheme, prec, jvp, ws, ws_bytes);
   if (s != PCEXP_OK) return s;
+  if (nsteps < 1) return fail(c, PCEXP_E_ARG, "nsteps must be >= 1");
   if (!u) return fail(c, PCEXP_E_ARG, "u is NULL");
   if (!(dt > 0.0) && !(cfl > 0.0)) return fail(c, PCEXP_E_ARG, "need dt > 0 or cfl > 0");
   if (!(dt > 0.0) && c->dense) return fail(c, PCEXP_E_ARG, "dense contexts need dt > 0");
@@ -1013,13 +1017,15 @@ pcexp_status pcexp_step(pcexp_ctx* c, double* u, double dt, double cfl, int32_t 
   double* Rn = (double*)(w + L.Rn);
   double* part = (double*)(w + L.part);
   unsigned* cnt = (unsigned*)(w + L.cnt);
-  k_fill<unsigned>(cnt, 0u, 64, nullptr, st);
   to_int(c, u, un, st);
   DtMode dm;
   dm.dt = dt > 0.0 ? dt : 0.0;
   dm.cfl = cfl;
-  s = step_core(c, un, dm, m, scheme, prec, jvp, w, L, st);
-  if (s != PCEXP_OK) return s;
+  for (int i = 0; i < nsteps; ++i) {
+    k_fill<unsigned>(cnt, 0u, 64, nullptr, st);
+    s = step_core(c, un, dm, m, scheme, prec, jvp, w, L, st);
+    if (s != PCEXP_OK) return s;
+  }
   to_abi(c, un, u, st);
   s = hip_check(c, "step");
   if (s != PCEXP_OK) return s;
@@ -1040,6 +1046,17 @@ pcexp_status pcexp_step(pcexp_ctx* c, double* u, double dt, double cfl, int32_t 
     return report_flags(c, &info->flags);
   }
   return PCEXP_OK;
+}
+
+pcexp_status pcexp_step(pcexp_ctx* c, double* u, double dt, double cfl, int32_t m, int32_t scheme, int32_t prec,
+                        int32_t jvp, void* ws, size_t ws_bytes, pcexp_step_info* info, void* stream) {
+  return advance_impl(c, u, 1, dt, cfl, m, scheme, prec, jvp, ws, ws_bytes, info, stream);
+}
+
+pcexp_status pcexp_advance(pcexp_ctx* c, double* u, int32_t nsteps, double dt, double cfl, int32_t m,
+                           int32_t scheme, int32_t prec, int32_t jvp, void* ws, size_t ws_bytes,
+                           pcexp_step_info* info, void* stream) {
+  return advance_impl(c, u, nsteps, dt, cfl, m, scheme, prec, jvp, ws, ws_bytes, info, stream);
 }
 
 pcexp_status pcexp_step_etd2(pcexp_ctx* c, double* u, double* u_prev, double* r_prev, int32_t have_prev, double dt,

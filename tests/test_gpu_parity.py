@@ -342,6 +342,40 @@ def test_unphysical_flag():
         ctx.step(_t(bad), dt=0.01, m=4, info=True)
 
 
+def test_advance_parity():
+    """pcexp_advance: N steps with one change of basis in and out equal the
+    oracle's N steps (fixed dt; dt from eq. (x3d) at every step; EXP1) and N
+    calls of pcexp_step up to the rounding of the basis changes."""
+    from paper_1801_06300_amd import PcexpError
+    g, ctx, u0 = _pair("sq4j", 2, "roe")
+    op = ExactJacobian(g)
+    dt = stable_dt(g, u0, 5.0)
+    want = u0
+    for _ in range(3):
+        want = pcexp_step(op, want, dt, 12)
+    a = _t(u0)
+    ctx.advance(a, 3, dt=dt, m=12)
+    assert rel(_n(a), want) < 1e-11
+    b = _t(u0)
+    for _ in range(3):
+        ctx.step(b, dt=dt, m=12)
+    assert rel(_n(a), _n(b)) < 1e-13
+    want = u0
+    for _ in range(3):
+        want = pcexp_step(op, want, stable_dt(g, want, 5.0), 12)
+    c = _t(u0)
+    info = ctx.advance(c, 3, cfl=5.0, m=12, info=True)
+    assert rel(_n(c), want) < 1e-11 and info["flags"] == 0
+    want = u0
+    for _ in range(2):
+        want = pcexp_step(op, want, dt, 12, scheme="exp1")
+    d = _t(u0)
+    ctx.advance(d, 2, dt=dt, m=12, scheme="exp1")
+    assert rel(_n(d), want) < 1e-11
+    with pytest.raises(PcexpError):
+        ctx.advance(_t(u0), 0, dt=dt, m=12)
+
+
 def test_step_argument_errors_on_a_live_context():
     """The step entry point's argument checks on a live context: each bad
     request is rejected on the host with its status before anything is
