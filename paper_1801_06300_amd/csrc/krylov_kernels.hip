@@ -92,14 +92,14 @@ __device__ __forceinline__ void col_sums_load(const double* part, int c0, int nc
   const int c = c0 + (threadIdx.x >> 3), sub = threadIdx.x & 7;
   const int cc = c < ncol ? c : ncol - 1;
 #pragma unroll
-  for (int r = 0; r < CS_PER; ++r) x[r] = part[(size_t)cc * PLD + sub + 8 * r];
+  for (int r = 0; r < NR; ++r) x[r] = part[(size_t)cc * PLD + sub + 8 * r];
 }
 template <int NR = CS_PER>
 __device__ __forceinline__ void col_sums_finish(const double (&x)[NR], int c0, int ncol, int nblk, double* col) {
   const int c = c0 + (threadIdx.x >> 3), sub = threadIdx.x & 7;
   double a = 0.0;
 #pragma unroll
-  for (int r = 0; r < CS_PER; ++r) a += (sub + 8 * r < nblk) ? x[r] : 0.0;
+  for (int r = 0; r < NR; ++r) a += (sub + 8 * r < nblk) ? x[r] : 0.0;
   a += __shfl_xor(a, 4, 64);
   a += __shfl_xor(a, 2, 64);
   a += __shfl_xor(a, 1, 64);
