@@ -376,6 +376,36 @@ def test_advance_parity():
         ctx.advance(_t(u0), 0, dt=dt, m=12)
 
 
+@pytest.mark.parametrize("prec,jvp", [("f64", "fd"), ("mixed", "tangent")])
+def test_advance_matches_steps_other_paths(prec, jvp):
+    """pcexp_advance with the finite-difference JVP and in mixed precision:
+    N steps in one call against N calls of pcexp_step (the same kernels; only
+    the per-call changes of basis differ, and their rounding reaches the FD
+    quotient amplified by 1/eps and the FP32 copies of the state as a flipped
+    last bit), and against the oracle's steps with the same operator.  Bars
+    are those of the single-step variant test: FD 1e-8 on the state (a
+    rounding of u by the basis change, ~1e-16, moves the FD quotient by about
+    1e-16 / eps ~ 1e-8 relative; measured 1.3e-9 between the two forms), mixed
+    1e-4 on the increment."""
+    g, ctx, u0 = _pair("sq4j", 2, "roe")
+    op = ExactJacobian(g, "fd" if jvp == "fd" else "exact")
+    dt = stable_dt(g, u0, 5.0)
+    want = u0
+    for _ in range(3):
+        want = pcexp_step(op, want, dt, 12)
+    a = _t(u0)
+    ctx.advance(a, 3, dt=dt, m=12, prec=prec, jvp=jvp)
+    b = _t(u0)
+    for _ in range(3):
+        ctx.step(b, dt=dt, m=12, prec=prec, jvp=jvp)
+    if prec == "mixed":
+        assert rel(_n(a) - u0, _n(b) - u0) < 1e-5
+        assert rel(_n(a) - u0, want - u0) < 1e-4
+    else:
+        assert rel(_n(a), _n(b)) < 1e-8
+        assert rel(_n(a), want) < 1e-8
+
+
 def test_step_argument_errors_on_a_live_context():
     """The step entry point's argument checks on a live context: each bad
     request is rejected on the host with its status before anything is
