@@ -273,19 +273,17 @@ def bench_vortex3d(args, dev):
     dt = ctx.stable_dt(u0, cfg["cfl"])
     steps = min(args.steps, cfg["steps"])
     u = u0.clone()
-    for _ in range(args.warmup):
-        ctx.step(u, dt=dt, m=cfg["m"], prec="mixed")
+    if args.warmup > 0:
+        ctx.advance(u, args.warmup, dt=dt, m=cfg["m"], prec="mixed")
     u = u0.clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        ctx.step(u, dt=dt, m=cfg["m"], prec="mixed")
+    ctx.advance(u, steps, dt=dt, m=cfg["m"], prec="mixed")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctx.profile("start")
     u = u0.clone()
-    for _ in range(2):
-        ctx.step(u, dt=dt, m=cfg["m"], prec="mixed")
+    ctx.advance(u, 2, dt=dt, m=cfg["m"], prec="mixed")
     prof = ctx.profile("read")
     ctx.profile("stop")
     kern = {k: dict(ms_total=v[0], launches=v[1], avg_us=(1e3 * v[0] / v[1]) if v[1] else 0.0,
