@@ -701,21 +701,21 @@ constexpr int PHI_T = 256;
 // A(i, k) with i = l % 16, k = l / 16, B(k, j) with k = l / 16, j = l % 16,
 // and result rows l / 16 + 4 r, r < 4, of column l % 16.
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
-__device__ void mat_mul_mfma(const double* A, const double* B, const double* D, double* C, int np) {
+__device__ void mat_mul_mfma(const double* A, const double* B, const double* D, double* C, int np, int ld) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nt = np >> 4;
   const int li = lane & 15, lk = lane >> 4;
   for (int tile = wid; tile < nt * nt; tile += PHI_T / 64) {
     const int ti = tile % nt, tj = tile / nt;
     mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
-    const double* a = A + (size_t)lk * np + ti * 16 + li;
-    const double* b = B + (size_t)(tj * 16 + li) * np + lk;
+    const double* a = A + (size_t)lk * ld + ti * 16 + li;
+    const double* b = B + (size_t)(tj * 16 + li) * ld + lk;
     for (int k0 = 0; k0 < np; k0 += 4)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[(size_t)k0 * np], b[k0], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[(size_t)k0 * ld], b[k0], acc, 0, 0, 0);
     const int col = tj * 16 + li;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const size_t t = (size_t)col * np + ti * 16 + lk + 4 * r;
+      const size_t t = (size_t)col * ld + ti * 16 + lk + 4 * r;
       C[t] = D ? acc[r] + D[t] : acc[r];
     }
   }
@@ -728,8 +728,8 @@ __device__ void mat_mul_mfma(const double* A, const double* B, const double* D, 
 // a pointer to the result inside mem, with leading dimension *ld = np.
 __device__ double* expm_core(double* mem, int n, int* ld) {
   const int tid = threadIdx.x;
-  const int np = pad16(n);
-  const int nn = np * np;
+  const int np = pad16(n), lm = phi_ld(np);
+  const int nn = np * lm;   // rows np .. lm-1 of every matrix are padding, never read by the products
   double* X = mem + (size_t)6 * nn;   // scaled, padded A (the input region is read first)
   double* X2 = mem;
   double* X3 = X2 + nn;
@@ -740,13 +740,13 @@ __device__ double* expm_core(double* mem, int n, int* ld) {
   __shared__ double colsum[pad16(2 * KMAX + 2)];
   __shared__ int s_sq;
   for (int t = tid; t < nn; t += PHI_T) {
-    const int i = t % np, jj = t / np;
+    const int i = t % lm, jj = t / lm;
     X[t] = (i < n && jj < n) ? mem[jj * n + i] : 0.0;
   }
   __syncthreads();
   for (int jj = tid; jj < np; jj += PHI_T) {
     double s = 0.0;
-    for (int i = 0; i < np; ++i) s += fabs(X[jj * np + i]);
+    for (int i = 0; i < np; ++i) s += fabs(X[jj * lm + i]);
     colsum[jj] = s;
   }
   __syncthreads();
@@ -764,9 +764,9 @@ __device__ double* expm_core(double* mem, int n, int* ld) {
   const double sc = ldexp(1.0, -s);
   for (int t = tid; t < nn; t += PHI_T) X[t] *= sc;
   __syncthreads();
-  mat_mul_mfma(X, X, nullptr, X2, np);
-  mat_mul_mfma(X2, X, nullptr, X3, np);
-  mat_mul_mfma(X2, X2, nullptr, X4, np);
+  mat_mul_mfma(X, X, nullptr, X2, np, lm);
+  mat_mul_mfma(X2, X, nullptr, X3, np, lm);
+  mat_mul_mfma(X2, X2, nullptr, X4, np, lm);
   // Taylor coefficients c_k = 1/k!, k = 0..18; blocks B_i = sum_{r<4} c_{4i+r} X^r,
   // T(X) = B_0 + X^4 (B_1 + X^4 (B_2 + X^4 (B_3 + X^4 B_4))), B_4 = c_16 + c_17 X + c_18 X^2
   double c[19];
@@ -776,27 +776,27 @@ __device__ double* expm_core(double* mem, int n, int* ld) {
     const double a0 = c[4 * i], a1 = (4 * i + 1 < 19) ? c[4 * i + 1] : 0.0;
     const double a2 = (4 * i + 2 < 19) ? c[4 * i + 2] : 0.0, a3 = (4 * i + 3 < 19) ? c[4 * i + 3] : 0.0;
     for (int t = tid; t < nn; t += PHI_T) {
-      const int r = t % np, jj = t / np;
+      const int r = t % lm, jj = t / lm;
       dst[t] = a1 * X[t] + a2 * X2[t] + a3 * X3[t] + (r == jj ? a0 : 0.0);
     }
     __syncthreads();
   };
   block(4, T0);                          // T0 = B_4
   block(3, Bq);
-  mat_mul_mfma(X4, T0, Bq, T1, np);      // T1 = B_3 + X^4 B_4
+  mat_mul_mfma(X4, T0, Bq, T1, np, lm);      // T1 = B_3 + X^4 B_4
   block(2, Bq);
-  mat_mul_mfma(X4, T1, Bq, T0, np);      // T0 = B_2 + X^4 T1
+  mat_mul_mfma(X4, T1, Bq, T0, np, lm);      // T0 = B_2 + X^4 T1
   block(1, Bq);
-  mat_mul_mfma(X4, T0, Bq, T1, np);      // T1 = B_1 + X^4 T0
+  mat_mul_mfma(X4, T0, Bq, T1, np, lm);      // T1 = B_1 + X^4 T0
   block(0, Bq);
-  mat_mul_mfma(X4, T1, Bq, T0, np);      // T0 = B_0 + X^4 T1 = T(X)
+  mat_mul_mfma(X4, T1, Bq, T0, np, lm);      // T0 = B_0 + X^4 T1 = T(X)
   double* P = T0;
   double* Q = T1;
   for (int it = 0; it < s; ++it) {
-    mat_mul_mfma(P, P, nullptr, Q, np);
+    mat_mul_mfma(P, P, nullptr, Q, np, lm);
     double* t = P; P = Q; Q = t;
   }
-  *ld = np;
+  *ld = lm;
   return P;
 }
 
@@ -948,7 +948,7 @@ __global__ __launch_bounds__(PHI_T) void krylov_check_glb(KState* ks, const doub
 
 void k_krylov_check(KState* ks, const double* dt, double tol, int j, double* scratch, hipStream_t st) {
   const int n = j + 2;
-  const size_t bytes = (size_t)7 * pad16(n) * pad16(n) * sizeof(double);
+  const size_t bytes = phi_scratch_doubles(n) * sizeof(double);
   if (bytes <= 60 * 1024) launch(krylov_check_lds, dim3(1), dim3(PHI_T), bytes, st, ks, dt, tol, j);
   else launch(krylov_check_glb, dim3(1), dim3(PHI_T), 0, st, ks, dt, tol, j, scratch);
 }
@@ -963,7 +963,7 @@ __global__ __launch_bounds__(PHI_T) void hess_phi_adapt_glb(KState* ks, double* 
 
 void k_hess_phi_adapt(KState* ks, double* dt, double tol, int m, double* scratch, hipStream_t st) {
   const int n = m + 2;
-  const size_t bytes = (size_t)7 * pad16(n) * pad16(n) * sizeof(double);
+  const size_t bytes = phi_scratch_doubles(n) * sizeof(double);
   if (bytes <= 60 * 1024) launch(hess_phi_adapt_lds, dim3(1), dim3(PHI_T), bytes, st, ks, dt, tol);
   else launch(hess_phi_adapt_glb, dim3(1), dim3(PHI_T), 0, st, ks, dt, tol, scratch);
 }
@@ -978,7 +978,7 @@ __global__ __launch_bounds__(PHI_T) void hess_phi_glb(KState* ks, const double* 
 
 void k_hess_phi(KState* ks, const double* dt, int k, int m, double* scratch, hipStream_t st) {
   const int n = m + (k >= 1 ? k : 0);
-  const size_t bytes = (size_t)7 * pad16(n) * pad16(n) * sizeof(double);
+  const size_t bytes = phi_scratch_doubles(n) * sizeof(double);
   if (bytes <= 60 * 1024) {
     launch(hess_phi_lds, dim3(1), dim3(PHI_T), bytes, st, ks, dt, k);
   } else {

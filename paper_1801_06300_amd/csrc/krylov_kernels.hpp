@@ -25,6 +25,11 @@ constexpr int GS_THREADS = 256;
 // dimension of the zero-padded matrices of the small exponential (a multiple
 // of the 16 x 16 matrix-core tile)
 __host__ __device__ constexpr int pad16(int n) { return (n + 15) & ~15; }
+// Leading dimension of the Hessenberg exponential's np x np matrices: one
+// padding row, so that the rows of one column lie in different LDS banks.
+__host__ __device__ constexpr int phi_ld(int np) { return np + 1; }
+// Doubles of scratch the exponential of an n x n matrix needs (7 matrices).
+__host__ __device__ constexpr size_t phi_scratch_doubles(int n) { return (size_t)7 * pad16(n) * phi_ld(pad16(n)); }
 
 // Arnoldi state.  Quantities that iteration j reads and iteration j writes
 // are kept apart (tentative values indexed by iteration, H's tentative column
@@ -82,14 +87,14 @@ void k_gs_update_one(TV* V, size_t ld, int j, size_t n, KState* ks, const double
 // into part[c * 512]; a no-op once ks->done is set.
 void k_gs_colsum(const double* fp, int pld, int nblk, int ncol, const KState* ks, double* part, hipStream_t st);
 void k_gs_close(KState* ks, const double* part, int m, size_t n, hipStream_t st);
-// scratch: >= 7 pad16(m + k)^2 doubles (used when that exceeds the LDS path)
+// scratch: >= phi_scratch_doubles(m + k) doubles (used when that exceeds the LDS path)
 void k_hess_phi(KState* ks, const double* dt, int k, int m, double* scratch, hipStream_t st);
 // phi_1 with the Krylov error estimate: halves *dt on the device until the
-// estimated relative error is <= tol; scratch >= 7 pad16(m+2)^2 doubles.
+// estimated relative error is <= tol; scratch >= phi_scratch_doubles(m + 2) doubles.
 void k_hess_phi_adapt(KState* ks, double* dt, double tol, int m, double* scratch, hipStream_t st);
 // Adaptive dimension: after iteration j (1 <= j < m), stop the run with
 // m_eff = j when the error estimate for dimension j at *dt is <= tol;
-// scratch >= 7 pad16(j+2)^2 doubles.
+// scratch >= phi_scratch_doubles(j + 2) doubles.
 void k_krylov_check(KState* ks, const double* dt, double tol, int j, double* scratch, hipStream_t st);
 template <typename TV, typename TX>
 void k_combine(const TV* V, size_t ld, const KState* ks, const double* base, double* out,

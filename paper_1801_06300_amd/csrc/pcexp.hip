@@ -295,7 +295,7 @@ WsLayout ws_layout(const pcexp_ctx* c, int m, int k, int prec) {
   L.ks2 = take(sizeof(KState));
   L.part = take(part_bytes(c, m));
   const size_t nphi = (size_t)(m + (k > 2 ? k : 2));   // k = 1 steps may use the (m+2) error-estimate matrix
-  L.phi = take(7 * (size_t)pad16((int)nphi) * pad16((int)nphi) * sizeof(double));
+  L.phi = take(phi_scratch_doubles((int)nphi) * sizeof(double));
   L.scal = take(64 * sizeof(double));
   L.cnt = take(64 * sizeof(unsigned));
   L.un = take(vb);
@@ -471,7 +471,7 @@ RevLayout rev_layout(const pcexp_ctx* c, int m) {
   L.rs = take(sizeof(RState));
   L.part = take(part_bytes(c, m));
   const size_t nphi = (size_t)std::max(m + 1, 2 * (m + 1));
-  L.mem = take(7 * (size_t)pad16((int)nphi) * pad16((int)nphi) * sizeof(double));
+  L.mem = take(phi_scratch_doubles((int)nphi) * sizeof(double));
   L.scal = take(64 * sizeof(double));
   L.un = take(vb); L.Rn = take(vb); L.us = take(vb); L.Rs = take(vb); L.x1 = take(vb);
   L.ub = take(vb); L.acc = take(vb); L.xb = take(vb); L.db = take(vb);
