@@ -701,6 +701,19 @@ constexpr int PHI_T = 256;
 // A(i, k) with i = l % 16, k = l / 16, B(k, j) with k = l / 16, j = l % 16,
 // and result rows l / 16 + 4 r, r < 4, of column l % 16.
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+// NS steps of 4 along k with every operand load issued before the first
+// product (the same products in the same order as the run-time loop).
+template <int NS>
+__device__ __forceinline__ void mfma_chain(const double* a, const double* b, int ld, mfma_d4& acc) {
+  double av[NS], bv[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    av[q] = a[(size_t)(4 * q) * ld];
+    bv[q] = b[4 * q];
+  }
+#pragma unroll
+  for (int q = 0; q < NS; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
+}
 __device__ void mat_mul_mfma(const double* A, const double* B, const double* D, double* C, int np, int ld) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nt = np >> 4;
@@ -710,8 +723,14 @@ __device__ void mat_mul_mfma(const double* A, const double* B, const double* D, 
     mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
     const double* a = A + (size_t)lk * ld + ti * 16 + li;
     const double* b = B + (size_t)(tj * 16 + li) * ld + lk;
-    for (int k0 = 0; k0 < np; k0 += 4)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[(size_t)k0 * ld], b[k0], acc, 0, 0, 0);
+    if (np == 32) {
+      mfma_chain<8>(a, b, ld, acc);
+    } else if (np == 16) {
+      mfma_chain<4>(a, b, ld, acc);
+    } else {
+      for (int k0 = 0; k0 < np; k0 += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[(size_t)k0 * ld], b[k0], acc, 0, 0, 0);
+    }
     const int col = tj * 16 + li;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
