@@ -108,9 +108,10 @@ typedef struct {
 
 typedef struct {
   pcexp_krylov_info k1, k2;  /* predictor and corrector Arnoldi runs */
-  double dt;                 /* time step used */
+  double dt;                 /* time step used (by the last step of the call) */
   double res_rho_norm;       /* |R(rho_n)| of eq. (cfl) at u_n */
   uint32_t flags;            /* PCEXP_FLAG_* seen since the previous report */
+  double t_advanced;         /* time advanced by the whole call: the sum of the dt each step used */
 } pcexp_step_info;
 
 typedef struct {
@@ -206,11 +207,15 @@ pcexp_status pcexp_step(pcexp_ctx* ctx, double* u, double dt, double cfl, int32_
  * basis between them: one change of basis in and one out instead of one pair
  * per step, so the result equals nsteps calls of pcexp_step up to the rounding
  * of those basis changes (an orthogonal transform per element).  dt > 0 is
- * used for every step; otherwise each step takes dt from eq. (x3d) at its own
- * u_n with the given cfl.  Same workspace as pcexp_step.  info, if not NULL,
+ * the step each step starts from; otherwise each step takes dt from eq. (x3d)
+ * at its own u_n with the given cfl.  With a Krylov tolerance set
+ * (pcexp_set_krylov_tol) the predictor of each step may halve that dt, so the
+ * steps need not be equal.  Same workspace as pcexp_step.  info, if not NULL,
  * describes the last step (its Krylov runs, dt, and ||R(rho)|| of the state it
- * started from) and reports PCEXP_E_NONFINITE / PCEXP_E_UNPHYSICAL flags raised
- * in any of the steps.  PCEXP_E_ARG for nsteps < 1 or as pcexp_step. */
+ * started from), gives in t_advanced the time advanced by all nsteps steps
+ * (summed on the device when the steps can differ, else nsteps dt), and
+ * reports PCEXP_E_NONFINITE / PCEXP_E_UNPHYSICAL flags raised in any of the
+ * steps.  PCEXP_E_ARG for nsteps < 1 or as pcexp_step. */
 pcexp_status pcexp_advance(pcexp_ctx* ctx, double* u, int32_t nsteps, double dt, double cfl,
                            int32_t m, int32_t scheme, int32_t prec, int32_t jvp, void* ws,
                            size_t ws_bytes, pcexp_step_info* info, void* stream);
@@ -240,6 +245,19 @@ pcexp_status pcexp_step_etd2(pcexp_ctx* ctx, double* u, double* u_prev, double* 
  * Synchronises. */
 pcexp_status pcexp_pressure_functional(pcexp_ctx* ctx, const double* u, double p_ref,
                                        double* value_host, double* grad, void* stream);
+
+/* Device-side accumulation for the adjoint workload (asynchronous, no
+ * synchronisation), with P(u) the functional of pcexp_pressure_functional:
+ *   *value_acc += scale P(u)      value_acc: device FP64 scalar, or NULL;
+ *   grad_acc   += scale dP/du(u)  grad_acc: device FP64 vector, ABI layout, or NULL.
+ * At least one of them must be given; neither may alias u or the other.
+ * The checkpointed gradient of J = sum_n dt P(u_n) seeds and accumulates
+ * with it (scale = dt times the incoming cotangent) so that no arithmetic of
+ * the sweep happens outside the library.  Uses the context's scratch (one
+ * stream at a time per context).  PCEXP_E_ARG for NULL u, no accumulator,
+ * aliasing or a non-finite scale / p_ref; PCEXP_E_UNSUPPORTED on dense contexts. */
+pcexp_status pcexp_pressure_functional_acc(pcexp_ctx* ctx, const double* u, double p_ref, double scale,
+                                           double* value_acc, double* grad_acc, void* stream);
 
 /* Reverse mode of one step (the discrete adjoint of pcexp_step in FP64 with
  * the tangent JVP; not part of the paper): ubar_n = (d u_{n+1} / d u_n)^T

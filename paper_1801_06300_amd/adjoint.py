@@ -2,12 +2,15 @@
 
 Objective (a pressure-fluctuation functional along a trajectory with a fixed
 time step): J(u_0) = sum_{n=1}^{N} dt int_Omega (p_h(t_n) - p_ref)^2 dx.
-Its gradient is accumulated backwards: ubar_N = dt dP/du(u_N), then for
-n = N-1 .. 0, ubar_n = (du_{n+1}/du_n)^T ubar_{n+1} (+ dt dP/du(u_n) for
-n >= 1).  Every step of the sweep runs in the library (pcexp_step,
-pcexp_step_vjp, pcexp_pressure_functional); this module only schedules
-them.  States are kept every `every` steps; a segment is recomputed forward
-before it is swept backwards, so at most N/every + every states are held.
+Its gradient is accumulated backwards: ubar_N = s dt dP/du(u_N), then for
+n = N-1 .. 0, ubar_n = (du_{n+1}/du_n)^T ubar_{n+1} (+ s dt dP/du(u_n) for
+n >= 1), with s the incoming cotangent.  Every step of both sweeps runs in
+the library (pcexp_step, pcexp_step_vjp, and pcexp_pressure_functional_acc,
+which adds s dt P and s dt dP/du into device accumulators); this module
+only schedules the calls and owns the buffers.  The forward sweep keeps the
+state every `every` steps; the reverse sweep recomputes each segment forward
+from its checkpoint before sweeping it backwards, so at most
+ceil(N / every) + every states are held at once.
 """
 
 import math
@@ -17,66 +20,86 @@ class Trajectory:
     def __init__(self, ctx, dt, nsteps, m=30, every=8, p_ref=1.0, scheme="pcexp"):
         if not (dt > 0.0):
             raise ValueError("the reverse sweep needs a fixed dt > 0")
+        if nsteps < 1 or every < 1:
+            raise ValueError("nsteps and every must be >= 1")
         self.ctx, self.dt, self.n, self.m, self.every = ctx, float(dt), int(nsteps), int(m), int(every)
         self.p_ref, self.scheme = float(p_ref), scheme
 
     def _step(self, u):
         self.ctx.step(u, dt=self.dt, m=self.m, scheme=self.scheme)
 
-    def value(self, u0):
-        u = u0.clone()
-        total = 0.0
-        for _ in range(self.n):
-            self._step(u)
-            total += self.dt * self.ctx.pressure_functional(u, self.p_ref)
-        return total
-
-    def value_and_grad(self, u0):
-        ctx = self.ctx
-        ckpt = {0: u0.clone()}
-        u = u0.clone()
-        total = 0.0
+    def forward(self, u0):
+        """Forward sweep only: returns (J as a 0-dim device tensor, checkpoints),
+        checkpoints being {n: u_n} for n = 0, every, 2 every, ... < N."""
+        torch = self.ctx.torch
+        acc = torch.zeros((), dtype=torch.float64, device=u0.device)
+        ckpt = {0: u0.detach().clone().contiguous()}
+        u = ckpt[0].clone()
         for n in range(1, self.n + 1):
             self._step(u)
-            total += self.dt * ctx.pressure_functional(u, self.p_ref)
+            self.ctx.pressure_functional_acc(u, self.dt, self.p_ref, value_acc=acc)
             if n % self.every == 0 and n < self.n:
                 ckpt[n] = u.clone()
-        _, g = ctx.pressure_functional(u, self.p_ref, grad=True)
-        ubar = self.dt * g
-        starts = sorted(ckpt)
-        for s in reversed(starts):
-            e = min(s + self.every, self.n)
-            states = [ckpt[s]]
-            w = ckpt[s].clone()
-            for _ in range(s + 1, e):
+        return acc, ckpt
+
+    def backward(self, ckpt, scale=1.0):
+        """Reverse sweep from the checkpoints of forward(): returns scale dJ/du_0."""
+        ctx = self.ctx
+        torch = ctx.torch
+        s = float(scale) * self.dt
+        # u_N: recompute the last segment's end from its checkpoint
+        last = max(ckpt)
+        u = ckpt[last].clone()
+        for _ in range(last, self.n):
+            self._step(u)
+        ubar = torch.zeros_like(u)
+        other = torch.empty_like(u)
+        ctx.pressure_functional_acc(u, s, self.p_ref, grad_acc=ubar)
+        del u
+        for start in sorted(ckpt, reverse=True):
+            end = min(start + self.every, self.n)
+            states = [ckpt[start]]
+            w = ckpt[start].clone()
+            for _ in range(start + 1, end):
                 self._step(w)
                 states.append(w.clone())
-            for k in range(e - 1, s - 1, -1):
-                ubar = ctx.step_vjp(states[k - s], ubar, self.dt, m=self.m, scheme=self.scheme)
+            for k in range(end - 1, start - 1, -1):
+                ctx.step_vjp(states[k - start], ubar, self.dt, m=self.m, scheme=self.scheme, out=other)
+                ubar, other = other, ubar
                 if k >= 1:
-                    _, g = ctx.pressure_functional(states[k - s], self.p_ref, grad=True)
-                    ubar = ubar + self.dt * g
-        return total, ubar
+                    ctx.pressure_functional_acc(states[k - start], s, self.p_ref, grad_acc=ubar)
+        return ubar
+
+    def value(self, u0):
+        acc, _ = self.forward(u0)
+        return float(acc)
+
+    def value_and_grad(self, u0):
+        acc, ckpt = self.forward(u0)
+        return float(acc), self.backward(ckpt)
 
     def peak_states(self):
-        """States held at once by value_and_grad (checkpoints + one segment)."""
+        """States held at once by the reverse sweep (checkpoints + one segment)."""
         return math.ceil(self.n / self.every) + self.every
 
 
 def objective(traj):
-    """torch.autograd.Function applying J(u_0) of the trajectory."""
+    """torch.autograd.Function applying J(u_0) of the trajectory: forward()
+    runs the checkpointed forward sweep only; backward() runs the reverse
+    sweep with the incoming cotangent passed to the library as a scale."""
     import torch
 
     class _Objective(torch.autograd.Function):
         @staticmethod
         def forward(fctx, u0):
-            val, g = traj.value_and_grad(u0.detach().contiguous())
-            fctx.save_for_backward(g)
-            return u0.new_tensor(val)
+            val, ckpt = traj.forward(u0.detach().contiguous())
+            fctx.ckpt = ckpt
+            return val
 
         @staticmethod
         def backward(fctx, gout):
-            (g,) = fctx.saved_tensors
-            return gout * g
+            g = traj.backward(fctx.ckpt, scale=float(gout))
+            fctx.ckpt = None
+            return g
 
     return _Objective.apply

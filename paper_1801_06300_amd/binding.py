@@ -49,11 +49,11 @@ class KrylovInfo(ctypes.Structure):
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("k1", KrylovInfo), ("k2", KrylovInfo), ("dt", ctypes.c_double),
-                ("res_rho_norm", ctypes.c_double), ("flags", ctypes.c_uint32)]
+                ("res_rho_norm", ctypes.c_double), ("flags", ctypes.c_uint32), ("t_advanced", ctypes.c_double)]
 
     def as_dict(self):
         return dict(k1=self.k1.as_dict(), k2=self.k2.as_dict(), dt=self.dt,
-                    res_rho_norm=self.res_rho_norm, flags=int(self.flags))
+                    res_rho_norm=self.res_rho_norm, flags=int(self.flags), t_advanced=self.t_advanced)
 
 
 class SteadyInfo(ctypes.Structure):
@@ -82,6 +82,7 @@ _SIGS = {
     "pcexp_vjp2": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "pcexp_step_vjp_workspace_bytes": (ctypes.c_size_t, [_VP, ctypes.c_int32]),
     "pcexp_pressure_functional": (ctypes.c_int, [_VP, _VP, ctypes.c_double, c_double_p, _VP, _VP]),
+    "pcexp_pressure_functional_acc": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_double, _VP, _VP, _VP]),
     "pcexp_step_vjp": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP,
                                       ctypes.c_size_t, _VP]),
     "pcexp_stable_dt": (ctypes.c_int, [_VP, _VP, ctypes.c_double, c_double_p, _VP]),
@@ -289,7 +290,20 @@ class PCEXP:
                     "pressure_functional")
         return (val.value, g) if grad else val.value
 
-    def step_vjp(self, u, ubar, dt, m=30, scheme="pcexp"):
+    def pressure_functional_acc(self, u, scale, p_ref=1.0, value_acc=None, grad_acc=None):
+        """value_acc += scale P(u) and grad_acc += scale dP/du on the device
+        (contiguous FP64 device tensors: a 0-dim scalar and a state-shaped
+        vector; either may be None), asynchronously."""
+        for t in (u, value_acc, grad_acc):
+            if t is not None and not (t.is_cuda and t.dtype == self.torch.float64 and t.is_contiguous()):
+                raise ValueError("pressure_functional_acc: pass contiguous float64 device tensors")
+        if grad_acc is not None and tuple(grad_acc.shape) != tuple(self.shape):
+            raise ValueError("grad_acc must have the state's shape")
+        self._check(self.lib.pcexp_pressure_functional_acc(
+            self.ctx, _ptr(u), float(p_ref), float(scale), _ptr(value_acc) if value_acc is not None else None,
+            _ptr(grad_acc) if grad_acc is not None else None, self._stream()), "pressure_functional_acc")
+
+    def step_vjp(self, u, ubar, dt, m=30, scheme="pcexp", out=None):
         """(d u_{n+1} / d u_n)^T ubar for the step from u with fixed dt (FP64, tangent JVP)."""
         u = self._vec(u, self.shape)
         ubar = self._vec(ubar, self.shape)
@@ -299,7 +313,7 @@ class PCEXP:
         if ws is None or ws.numel() < nbytes:
             ws = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
             self._ws[key] = ws
-        out = self.empty()
+        out = self.empty() if out is None else out
         self._check(self.lib.pcexp_step_vjp(self.ctx, _ptr(u), float(dt), m, SCHEME[scheme], _ptr(ubar), _ptr(out),
                                             _ptr(ws), nbytes, self._stream()), "step_vjp")
         return out

@@ -43,9 +43,12 @@ struct ElemArgs {
 void ek_to_internal(const ElemArgs& a, const double* u_abi, double* u_int, hipStream_t st);
 // value = int (p_h - p_ref)^2 dx (device scalar); grad_int (optional) its
 // gradient with respect to the internal coefficients; part >= Epad/256 doubles.
+// value (device): P(u), or value += scale P(u) when acc; value may be NULL.
 void ek_pressure_functional(const ElemArgs& a, const double* u_int, double p_ref, double* value, double* grad_int,
-                            double* part, hipStream_t st);
+                            double* part, hipStream_t st, int acc = 0, double scale = 1.0);
 void ek_to_abi(const ElemArgs& a, const double* u_int, double* u_abi, hipStream_t st);
+// u_abi += scale Q^T u_int
+void ek_to_abi_axpy(const ElemArgs& a, const double* u_int, double scale, double* u_abi, hipStream_t st);
 void ek_quad_points(const ElemArgs& a, double* xyz, hipStream_t st);
 void ek_project(const ElemArgs& a, const double* Uqp, double* u_abi, hipStream_t st);
 void ek_evaluate(const ElemArgs& a, const double* u_abi, double* Uqp, hipStream_t st);

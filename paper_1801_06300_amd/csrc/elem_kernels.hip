@@ -38,7 +38,10 @@ __global__ void to_internal_kernel(ElemArgs a, const double* __restrict__ u_abi,
   }
 }
 
-__global__ void to_abi_kernel(ElemArgs a, const double* __restrict__ u_int, double* __restrict__ u_abi) {
+// u_abi = Q^T u_int, or u_abi += scale Q^T u_int when acc (the same rounding
+// of Q^T u_int in both forms, then one multiply-add).
+__global__ void to_abi_kernel(ElemArgs a, const double* __restrict__ u_int, double* __restrict__ u_abi, int acc,
+                              double scale) {
   const size_t t = (size_t)blockIdx.x * EK_T + threadIdx.x;
   const int nb = a.nb, nv = a.nv;
   if (t >= (size_t)a.nE * nv) return;
@@ -50,7 +53,9 @@ __global__ void to_abi_kernel(ElemArgs a, const double* __restrict__ u_int, doub
   for (int j = 0; j < nb; ++j) {
     double s = 0.0;
     for (int i = 0; i < nb; ++i) s += Q[i * nb + j] * x[i];
-    u_abi[((size_t)e * nv + k) * nb + j] = s;
+    double* o = &u_abi[((size_t)e * nv + k) * nb + j];
+    if (acc) *o = fma(scale, s, *o);
+    else *o = s;
   }
 }
 
@@ -239,25 +244,29 @@ __global__ void pfun_kernel(ElemArgs a, const double* __restrict__ u, double p_r
   }
 }
 
-__global__ void pfun_finalize(const double* part, int nblk, double* out) {
+// *out = P, or *out += scale P when acc.
+__global__ void pfun_finalize(const double* part, int nblk, double* out, int acc, double scale) {
   double t = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 64) t += part[b];
   t = ek_wave_sum(t);
-  if (threadIdx.x == 0) *out = t;
+  if (threadIdx.x == 0) *out = acc ? fma(scale, t, *out) : t;
 }
 
 void ek_pressure_functional(const ElemArgs& a, const double* u_int, double p_ref, double* value, double* grad_int,
-                            double* part, hipStream_t st) {
+                            double* part, hipStream_t st, int acc, double scale) {
   const dim3 g = grid_for((size_t)a.Epad);
   launch(pfun_kernel, g, dim3(EK_T), 0, st, a, u_int, p_ref, part, grad_int);
-  launch(pfun_finalize, dim3(1), dim3(64), 0, st, (const double*)part, (int)g.x, value);
+  if (value) launch(pfun_finalize, dim3(1), dim3(64), 0, st, (const double*)part, (int)g.x, value, acc, scale);
 }
 
 void ek_to_internal(const ElemArgs& a, const double* u_abi, double* u_int, hipStream_t st) {
   launch(to_internal_kernel, grid_for((size_t)a.Epad * a.nv), dim3(EK_T), 0, st, a, u_abi, u_int);
 }
 void ek_to_abi(const ElemArgs& a, const double* u_int, double* u_abi, hipStream_t st) {
-  launch(to_abi_kernel, grid_for((size_t)a.nE * a.nv), dim3(EK_T), 0, st, a, u_int, u_abi);
+  launch(to_abi_kernel, grid_for((size_t)a.nE * a.nv), dim3(EK_T), 0, st, a, u_int, u_abi, 0, 0.0);
+}
+void ek_to_abi_axpy(const ElemArgs& a, const double* u_int, double scale, double* u_abi, hipStream_t st) {
+  launch(to_abi_kernel, grid_for((size_t)a.nE * a.nv), dim3(EK_T), 0, st, a, u_int, u_abi, 1, scale);
 }
 void ek_quad_points(const ElemArgs& a, double* xyz, hipStream_t st) {
   launch(quad_points_kernel, grid_for((size_t)a.nE * a.nq), dim3(EK_T), 0, st, a, xyz);

@@ -1103,6 +1103,11 @@ void k_set_scalar(double* p, double v, hipStream_t st) {
   launch(set_scalar_kernel, dim3(1), dim3(1), 0, st, p, v);
 }
 
+__global__ void add_scalar_kernel(double* acc, const double* x) { *acc += *x; }
+void k_add_scalar(double* acc, const double* x, hipStream_t st) {
+  launch(add_scalar_kernel, dim3(1), dim3(1), 0, st, acc, x);
+}
+
 template <typename T>
 __global__ void gemv_kernel(const T* A, const T* v, T* out, int n, const double* vscale, const int* skip) {
   if (skip && *skip) return;

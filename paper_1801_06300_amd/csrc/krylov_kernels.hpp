@@ -140,6 +140,8 @@ void k_fd_eps(const double* unorm, const double* vnorm, double c0, double* eps, 
 template <typename TC>
 void k_glue_d(const double* a, const double* b, const TC* c, double* out, size_t n, hipStream_t st);
 void k_set_scalar(double* p, double v, hipStream_t st);
+// *acc += *x (one thread)
+void k_add_scalar(double* acc, const double* x, hipStream_t st);
 // dense operator: out = A (scale * v)
 template <typename T>
 void k_gemv(const T* A, const T* v, T* out, int n, const double* vscale, const int* skip,

@@ -23,6 +23,7 @@ namespace pcexp {
 thread_local LaunchTiming g_launch_timing;
 }  // namespace pcexp
 
+
 using namespace pcexp;
 
 namespace {
@@ -1021,10 +1022,16 @@ static pcexp_status advance_impl(pcexp_ctx* c, double* u, int nsteps, double dt,
   DtMode dm;
   dm.dt = dt > 0.0 ? dt : 0.0;
   dm.cfl = cfl;
+  // the time advanced: nsteps dt when every step takes the given dt, else the
+  // sum over the steps of the dt each one used (eq. (x3d) per step, or a dt
+  // the Krylov tolerance halved on the device), summed in scal[16]
+  const bool dt_varies = !(dt > 0.0) || c->krylov_tol > 0.0;
+  if (dt_varies && info) k_set_scalar(&scal[16], 0.0, st);
   for (int i = 0; i < nsteps; ++i) {
     k_fill<unsigned>(cnt, 0u, 64, nullptr, st);
     s = step_core(c, un, dm, m, scheme, prec, jvp, w, L, st);
     if (s != PCEXP_OK) return s;
+    if (dt_varies && info) k_add_scalar(&scal[16], &scal[0], st);
   }
   to_abi(c, un, u, st);
   s = hip_check(c, "step");
@@ -1033,7 +1040,7 @@ static pcexp_status advance_impl(pcexp_ctx* c, double* u, int nsteps, double dt,
     std::memset(info, 0, sizeof(*info));
     if (!c->dense) k_sumsq(Rn, (size_t)c->nb * c->Epad, &scal[4], 1, part, &cnt[3], st);
     KState h1, h2;
-    double sc[8];
+    double sc[17];
     if (hipMemcpyAsync(&h1, (KState*)(w + L.ks1), sizeof(KState), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipMemcpyAsync(&h2, (KState*)(w + L.ks2), sizeof(KState), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipMemcpyAsync(sc, scal, sizeof(sc), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -1043,6 +1050,7 @@ static pcexp_status advance_impl(pcexp_ctx* c, double* u, int nsteps, double dt,
     if (scheme == PCEXP_SCHEME_PCEXP) fill_info(&info->k2, h2);
     info->dt = sc[0];
     info->res_rho_norm = c->dense ? 0.0 : sc[4] / c->volume_total;
+    info->t_advanced = dt_varies ? sc[16] : nsteps * dt;
     return report_flags(c, &info->flags);
   }
   return PCEXP_OK;
@@ -1177,6 +1185,22 @@ pcexp_status pcexp_pressure_functional(pcexp_ctx* c, const double* u, double p_r
       hipStreamSynchronize(st) != hipSuccess)
     return fail(c, PCEXP_E_HIP, "pressure functional sync failed");
   return hip_check(c, "pressure_functional");
+}
+
+pcexp_status pcexp_pressure_functional_acc(pcexp_ctx* c, const double* u, double p_ref, double scale,
+                                           double* value_acc, double* grad_acc, void* stream) {
+  if (!c || !u) return c ? fail(c, PCEXP_E_ARG, "u is NULL") : PCEXP_E_ARG;
+  if (c->dense) return fail(c, PCEXP_E_UNSUPPORTED, "dense context has no mesh");
+  if (!value_acc && !grad_acc) return fail(c, PCEXP_E_ARG, "nothing to accumulate");
+  if (!std::isfinite(scale) || !std::isfinite(p_ref)) return fail(c, PCEXP_E_ARG, "scale and p_ref must be finite");
+  if ((const double*)grad_acc == u || (const double*)value_acc == u || (value_acc && value_acc == grad_acc))
+    return fail(c, PCEXP_E_ARG, "accumulators must not alias u or each other");
+  hipStream_t st = (hipStream_t)stream;
+  to_int(c, u, c->io[0], st);
+  ek_pressure_functional(elem_args(c), c->io[0], p_ref, value_acc, grad_acc ? c->io[1] : nullptr, c->part, st, 1,
+                         scale);
+  if (grad_acc) ek_to_abi_axpy(elem_args(c), c->io[1], scale, grad_acc, st);
+  return hip_check(c, "pressure_functional_acc");
 }
 
 size_t pcexp_step_vjp_workspace_bytes(const pcexp_ctx* c, int32_t m) {

@@ -136,6 +136,30 @@ def test_pressure_functional_parity():
     assert abs(float(np.sum(_n(grad) * d)) - cs) < 1e-11 * max(abs(cs), 1e-12)
 
 
+def test_pressure_functional_acc_parity():
+    """value_acc += s P(u) and grad_acc += s dP/du on the device, against the
+    oracle's functional and its complex-step derivative; two calls in a row
+    accumulate."""
+    g, ctx, u = _pair("sq4j", 2, "roe")
+    ud = _t(u)
+    val = torch.full((), 0.5, dtype=torch.float64, device="cuda")
+    r0 = W.random_unit_vector(u.shape, 52)
+    grad = _t(r0)
+    s = 0.3
+    ctx.pressure_functional_acc(ud, s, 1.0, value_acc=val, grad_acc=grad)
+    ctx.pressure_functional_acc(ud, -0.1, 1.0, value_acc=val)
+    P = pressure_fluctuation(g, u, 1.0)
+    assert abs(float(val) - (0.5 + 0.2 * P)) < 1e-12 * abs(0.5 + 0.2 * P)
+    d = W.random_unit_vector(u.shape, 51)
+    cs = np.imag(pressure_fluctuation(g, u + 1e-30j * d, 1.0)) / 1e-30
+    got = float(np.sum((_n(grad) - r0) * d)) / s
+    assert abs(got - cs) < 1e-11 * max(abs(cs), 1e-12)
+    with pytest.raises(Exception):
+        ctx.pressure_functional_acc(ud, s, 1.0)            # nothing to accumulate
+    with pytest.raises(Exception):
+        ctx.pressure_functional_acc(ud, s, 1.0, grad_acc=ud)  # aliasing
+
+
 def test_trajectory_gradient_checkpointed():
     """Gradient of sum_n dt int (p - 1)^2 over 5 steps with checkpoints every
     2 steps, against the oracle's Richardson derivative of the same sum."""
