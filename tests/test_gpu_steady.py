@@ -83,6 +83,29 @@ def test_step_krylov_dt_control_parity():
     ctx.set_krylov_tol(0.0)
 
 
+def test_advance_reports_time_advanced():
+    """pcexp_advance's t_advanced: with dt from eq. (x3d) per step (cfl mode)
+    and with a Krylov tolerance that halves dt on the device, it equals the
+    sum of the dt reported by the same steps taken one call at a time; with a
+    fixed dt and no tolerance it is nsteps dt."""
+    g, ctx, u = _setup(2)
+    for tol, cfl in ((0.0, 3.0), (1e-7, 200.0)):
+        ctx.set_krylov_tol(tol)
+        ua, ub = _t(u), _t(u)
+        info = ctx.advance(ua, 4, cfl=cfl, m=12, info=True)
+        total = 0.0
+        for _ in range(4):
+            total += ctx.step(ub, cfl=cfl, m=12, info=True)["dt"]
+        print(f"[t] tol {tol} cfl {cfl}: t_advanced {info['t_advanced']:.15e} sum {total:.15e} "
+              f"last halvings {info['k1']['dt_halvings']}", flush=True)
+        assert abs(info["t_advanced"] - total) <= 1e-12 * total
+        if tol > 0.0:
+            assert info["k1"]["dt_halvings"] > 0
+    ctx.set_krylov_tol(0.0)
+    info = ctx.advance(_t(u), 3, dt=0.01, m=12, info=True)
+    assert info["t_advanced"] == 3 * 0.01
+
+
 def test_steady_with_krylov_control_parity():
     g, ctx, u = _setup(2)
     ctx.set_krylov_tol(1e-5)
@@ -144,3 +167,55 @@ def test_steady_exp1_adaptive_dimension_parity():
     want, hist = steady_iterations(g, ExactJacobian(g), u, 4, 1000.0, 30, "exp1", krylov_tol=1e-5,
                                    krylov_every=3)
     assert rel(ud.cpu().numpy(), want) < 1e-9
+
+
+def test_open_channel_p2_converges_f64_and_mixed():
+    """The bump channel with a far-field top (the steady workload's geometry)
+    at 96x32x2, P2 Roe, from the uniform free stream with the paper's steady
+    settings: PCEXP, m = 30, the eq. (cfl) ramp to CFL_max 1000 and the
+    Krylov tolerance 1e-5 (the predictor's dt control): both precisions reach
+    ||R(rho)|| <= 1e-10, and the two converged states differ by at most 1e-9
+    relative (both solve R(u) = 0 with FP64 stage residuals)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1801_06300_amd import PCEXP
+    m = W.channel_bump(96, 32, height=0.1, jitter=0.15, seed=302, top_bc=W.BC_FARFIELD)
+    prim = W.freestream_prim(2, angle_deg=0.0)
+    print(f"\n[case] open channel 96x32 P2, nE={m.n_elem}", flush=True)
+    ctx = PCEXP(m, 2, "roe", farfield_prim=prim)
+    xq = ctx.quad_points().cpu().numpy()
+    Uq = W.uniform_state(xq.reshape(-1, 2), prim).reshape(ctx.nE, ctx.nq, ctx.nv)
+    u0 = ctx.project(torch.as_tensor(Uq, device="cuda")).contiguous()
+    ctx.set_krylov_tol(1e-5)
+    out = {}
+    for prec in ("f64", "mixed"):
+        u = u0.clone()
+        info = ctx.steady(u, cfl_max=1000.0, tol=1e-10, max_iter=4000, check_every=50, m=30, prec=prec)
+        print(f"[open] {prec}: {info}", flush=True)
+        assert info["converged"] and info["res_rho_norm"] <= 1e-10
+        out[prec] = u
+    ctx.set_krylov_tol(0.0)
+    d = float(torch.linalg.norm(out["mixed"] - out["f64"]) / torch.linalg.norm(out["f64"]))
+    print(f"[open] converged mixed vs FP64 relative state difference {d:.3e}", flush=True)
+    assert d <= 1e-9
+
+
+def test_open_channel_krylov_control_parity():
+    """Four ramped iterations with the Krylov tolerance on the 12x4 P2 channel
+    with a far-field top equal the oracle's."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1801_06300_amd import PCEXP
+    m = W.channel_bump(12, 4, height=0.1, seed=5, top_bc=W.BC_FARFIELD)
+    prim = W.freestream_prim(2, angle_deg=0.0)
+    g = DG(m, 2, "roe", farfield_prim=prim)
+    ctx = PCEXP(m, 2, "roe", farfield_prim=prim)
+    u = g.project(lambda x: W.uniform_state(x, prim))
+    ctx.set_krylov_tol(1e-5)
+    ud = _t(u)
+    ctx.steady(ud, cfl_max=1000.0, tol=0.0, max_iter=4, check_every=1, m=30)
+    ctx.set_krylov_tol(0.0)
+    want, hist = steady_iterations(g, ExactJacobian(g), u, 4, 1000.0, 30, krylov_tol=1e-5)
+    e = rel(ud.cpu().numpy(), want)
+    print(f"[open] 4 iterations vs oracle rel {e:.3e}", flush=True)
+    assert e < 1e-9

@@ -130,13 +130,14 @@ def bump_height(x, height=0.1, width=0.25):
 
 
 def channel_bump(nx, ny, height=0.1, jitter=0.15, seed=None, x0=-3.0, x1=3.0,
-                 y_top=2.0, name=""):
+                 y_top=2.0, top_bc=BC_SLIP, name=""):
     """Channel x in [x0, x1], y in [y_b(x), y_top] with a Gaussian bump.
 
     Structured (x, eta) grid mapped by y = y_b(x) + eta (y_top - y_b(x));
     interior vertices are jittered by U(-jitter, jitter) of the local
-    spacing in x and in eta.  Bottom and top are slip walls, left and right
-    are far-field boundaries.
+    spacing in x and in eta.  The bottom (with the bump) is a slip wall, the
+    top boundary y = y_top has the tag ``top_bc`` (a slip wall by default),
+    left and right are far-field boundaries.
     """
     xs = np.linspace(x0, x1, nx + 1)
     es = np.linspace(0.0, 1.0, ny + 1)
@@ -164,11 +165,11 @@ def channel_bump(nx, ny, height=0.1, jitter=0.15, seed=None, x0=-3.0, x1=3.0,
     left = np.stack([vid(0, j), vid(0, j + 1)], axis=-1)
     right = np.stack([vid(nx, j), vid(nx, j + 1)], axis=-1)
     bface = np.concatenate([bottom, top, left, right]).astype(np.int32)
-    tag = np.concatenate([np.full(nx, BC_SLIP), np.full(nx, BC_SLIP),
+    tag = np.concatenate([np.full(nx, BC_SLIP), np.full(nx, top_bc),
                           np.full(ny, BC_FARFIELD), np.full(ny, BC_FARFIELD)]).astype(np.int32)
     return MeshArrays(dim=2, vert=vert, elem=elem, vert_canon=None, bface=bface,
                       bface_tag=tag, period=np.zeros(2), name=name or f"channel_{nx}x{ny}",
-                      meta=dict(nx=nx, ny=ny, height=height, jitter=jitter, seed=seed))
+                      meta=dict(nx=nx, ny=ny, height=height, jitter=jitter, seed=seed, top_bc=top_bc))
 
 
 def periodic_cube(n, length, name=""):
