@@ -121,6 +121,23 @@ def test_fullsize_residual_and_jvps():
     assert rel(Jf, Jo) < 1e-5
 
 
+def test_fullsize_residual_perturbed_state():
+    """The residual of the full-size vortex plus a seeded 1e-3 perturbation of
+    every coefficient: the perturbation's flux differences are not small
+    against the flux terms, so summation-order rounding stays below the FP64
+    bar of 1e-11 here (the bar the smooth state needs is the floor-derived
+    one of test_fullsize_residual_and_jvps, printed beside it)."""
+    c = _full()
+    g, ctx, u0 = c["g"], c["ctx"], c["u0"]
+    u1 = u0 + W.perturbation(u0.shape, 7, 1e-3)
+    Ro = g.residual(u1)
+    R = _n(ctx.residual(_t(u1)))
+    e = rel(R, Ro)
+    print(f"[full] perturbed-state residual rel {e:.3e} (bar 1e-11; smooth-state floor bar {c['tol_r']:.2e})",
+          flush=True)
+    assert e < 1e-11
+
+
 def test_fullsize_stable_dt():
     c = _full()
     dt = c["ctx"].stable_dt(_t(c["u0"]), c["cfg"]["cfl"])
