@@ -9,10 +9,20 @@ through the C ABI; the timed steps run in one pcexp_advance call, which keeps
 the state in the internal basis between steps.  Inputs are resident in HBM
 before the timed region.
 
+Each step takes dt from eq. (x3d) at its own u_n (CFL 20) on the device;
+the time reached is read back from the call and the exact solution (the
+translated vortex) is evaluated there.
+
 Prints one JSON line.  `value` is the FP64 tangent-JVP variant; the FP64
 finite-difference JVP and the mixed FP32/FP64 tangent variants, and ETD2
-(eq. (s7), FP64 tangent), are timed on the same workload and time levels and
-reported in `variants` with their solution error.
+(eq. (s7), FP64 tangent, dt fixed from u_0), are timed on the same workload
+and reported in `variants` with their solution error.  The default run adds
+sections (progress on stderr): `measurement` (cold-cache standalone JVP and
+the timed 1 GiB copy), `adjoint` (the 40-step checkpointed gradient),
+`channel` (the steady bump channel converged to ||R(rho)|| <= 1e-10 in FP64
+and mixed precision), `vortex3d` (the 48^3 x 6 tetrahedral P2 vortex, mixed
+precision), and `cpu_baseline` (one full step of the FP64 oracle on the
+host).
 """
 
 import argparse
@@ -67,6 +77,11 @@ def traffic_per_launch(cls):
     return float(vals["traffic_bytes_per_launch"])
 
 
+def log(msg):
+    """Progress line on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,64 +92,62 @@ def parse():
     ap.add_argument("--workload", default="vortex2d", choices=["vortex2d", "channel", "vortex3d", "stiffvortex"],
                     help="vortex2d: the headline PCEXP step benchmark; channel: steady bump channel to "
                          "||R(rho)|| <= 1e-10 with the CFL ramp; vortex3d: 3D P2 vortex, mixed precision")
+    ap.add_argument("--sections", default="all",
+                    help="extra sections of the default run, comma separated: measurement, adjoint, channel, "
+                         "vortex3d; 'all' (default) or 'none'")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counter calibration)")
     return ap.parse_args()
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(mesh, cfg, u0_np, K):
-    """Time the FP64 oracle on a bounded sample of the same workload (about
-    10 s on 16 cores): two residuals, 24 complex-step JVPs and the 30
-    modified Gram-Schmidt projections of one late Arnoldi iteration, all at
-    full size.  A PCEXP step costs 2 residuals + (2m+1) JVPs + two MGS
-    Arnoldi runs (sum_{j<m} (j+1) projections each), from which seconds per
-    step are extrapolated."""
-    import numpy as np
+    """Time one full PCEXP step of the FP64 oracle (2 residuals, 2m + 1
+    complex-step JVPs, two modified Gram-Schmidt Arnoldi runs, expm of the
+    Hessenberg matrices, the corrector) on the host, on the same workload
+    and state, dt from eq. (x3d) at u_0.  `cores` is the parallelism the
+    step actually used: process CPU time over wall time (NumPy's
+    elementwise work, most of the residual and JVP, runs on one thread;
+    BLAS calls may use the threads OMP/OPENBLAS_NUM_THREADS allow)."""
     from oracle.dg import DG
-    from oracle.derivatives import jvp_cs
-    import workloads as W
+    from oracle.integrators import ExactJacobian, pcexp_step, stable_dt
 
-    threads = len(os.sched_getaffinity(0))
     g = DG(mesh, cfg["p"], cfg["flux"])
-    u = u0_np
-    t0 = time.perf_counter()
-    for _ in range(2):
-        R = g.residual(u)
-    t_res = (time.perf_counter() - t0) / 2
-    v = W.random_unit_vector(u.shape, 1)
-    njvp = 24
-    t0 = time.perf_counter()
-    for _ in range(njvp):
-        jvp_cs(g, u, v)
-    t_jvp = (time.perf_counter() - t0) / njvp
-    m = cfg["m"]
-    nproj = m
-    Vb = np.random.default_rng(0).standard_normal((K, nproj))
-    w = R.ravel().copy()
-    t0 = time.perf_counter()
-    for i in range(nproj):
-        h = Vb[:, i] @ w
-        w = w - h * Vb[:, i]
-    t_proj = (time.perf_counter() - t0) / nproj
-    t_gs = t_proj * (m * (m + 1) / 2)     # MGS of one Arnoldi run
-    s_step = 2 * t_res + (2 * m + 1) * t_jvp + 2 * t_gs
-    sample_s = 2 * t_res + njvp * t_jvp + nproj * t_proj
-    return dict(value=K / s_step, unit="DOF-updates/s", cores=threads, kind="oracle",
-                sample=(f"128x128 P2 vortex size, FP64 NumPy oracle, {sample_s:.1f} s measured: 2 residuals "
-                        f"({t_res:.2f} s each), {njvp} complex-step JVPs ({t_jvp:.2f} s each), {nproj} MGS "
-                        f"projections ({1e3 * t_proj:.1f} ms each); per step = 2 R + {2 * m + 1} JVP + "
-                        f"2 Arnoldi MGS = {s_step:.1f} s extrapolated"),
-                seconds_per_step=s_step)
+    dt = stable_dt(g, u0_np, cfg["cfl"])
+    log("cpu baseline: one oracle PCEXP step at full size")
+    c0, t0 = time.process_time(), time.perf_counter()
+    pcexp_step(ExactJacobian(g), u0_np, dt, cfg["m"])
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    return dict(value=K / wall, unit="DOF-updates/s", cores=round(cpu / wall, 2), kind="oracle",
+                sample=(f"one full FP64 oracle PCEXP step on the 128x128 P2 Roe vortex (K = {K}, m = {cfg['m']}, "
+                        f"{2 * cfg['m'] + 1} complex-step JVPs), measured: {wall:.1f} s wall, {cpu:.1f} s CPU"),
+                seconds_per_step=wall, cpu_model=_cpu_model(), affinity_cpus=len(os.sched_getaffinity(0)),
+                thread_env=env,
+                note="NumPy elementwise work is single-threaded; cores = CPU time / wall time of the step")
 
 
-def bench_channel(args, dev):
-    """Steady subsonic channel over a Gaussian bump (384x128x2 jittered
-    triangles, P2 Roe, Mach 0.5): pseudo-time PCEXP with the CFL ramp of
-    eq. (cfl) (CFL_max 1000, m = 30) from the uniform free stream, in FP64
-    and in mixed precision, for at most `--steps` pseudo-time steps or until
-    ||R(rho)|| <= 1e-10.  With a fixed Krylov dimension this P2 case does not
-    converge at the ramp's CFL (it does on small P1 channels); the line then
-    reports the throughput and the residual reached."""
+def section_channel(dev, max_iter=12000):
+    """Steady subsonic flow over a Gaussian bump (384x128x2 jittered
+    triangles, P2 Roe, Mach 0.5; slip wall along the bump, characteristic
+    far field at inflow, outflow and top): pseudo-time PCEXP from the
+    uniform free stream with the paper's steady settings (m = 30, the CFL
+    ramp of eq. (cfl) to CFL_max 1000, Krylov tolerance 1e-5 controlling
+    the predictor's dt), in FP64 and in mixed precision, until
+    ||R(rho)|| <= 1e-10 or max_iter iterations.  Reports iterations, wall
+    time and DOF-updates/s per precision and the relative difference of the
+    two converged states."""
     import torch
     import workloads as W
     from paper_1801_06300_amd import PCEXP, PcexpError
@@ -146,15 +159,17 @@ def bench_channel(args, dev):
     xq = ctx.quad_points().cpu().numpy()
     Uq = W.uniform_state(xq.reshape(-1, 2), prim).reshape(ctx.nE, ctx.nq, ctx.nv)
     u0 = ctx.project(torch.as_tensor(Uq, device=dev)).contiguous()
-    res = {}
+    ctx.set_krylov_tol(cfg["krylov_tol"])
+    res, states = {}, {}
     for prec in ("f64", "mixed"):
+        log(f"channel: steady run, {prec}")
+        ctx.steady(u0.clone(), cfl_max=cfg["cfl_max"], tol=1.0, max_iter=1, m=cfg["m"], prec=prec)   # warm-up
         u = u0.clone()
-        ctx.steady(u.clone(), cfl_max=cfg["cfl_max"], tol=1.0, max_iter=1, m=cfg["m"], prec=prec)   # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
-            info = ctx.steady(u, cfl_max=cfg["cfl_max"], tol=cfg["target_residual"], max_iter=args.steps,
-                              check_every=10, m=cfg["m"], prec=prec)
+            info = ctx.steady(u, cfl_max=cfg["cfl_max"], tol=cfg["target_residual"], max_iter=max_iter,
+                              check_every=100, m=cfg["m"], prec=prec)
         except PcexpError as e:
             res[prec] = dict(error=str(e))
             continue
@@ -162,18 +177,30 @@ def bench_channel(args, dev):
         wall = time.perf_counter() - t0
         res[prec] = dict(info, seconds=wall, ms_per_iteration=1e3 * wall / info["iterations"],
                          dofs_per_s=ctx.K * info["iterations"] / wall)
-    main = res.get("mixed", {})
-    out = {
-        "metric": "PCEXP DOF-updates/s (steady channel, CFL ramp)",
+        states[prec] = u
+    ctx.set_krylov_tol(0.0)
+    out = dict(workload="steady bump channel 384x128x2 jittered (98304 triangles), DG P2, Roe, Mach 0.5, "
+                        "PCEXP m=30, CFL ramp eq. (cfl) to 1000, Krylov tolerance 1e-5, target ||R(rho)|| 1e-10",
+               K=ctx.K, runs=res)
+    if len(states) == 2:
+        out["converged_state_rel_diff_mixed_vs_f64"] = float(
+            torch.linalg.norm(states["mixed"] - states["f64"]) / torch.linalg.norm(states["f64"]))
+    return out
+
+
+def bench_channel(args, dev):
+    out = section_channel(dev)
+    main = out["runs"].get("mixed", {})
+    line = {
+        "metric": "PCEXP DOF-updates/s (steady channel to ||R(rho)|| <= 1e-10)",
         "value": round(main.get("dofs_per_s", 0.0), 1), "unit": "DOF-updates/s", "n_gpus": 1,
         "steps": main.get("iterations", 0), "warmup": 1,
         "ms_per_step": round(main.get("ms_per_iteration", 0.0), 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64 (mixed)", "data": "synthetic",
-        "config": {"workload": "steady bump channel, 384x128x2 jittered triangles (98304), DG P2, Roe, "
-                               "Mach 0.5, m=30, CFL ramp to 1000, mixed precision", "K": ctx.K},
-        "runs": res,
+        "config": {"workload": out["workload"] + ", mixed precision", "K": out["K"]},
+        "channel": out,
     }
-    print(json.dumps(out))
+    print(json.dumps(line))
 
 
 def bench_stiffvortex(args, dev):
@@ -255,14 +282,17 @@ def bench_stiffvortex(args, dev):
     print(json.dumps(out))
 
 
-def bench_vortex3d(args, dev):
+def section_vortex3d(dev, steps, warmup):
     """3D vortex column (48^3 cubes x 6 tetrahedra, P2, LF), mixed precision,
-    m = 30, CFL 10 (dt from eq. (x3d) at u_0), `steps` PCEXP steps."""
+    m = 30, CFL 10 (dt from eq. (x3d) at each step's u_n), `steps` PCEXP steps
+    in one pcexp_advance call; then two profiled steps for the per-kernel
+    event times (the FP32 JVP's algorithmic GB/s among them)."""
     import torch
     import workloads as W
     from paper_1801_06300_amd import PCEXP
 
     cfg = W.get_config("vortex3d_p2_48cube_lf")
+    log("vortex3d: mesh and context")
     mesh = W.build_mesh(cfg)
     ctx = PCEXP(mesh, cfg["p"], cfg["flux"], device=dev)
     xq = ctx.quad_points().cpu().numpy()
@@ -270,34 +300,123 @@ def bench_vortex3d(args, dev):
     Uq = W.isentropic_vortex(xq.reshape(-1, 3), center=c, period=mesh.period).reshape(ctx.nE, ctx.nq, ctx.nv)
     u0 = ctx.project(torch.as_tensor(Uq, device=dev))
     u0 = (u0 + torch.as_tensor(W.perturbation(tuple(u0.shape), cfg["pert_seed"]), device=dev)).contiguous()
-    dt = ctx.stable_dt(u0, cfg["cfl"])
-    steps = min(args.steps, cfg["steps"])
+    del xq, Uq
     u = u0.clone()
-    if args.warmup > 0:
-        ctx.advance(u, args.warmup, dt=dt, m=cfg["m"], prec="mixed")
+    if warmup > 0:
+        ctx.advance(u, warmup, cfl=cfg["cfl"], m=cfg["m"], prec="mixed")
     u = u0.clone()
+    log(f"vortex3d: {steps} timed steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.advance(u, steps, dt=dt, m=cfg["m"], prec="mixed")
+    info = ctx.advance(u, steps, cfl=cfg["cfl"], m=cfg["m"], prec="mixed", info=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctx.profile("start")
     u = u0.clone()
-    ctx.advance(u, 2, dt=dt, m=cfg["m"], prec="mixed")
+    ctx.advance(u, 2, cfl=cfg["cfl"], m=cfg["m"], prec="mixed")
     prof = ctx.profile("read")
     ctx.profile("stop")
     kern = {k: dict(ms_total=v[0], launches=v[1], avg_us=(1e3 * v[0] / v[1]) if v[1] else 0.0,
                     gbs=(v[2] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else 0.0) for k, v in prof.items() if v[1]}
-    out = {
-        "metric": "PCEXP DOF-updates/s (3D vortex, mixed)", "value": round(ctx.K * steps / wall, 1),
+    out = dict(workload="3D isentropic vortex column, periodic [0,10]^3, 48^3 cubes x 6 tetrahedra (663552), "
+                        "DG P2, LF, m=30, CFL 10 (dt from eq. x3d each step), mixed precision",
+               K=ctx.K, steps=steps, warmup=warmup, ms_per_step=1e3 * wall / steps, dofs_per_s=ctx.K * steps / wall,
+               t_advanced=info["t_advanced"], kernels=kern)
+    del ctx, u, u0
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_vortex3d(args, dev):
+    steps = min(args.steps, 20)
+    out = section_vortex3d(dev, steps, args.warmup)
+    line = {
+        "metric": "PCEXP DOF-updates/s (3D vortex, mixed)", "value": round(out["dofs_per_s"], 1),
         "unit": "DOF-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
-        "ms_per_step": round(1e3 * wall / steps, 4), "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": round(out["ms_per_step"], 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64 (mixed)", "data": "synthetic",
-        "config": {"workload": "3D isentropic vortex column, periodic [0,10]^3, 48^3 cubes x 6 tetrahedra "
-                               "(663552), DG P2, LF, m=30, CFL 10, mixed precision", "K": ctx.K, "dt": dt},
-        "kernels": kern,
+        "config": {"workload": out["workload"], "K": out["K"]}, "vortex3d": out,
     }
-    print(json.dumps(out))
+    print(json.dumps(line))
+
+
+def section_adjoint(dev, ctx, u0, dt_fixed):
+    """Gradient of J(u_0) = sum_{n=1}^{40} dt int (p_h(t_n) - 1)^2 dx through 40
+    PCEXP steps (dt frozen from u_0, m = 30, checkpoints every 8) on the
+    headline mesh and state, behind torch.autograd: forward time, gradient
+    (forward + reverse) time, their ratio, and the peak device memory the
+    gradient call holds beyond what was allocated before it."""
+    import torch
+    import workloads as W
+    from paper_1801_06300_amd.adjoint import Trajectory, objective
+
+    cfg = W.get_config("adjoint_vortex2d_p2_128x128_roe")
+    traj = Trajectory(ctx, dt_fixed, nsteps=cfg["steps"], m=cfg["m"], every=cfg["checkpoint_every"])
+    log("adjoint: 40-step trajectory gradient")
+    traj.value(u0)                                 # warm-up (allocations, kernels)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    val = traj.value(u0)
+    t_fwd = time.perf_counter() - t0
+    x = u0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated(dev)
+    torch.cuda.reset_peak_memory_stats(dev)
+    t0 = time.perf_counter()
+    J = objective(traj)(x)
+    J.backward()
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    peak = torch.cuda.max_memory_allocated(dev) - base
+    return dict(workload="gradient of sum_n dt int (p_h - 1)^2 through 40 PCEXP steps on the 128x128 P2 Roe vortex, "
+                         "dt frozen from u_0 (CFL 20), m=30, checkpoints every 8, FP64, torch.autograd.Function",
+                value=val, forward_s=t_fwd, gradient_s=t_grad, gradient_over_forward=t_grad / t_fwd,
+                peak_bytes_beyond_inputs=int(peak),
+                states_held=traj.peak_states())
+
+
+def section_measurement(dev, ctx, u0):
+    """Cold-cache standalone JVP and the measured copy bandwidth.  Each timed
+    JVP launch follows a write of a 1 GiB buffer (larger than the 256 MB
+    Infinity Cache and the L2s), so its inputs come from HBM; the kernel's
+    own execution time comes from the library's event pair on its dispatch.
+    The copy is a 1 GiB device-to-device copy timed with HIP events
+    (2 GiB moved per copy)."""
+    import torch
+    import workloads as W
+
+    out = {}
+    flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    v = torch.as_tensor(W.random_unit_vector(tuple(u0.shape), 7), device=dev)
+    for prec in ("f64", "mixed"):
+        ctx.jvp(u0, v, "tangent", prec)
+        ctx.profile("start")
+        for i in range(10):
+            flush.fill_(float(i))
+            ctx.jvp(u0, v, "tangent", prec)
+        prof = ctx.profile("read")
+        ctx.profile("stop")
+        ms, n, nbytes = prof["jvp"]
+        out[f"jvp_cold_{prec}"] = dict(avg_us=1e3 * ms / n, launches=n, bytes_per_launch=nbytes / n,
+                                       gbs=nbytes / (ms * 1e-3) / 1e9)
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    s = ev0.elapsed_time(ev1) / 1e3 / 10
+    out["copy_1gib"] = dict(seconds=s, gbs=2 * src.numel() * 8 / s / 1e9,
+                            note="read 1 GiB + write 1 GiB per copy; the measured-copy denominator")
+    for k in ("jvp_cold_f64", "jvp_cold_mixed"):
+        out[k]["frac_of_copy"] = out[k]["gbs"] / out["copy_1gib"]["gbs"]
+        out[k]["frac_of_8tbs"] = out[k]["gbs"] / HBM_PEAK_GBS
+    del flush, src, dst
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -306,7 +425,6 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     import workloads as W
     from paper_1801_06300_amd import PCEXP
@@ -323,26 +441,28 @@ def main():
     if args.workload == "vortex3d":
         return bench_vortex3d(args, dev)
     cfg = W.get_config("vortex2d_p2_128x128_jitter_roe")
+    log("vortex2d: mesh and context")
     mesh = W.build_mesh(cfg)
     ctx = PCEXP(mesh, cfg["p"], cfg["flux"], device=dev)
     K = ctx.K
-    L = mesh.period[0]
     c = cfg["vortex_center"]
     xq = ctx.quad_points().cpu().numpy()
     Uq = W.isentropic_vortex(xq.reshape(-1, 2), center=c, period=mesh.period).reshape(ctx.nE, ctx.nq, ctx.nv)
     u0 = ctx.project(torch.as_tensor(Uq, device=dev))
     u0 = u0 + torch.as_tensor(W.perturbation(tuple(u0.shape), cfg["pert_seed"]), device=dev)
     u0 = u0.contiguous()
-    dt = ctx.stable_dt(u0, cfg["cfl"])
+    cfl = cfg["cfl"]
+    dt0 = ctx.stable_dt(u0, cfl)
     m = cfg["m"]
     steps, warm = args.steps, args.warmup
 
     def run(prec, jvp, nsteps, profile=False):
-        # the steps of a timed region run through pcexp_advance: the state stays
-        # in the internal basis between them (one change of basis in and out)
+        # the steps of a timed region run through one pcexp_advance call: the
+        # state stays in the internal basis between them, and each step takes
+        # dt from eq. (x3d) at its own u_n (CFL 20) on the device
         u = u0.clone()
         if warm > 0:
-            ctx.advance(u, warm, dt=dt, m=m, prec=prec, jvp=jvp)
+            ctx.advance(u, warm, cfl=cfl, m=m, prec=prec, jvp=jvp)
         u = u0.clone()
         torch.cuda.synchronize()
         if profile:
@@ -350,7 +470,7 @@ def main():
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         ev0.record()
-        ctx.advance(u, nsteps, dt=dt, m=m, prec=prec, jvp=jvp)
+        info = ctx.advance(u, nsteps, cfl=cfl, m=m, prec=prec, jvp=jvp, info=True)
         ev1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -358,55 +478,63 @@ def main():
         if profile:
             prof = ctx.profile("read")
             ctx.profile("stop")
-        return u, wall, ev0.elapsed_time(ev1) / 1e3, prof
+        return u, wall, ev0.elapsed_time(ev1) / 1e3, prof, info["t_advanced"]
 
-    u_t64, wall, gpu_s, _ = run("f64", "tangent", steps)
+    log(f"vortex2d: {steps} timed FP64 tangent steps")
+    u_t64, wall, gpu_s, _, tN = run("f64", "tangent", steps)
     value = K * steps / wall
 
-    # exact solution at t_N (translation of the vortex), projected; L2 error of the coefficients
-    tN = steps * dt
-    Ue = W.isentropic_vortex(xq.reshape(-1, 2), t=tN, center=c, period=mesh.period).reshape(ctx.nE, ctx.nq, ctx.nv)
-    ue = ctx.project(torch.as_tensor(Ue, device=dev))
-
-    def err(u):
+    def err(u, t):
+        # L2 (coefficient 2-norm) error against the projected exact solution: the vortex translated to time t
+        Ue = W.isentropic_vortex(xq.reshape(-1, 2), t=t, center=c, period=mesh.period).reshape(ctx.nE, ctx.nq,
+                                                                                               ctx.nv)
+        ue = ctx.project(torch.as_tensor(Ue, device=dev))
         return float(torch.linalg.norm(u - ue).item())
 
-    variants = {"t64": dict(dofs_per_s=value, ms_per_step=1e3 * wall / steps, l2_error=err(u_t64))}
+    variants = {"t64": dict(dofs_per_s=value, ms_per_step=1e3 * wall / steps, t_final=tN, l2_error=err(u_t64, tN))}
     if not args.no_variants:
         for name, prec, jvp in (("fd64", "f64", "fd"), ("tmix", "mixed", "tangent")):
-            u, w_s, _, _ = run(prec, jvp, steps)
-            variants[name] = dict(dofs_per_s=K * steps / w_s, ms_per_step=1e3 * w_s / steps, l2_error=err(u),
+            log(f"vortex2d: variant {name}")
+            u, w_s, _, _, t_v = run(prec, jvp, steps)
+            variants[name] = dict(dofs_per_s=K * steps / w_s, ms_per_step=1e3 * w_s / steps, t_final=t_v,
+                                  l2_error=err(u, t_v),
                                   rel_diff_vs_t64=float((torch.linalg.norm(u - u_t64) /
                                                          torch.linalg.norm(u_t64)).item()))
-        # ETD2 (eq. (s7)) on the same time levels: the first step is ETD1, later ones use one step of history
+
+        # ETD2 (eq. (s7)) with dt fixed from u_0 (its difference quotient assumes a constant step);
+        # the first step is ETD1, later ones use one step of history
         def run_etd2(nsteps):
             u = u0.clone()
             u_prev, r_prev = torch.empty_like(u0), torch.empty_like(u0)
             for i in range(warm):
-                ctx.step_etd2(u, u_prev, r_prev, i > 0, dt, m=m)
+                ctx.step_etd2(u, u_prev, r_prev, i > 0, dt0, m=m)
             u = u0.clone()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for i in range(nsteps):
-                ctx.step_etd2(u, u_prev, r_prev, i > 0, dt, m=m)
+                ctx.step_etd2(u, u_prev, r_prev, i > 0, dt0, m=m)
             torch.cuda.synchronize()
             return u, time.perf_counter() - t0
 
+        log("vortex2d: variant etd2")
         u, w_s = run_etd2(steps)
-        variants["etd2"] = dict(dofs_per_s=K * steps / w_s, ms_per_step=1e3 * w_s / steps, l2_error=err(u),
+        variants["etd2"] = dict(dofs_per_s=K * steps / w_s, ms_per_step=1e3 * w_s / steps, t_final=steps * dt0,
+                                l2_error=err(u, steps * dt0),
                                 rel_diff_vs_t64=float((torch.linalg.norm(u - u_t64) /
-                                                       torch.linalg.norm(u_t64)).item()))
+                                                       torch.linalg.norm(u_t64)).item()),
+                                note="dt fixed from u_0")
 
     # reverse mode (discrete adjoint of one step, fixed dt): time per step_vjp vs forward step
     reverse = None
     if not args.no_variants:
+        log("vortex2d: reverse step")
         ub = torch.as_tensor(W.random_unit_vector(tuple(u0.shape), 501), device=dev)
-        ctx.step_vjp(u0, ub, dt, m=m)
+        ctx.step_vjp(u0, ub, dt0, m=m)
         torch.cuda.synchronize()
         nrev = 3
         t0 = time.perf_counter()
         for _ in range(nrev):
-            ctx.step_vjp(u0, ub, dt, m=m)
+            ctx.step_vjp(u0, ub, dt0, m=m)
         torch.cuda.synchronize()
         rev_s = (time.perf_counter() - t0) / nrev
         reverse = dict(ms_per_step_vjp=1e3 * rev_s, ratio_to_forward=rev_s / (wall / steps),
@@ -414,7 +542,8 @@ def main():
                        note="recomputes the forward step with both Krylov bases, then the reverse sweep")
 
     # live per-kernel timing (HIP events on the step's stream) over a second timed region
-    _, _, _, prof = run("f64", "tangent", steps, profile=True)
+    log("vortex2d: profiled steps")
+    _, _, _, prof, _ = run("f64", "tangent", steps, profile=True)
     kern = {k: dict(ms_total=v[0], launches=v[1], avg_us=(1e3 * v[0] / v[1]) if v[1] else 0.0,
                     gbs=(v[2] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else 0.0) for k, v in prof.items() if v[1]}
     # dominant kernel: most GPU time among the kernels that move HBM bytes
@@ -442,9 +571,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "2D isentropic vortex, periodic [0,20]^2, 128x128x2 jittered triangles (32768), "
-                               "DG P2, Roe, m=30, CFL 20 (dt from eq. x3d at u_0), FP64 tangent JVP",
-                   "K": K, "n_elem": ctx.nE, "p": cfg["p"], "flux": cfg["flux"], "m": m, "cfl": cfg["cfl"],
-                   "dt": dt},
+                               "DG P2, Roe, m=30, CFL 20 (dt from eq. x3d at each step's u_n), FP64 tangent JVP",
+                   "K": K, "n_elem": ctx.nE, "p": cfg["p"], "flux": cfg["flux"], "m": m, "cfl": cfl,
+                   "dt_first": dt0, "t_final": tN},
         "jvp_gbs": round(jvp_gbs, 1),
         "roofline": roofline,
         "variants": variants,
@@ -461,8 +590,21 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8, "launches": 3}
         del src, dst
+    sections = set(args.sections.split(",")) if args.sections != "all" else {"measurement", "adjoint", "channel",
+                                                                             "vortex3d"}
+    if "measurement" in sections:
+        log("measurement: cold-cache JVP and timed copy")
+        out["measurement"] = section_measurement(dev, ctx, u0)
+    if "adjoint" in sections:
+        out["adjoint"] = section_adjoint(dev, ctx, u0, dt0)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mesh, cfg, u0.cpu().numpy(), K)
+    del ctx
+    torch.cuda.empty_cache()
+    if "channel" in sections:
+        out["channel"] = section_channel(dev)
+    if "vortex3d" in sections:
+        out["vortex3d"] = section_vortex3d(dev, 20, 2)
     print(json.dumps(out))
 
 
