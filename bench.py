@@ -92,6 +92,8 @@ def parse():
     ap.add_argument("--workload", default="vortex2d", choices=["vortex2d", "channel", "vortex3d", "stiffvortex"],
                     help="vortex2d: the headline PCEXP step benchmark; channel: steady bump channel to "
                          "||R(rho)|| <= 1e-10 with the CFL ramp; vortex3d: 3D P2 vortex, mixed precision")
+    ap.add_argument("--channel-iters", type=int, default=12000,
+                    help="iteration cap of the steady channel runs (a short cap serves profiling)")
     ap.add_argument("--sections", default="all",
                     help="extra sections of the default run, comma separated: measurement, adjoint, channel, "
                          "vortex3d; 'all' (default) or 'none'")
@@ -189,7 +191,7 @@ def section_channel(dev, max_iter=12000):
 
 
 def bench_channel(args, dev):
-    out = section_channel(dev)
+    out = section_channel(dev, max_iter=args.channel_iters)
     main = out["runs"].get("mixed", {})
     line = {
         "metric": "PCEXP DOF-updates/s (steady channel to ||R(rho)|| <= 1e-10)",
@@ -602,7 +604,7 @@ def main():
     del ctx
     torch.cuda.empty_cache()
     if "channel" in sections:
-        out["channel"] = section_channel(dev)
+        out["channel"] = section_channel(dev, max_iter=args.channel_iters)
     if "vortex3d" in sections:
         out["vortex3d"] = section_vortex3d(dev, 20, 2)
     print(json.dumps(out))

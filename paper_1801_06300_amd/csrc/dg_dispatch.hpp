@@ -41,9 +41,9 @@ struct ElemArgs {
   double gamma;
 };
 void ek_to_internal(const ElemArgs& a, const double* u_abi, double* u_int, hipStream_t st);
-// value = int (p_h - p_ref)^2 dx (device scalar); grad_int (optional) its
-// gradient with respect to the internal coefficients; part >= Epad/256 doubles.
-// value (device): P(u), or value += scale P(u) when acc; value may be NULL.
+// value = int (p_h - p_ref)^2 dx (device scalar; with acc, value += scale times
+// it; may be NULL); grad_int (optional) its gradient with respect to the
+// internal coefficients; part >= Epad/256 doubles.
 void ek_pressure_functional(const ElemArgs& a, const double* u_int, double p_ref, double* value, double* grad_int,
                             double* part, hipStream_t st, int acc = 0, double scale = 1.0);
 void ek_to_abi(const ElemArgs& a, const double* u_int, double* u_abi, hipStream_t st);
