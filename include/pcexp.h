@@ -203,6 +203,25 @@ pcexp_status pcexp_step(pcexp_ctx* ctx, double* u, double dt, double cfl, int32_
                         int32_t scheme, int32_t prec, int32_t jvp, void* ws, size_t ws_bytes,
                         pcexp_step_info* info, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): pcexp_step with its
+ * workspace taken from a fixed device array owned by the library, of
+ * PCEXP_NOALLOC_WS_BYTES (64 MiB) on each GPU the library runs on, held until
+ * the process ends, instead of a caller-provided one.  The caller passes u
+ * and info as for pcexp_step; the call allocates nothing.  The context must
+ * be used on the device it was created on (PCEXP_E_ARG otherwise).
+ * PCEXP_E_WORKSPACE, before any work is enqueued, when
+ * pcexp_workspace_bytes(ctx, m, 1, prec, jvp) exceeds the fixed size (for the
+ * 2D P2 FP64 step with m = 30 that is about 230 000 unknowns).  All calls on
+ * one GPU share its array, which keeps the last call's contents: the step
+ * clears what must start at zero, and calls that overlap on one GPU (other
+ * streams, other host threads, other contexts) race and must be serialised
+ * by the caller.  With info non-NULL the call synchronises as pcexp_step. */
+#define PCEXP_NOALLOC_WS_BYTES (64u << 20)
+pcexp_status pcexp_step_noalloc(pcexp_ctx* ctx, double* u, double dt, double cfl, int32_t m,
+                                int32_t scheme, int32_t prec, int32_t jvp, pcexp_step_info* info,
+                                void* stream);
+
 /* nsteps (>= 1) steps as by pcexp_step, in place, with u kept in the internal
  * basis between them: one change of basis in and one out instead of one pair
  * per step, so the result equals nsteps calls of pcexp_step up to the rounding

@@ -101,6 +101,9 @@ _SIGS = {
     "pcexp_step": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_int32, ctypes.c_int32, _VP, ctypes.c_size_t,
                                   ctypes.POINTER(StepInfo), _VP]),
+    "pcexp_step_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(StepInfo), _VP]),
     "pcexp_advance": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP, ctypes.c_size_t,
                                      ctypes.POINTER(StepInfo), _VP]),
@@ -402,6 +405,17 @@ class PCEXP:
         self._check(self.lib.pcexp_advance(self.ctx, _ptr(u), int(nsteps), float(dt), float(cfl), m, SCHEME[scheme],
                                            PREC[prec], JVP[jvp], _ptr(ws), nbytes,
                                            ctypes.byref(inf) if info else None, self._stream()), "advance")
+        return inf.as_dict() if info else None
+
+    def step_noalloc(self, u, dt=0.0, cfl=0.0, m=30, scheme="pcexp", prec="f64", jvp="tangent", info=False):
+        """pcexp_step with the library's fixed per-GPU workspace (no allocation
+        by the call or by this method)."""
+        if not (u.is_cuda and u.dtype == self.torch.float64 and u.is_contiguous()):
+            raise ValueError("step_noalloc updates u in place: pass a contiguous float64 device tensor")
+        inf = StepInfo()
+        self._check(self.lib.pcexp_step_noalloc(self.ctx, _ptr(u), float(dt), float(cfl), m, SCHEME[scheme],
+                                                PREC[prec], JVP[jvp], ctypes.byref(inf) if info else None,
+                                                self._stream()), "step_noalloc")
         return inf.as_dict() if info else None
 
     def step(self, u, dt=0.0, cfl=0.0, m=30, scheme="pcexp", prec="f64", jvp="tangent", info=False):

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -23,6 +24,33 @@ namespace pcexp {
 thread_local LaunchTiming g_launch_timing;
 }  // namespace pcexp
 
+// Workspace of pcexp_step_noalloc: a fixed array in device memory, one copy
+// per GPU the library runs on, held until the process ends.  Host code never
+// uses this name as an address (on the host it is only a stand-in for the
+// symbol); it takes the device address from hipGetSymbolAddress once per
+// device, at context creation with that device current.
+constexpr size_t kNoallocBytes = (size_t)PCEXP_NOALLOC_WS_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch` on each device
+
+// Device address of this device's copy of `scratch` (looked up once per device).
+hipError_t noalloc_scratch(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+}  // namespace
 
 using namespace pcexp;
 
@@ -79,6 +107,9 @@ struct pcexp_ctx {
   struct Rec { int cls; double bytes; int e0; };
   std::vector<Rec> recs;
   hipStream_t prof_stream = nullptr;
+  // device the context was created on, and that device's no-allocation workspace
+  int device = -1;
+  void* noalloc_ws = nullptr;
 };
 
 namespace {
@@ -521,6 +552,13 @@ pcexp_status report_flags(pcexp_ctx* c, uint32_t* out_flags) {
 }
 
 pcexp_status alloc_common(pcexp_ctx* c, hipStream_t st) {
+  if (hipGetDevice(&c->device) != hipSuccess || c->device < 0 || c->device >= kMaxDevices)
+    return fail(c, PCEXP_E_HIP, "hipGetDevice failed");
+  {
+    const hipError_t e = noalloc_scratch(c->device, &c->noalloc_ws);
+    if (e != hipSuccess)
+      return fail(c, PCEXP_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
   for (int i = 0; i < 5; ++i)
     if (!dalloc(c, &c->io[i], c->Kint)) return fail(c, PCEXP_E_HIP, "hipMalloc failed");
   for (int i = 0; i < 2; ++i)
@@ -1059,6 +1097,26 @@ static pcexp_status advance_impl(pcexp_ctx* c, double* u, int nsteps, double dt,
 pcexp_status pcexp_step(pcexp_ctx* c, double* u, double dt, double cfl, int32_t m, int32_t scheme, int32_t prec,
                         int32_t jvp, void* ws, size_t ws_bytes, pcexp_step_info* info, void* stream) {
   return advance_impl(c, u, 1, dt, cfl, m, scheme, prec, jvp, ws, ws_bytes, info, stream);
+}
+
+pcexp_status pcexp_step_noalloc(pcexp_ctx* c, double* u, double dt, double cfl, int32_t m, int32_t scheme,
+                                int32_t prec, int32_t jvp, pcexp_step_info* info, void* stream) {
+  if (!c) return PCEXP_E_ARG;
+  if (!c->noalloc_ws) return fail(c, PCEXP_E_HIP, "no-allocation workspace was not set up");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(c, PCEXP_E_HIP, "hipGetDevice failed");
+  if (dev != c->device) return fail(c, PCEXP_E_ARG, "the current device is not the context's device");
+  const size_t need = pcexp_workspace_bytes(c, m, 1, prec, jvp);
+  if (need == 0) return fail(c, PCEXP_E_ARG, "bad m, prec or jvp");
+  if (need > kNoallocBytes)
+    return fail(c, PCEXP_E_WORKSPACE,
+                "pcexp_step_noalloc: this mesh and Krylov dimension need " + std::to_string(need) +
+                    " workspace bytes, more than the fixed " + std::to_string(kNoallocBytes) +
+                    " (use pcexp_step with a caller workspace)");
+  // every quantity the step needs at zero is cleared by the step itself
+  // (counters at its start, accumulators by their first write), so the
+  // contents left by an earlier call do not matter
+  return advance_impl(c, u, 1, dt, cfl, m, scheme, prec, jvp, c->noalloc_ws, kNoallocBytes, info, stream);
 }
 
 pcexp_status pcexp_advance(pcexp_ctx* c, double* u, int32_t nsteps, double dt, double cfl, int32_t m,
