@@ -190,8 +190,22 @@ def section_channel(dev, max_iter=12000):
     return out
 
 
+def calibration_copy(dev):
+    """A plain 1 GiB device copy (1 GiB read, 1 GiB written), three times: the
+    reference the HBM counters of a profiled run are scaled by."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"read": src.numel() * 8, "write": dst.numel() * 8, "launches": 3}
+
+
 def bench_channel(args, dev):
     out = section_channel(dev, max_iter=args.channel_iters)
+    if args.calibrate_copy:
+        out["copy_calibration_bytes"] = calibration_copy(dev)
     main = out["runs"].get("mixed", {})
     line = {
         "metric": "PCEXP DOF-updates/s (steady channel to ||R(rho)|| <= 1e-10)",
@@ -584,14 +598,7 @@ def main():
         "gpu_event_seconds": gpu_s,
     }
     if args.calibrate_copy:
-        # plain copy kernel of known size: 1 GiB read + 1 GiB written per launch
-        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8, "launches": 3}
-        del src, dst
+        out["copy_calibration_bytes"] = calibration_copy(dev)
     sections = set(args.sections.split(",")) if args.sections != "all" else {"measurement", "adjoint", "channel",
                                                                              "vortex3d"}
     if "measurement" in sections:
