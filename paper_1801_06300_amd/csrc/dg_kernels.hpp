@@ -413,28 +413,9 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     for (int c = 0; c < NI; ++c) acc[o][c] = T(0);
 
   // ---- volume: pointwise flux contracted with the rows of A^{-1}
-  for (int t = tid; t < NQ * TE; t += NT) {
-    const int q = t / TE, e = t % TE, ge = e0 + e;
-    if (ge >= nE) continue;
-    const T sd = g_det(e);
-    const T rs = T(1) / sd;
-    S U[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      T a = T(0), b = T(0);
-#pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        const T bq = tB[q * NB + i];
-        a += su[(k * NB + i) * TE + e] * bq;
-        if (DUAL) b += sv[(k * NB + i) * TE + e] * bq;
-      }
-      if constexpr (DUAL) {
-        U[k].v = a * rs;
-        U[k].d[0] = b * rs;
-      } else {
-        U[k] = a * rs;
-      }
-    }
+  // (flags in residual mode, then the weighted normal fluxes of point q of
+  // element e into the flux scratch)
+  auto vol_flux = [&](int q, int e, const S* U) {
     if (MODE == MODE_RES && io.flags) {
       T rho = val(U[0]), m2 = T(0);
 #pragma unroll
@@ -445,7 +426,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
       else if (!(rho > T(0)) || !(p > T(0))) fl |= 2u;
       if (fl) atomicOr(io.flags, fl);
     }
-    const T wgt = sd * twq[q];
+    const T wgt = g_det(e) * twq[q];
 #pragma unroll
     for (int r = 0; r < D; ++r) {
       T a[D];
@@ -455,6 +436,109 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
       normal_flux<D>(U, a, gm1, F);
 #pragma unroll
       for (int k = 0; k < NV; ++k) sw[vix(q, k, r, e)] = wgt * Part<S>::get(F[k]);
+    }
+  };
+  if constexpr (Tl::VMFMA) {
+    // U at the quadrature points on the matrix cores: C = B X with rows the
+    // points q < NQ (tiles of 16), the contraction over the basis functions
+    // i < NB in steps of 4, and columns c = (s, k, e): coefficient set s (the
+    // state, and the direction for the tangent), variable k, element e.
+    // The point values go to the flux scratch, then into registers, before
+    // the scratch receives the fluxes.
+    constexpr int NS = DUAL ? 2 : 1;
+    constexpr int NCI = NS * NV * TE, NTI = (NCI + 15) / 16;
+    constexpr int NRT = (NQ + 15) / 16, KB4 = (NB + 3) / 4;
+    constexpr int NW_ = NT / 64, MTI = (NTI + NW_ - 1) / NW_;
+    static_assert(NS * NV * NQ <= Tl::NW, "point values fit the flux scratch");
+    auto uix = [](int s_, int k, int q, int e) { return ((s_ * NV + k) * NQ + q) * TE + e; };
+    const int lane = tid & 63, li = lane & 15, lk = lane >> 4, wid = tid >> 6;
+    T av[NRT][KB4];   // A operands of this lane: B(q = 16 rt + li, i = 4 kb + lk)
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+      for (int kb = 0; kb < KB4; ++kb) {
+        const int q = 16 * rt + li, i = 4 * kb + lk;
+        av[rt][kb] = (q < NQ && i < NB) ? tB[q * NB + i] : T(0);
+      }
+#pragma unroll
+    for (int mt = 0; mt < MTI; ++mt) {
+      const int tn = wid + mt * NW_;
+      if (tn < NTI) {
+        const int c = tn * 16 + li;
+        const bool cv = c < NCI;
+        const int cs_ = cv ? c / (NV * TE) : 0, ck = cv ? (c / TE) % NV : 0, ce = cv ? c % TE : 0;
+        const T* X = (DUAL && cs_ == 1) ? sv : su;
+        T bv[KB4];   // B operands of this lane: X(i = 4 kb + lk, c)
+#pragma unroll
+        for (int kb = 0; kb < KB4; ++kb) {
+          const int i = 4 * kb + lk;
+          bv[kb] = (cv && i < NB) ? X[(ck * NB + i) * TE + ce] : T(0);
+        }
+#pragma unroll
+        for (int rt = 0; rt < NRT; ++rt) {
+          typename Mfma16<T>::v4 cq = typename Mfma16<T>::v4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+          for (int kb = 0; kb < KB4; ++kb) cq = Mfma16<T>::mma(av[rt][kb], bv[kb], cq);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int q = 16 * rt + Mfma16<T>::row(lane, r);
+            if (cv && q < NQ) sw[uix(cs_, ck, q, ce)] = cq[r];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    constexpr int NVI = (NQ * TE + NT - 1) / NT;
+    S Ur[NVI][NV];
+#pragma unroll
+    for (int it = 0; it < NVI; ++it) {
+      const int t = tid + it * NT;
+      if (t < NQ * TE) {
+        const int q = t / TE, e = t % TE;
+        const T rs = s_inv(g_det(e));
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+          if constexpr (DUAL) {
+            Ur[it][k].v = sw[uix(0, k, q, e)] * rs;
+            Ur[it][k].d[0] = sw[uix(1, k, q, e)] * rs;
+          } else {
+            Ur[it][k] = sw[uix(0, k, q, e)] * rs;
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NVI; ++it) {
+      const int t = tid + it * NT;
+      if (t < NQ * TE) {
+        const int q = t / TE, e = t % TE;
+        if (e0 + e < nE) vol_flux(q, e, Ur[it]);
+      }
+    }
+  } else {
+    for (int t = tid; t < NQ * TE; t += NT) {
+      const int q = t / TE, e = t % TE, ge = e0 + e;
+      if (ge >= nE) continue;
+      const T rs = s_inv(g_det(e));
+      S U[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        T a = T(0), b = T(0);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const T bq = tB[q * NB + i];
+          a += su[(k * NB + i) * TE + e] * bq;
+          if (DUAL) b += sv[(k * NB + i) * TE + e] * bq;
+        }
+        if constexpr (DUAL) {
+          U[k].v = a * rs;
+          U[k].d[0] = b * rs;
+        } else {
+          U[k] = a * rs;
+        }
+      }
+      vol_flux(q, e, U);
     }
   }
   __syncthreads();
@@ -539,7 +623,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     if (nb < 0) continue;
     const int info = g_info(e, f);
     const int fN = info & 3, oN = (info >> 2) & 7;
-    const T rsn = T(1) / prm.sdet[nb];
+    const T rsn = s_inv(prm.sdet[nb]);
     T cu[NB], cv[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -574,7 +658,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     const int oE = (info >> 5) & 7;
     if (r == 0) sori[f * TE + e] = (unsigned char)oE;
     const T sd = g_det(e);
-    const T rs = T(1) / sd;
+    const T rs = s_inv(sd);
     const T* bl = tBf + ((f * NORI + oE) * NFQ + r) * NB;
     S UL[NV], UR[NV];
 #pragma unroll
@@ -604,9 +688,10 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
       len2 += nl[c] * nl[c];
     }
     const T len = s_sqrt(len2);
+    const T ilen = s_inv(len);
     T n[D];
 #pragma unroll
-    for (int c = 0; c < D; ++c) n[c] = nl[c] / len;
+    for (int c = 0; c < D; ++c) n[c] = nl[c] * ilen;
     if (nb >= 0) {
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
@@ -900,9 +985,10 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
       len2 += nl[c] * nl[c];
     }
     const T len = s_sqrt(len2);
+    const T ilen = s_inv(len);
     T n[D];
 #pragma unroll
-    for (int c = 0; c < D; ++c) n[c] = nl[c] / len;
+    for (int c = 0; c < D; ++c) n[c] = nl[c] * ilen;
     ST Ub[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) Ub[j] = ST(0);
@@ -937,9 +1023,15 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
         l2N += nN[c] * nN[c];
       }
       const T lenN = s_sqrt(l2N);
-#pragma unroll
-      for (int c = 0; c < D; ++c) nN[c] = nN[c] / lenN;
       const T cn = -prm.wf[r] * lenN * rsN;
+      // The neighbour's term F~(U_N, U_E, n_N) at the same physical point,
+      // with n_N = -n on the shared straight face, equals -F~(U_E, U_N, n)
+      // (both fluxes are antisymmetric), so one flux evaluation seeded on
+      // U_E serves the own term (weight cs wl) and the neighbour's (weight
+      // -cn wn); the face lengths |f| and |f|_N stay each side's own.
+      T wc[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) wc[k] = cs * wl[k] - cn * wn[k];
 #pragma unroll 1
       for (int j0 = 0; j0 < NV; j0 += NC) {
         SD UE[NV], UN[NV], F[NV];
@@ -951,15 +1043,7 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
         for (int c = 0; c < NC; ++c) {
           ST x = ST(0);
 #pragma unroll
-          for (int k = 0; k < NV; ++k) x = x + F[k].d[c] * (cs * wl[k]);
-          add_dir(Ub, j0 + c, x);
-        }
-        num_flux<D, FLUX>(UN, UE, nN, prm.gamma, F);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          ST x = ST(0);
-#pragma unroll
-          for (int k = 0; k < NV; ++k) x = x + F[k].d[c] * (cn * wn[k]);
+          for (int k = 0; k < NV; ++k) x = x + F[k].d[c] * wc[k];
           add_dir(Ub, j0 + c, x);
         }
       }

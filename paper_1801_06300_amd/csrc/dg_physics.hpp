@@ -65,6 +65,25 @@ template <typename T, int N> struct Make<Dual<T, N>> {
 template <typename S> __device__ __forceinline__ S mkzero() { return Make<S>::zero(); }
 template <typename S, typename T> __device__ __forceinline__ S mkconst_s(T x) { return Make<S>::c(x); }
 
+// ---- reciprocal
+// 1/x from the hardware reciprocal estimate refined by Newton steps (two in
+// FP64, one in FP32): within about an ulp of the IEEE quotient for finite,
+// nonzero x of normal range.  Every reciprocal the flux kernels take is of a
+// physical quantity of order one (density, the speed of sound squared, a sum
+// of square roots of densities, sqrt(det A), a face length), so the
+// special-case handling of IEEE division (denormals, overflow, infinities) is
+// not needed; a zero or non-finite operand gives a non-finite result, which
+// the kernels' flags report.
+__device__ __forceinline__ double s_inv(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+}
+__device__ __forceinline__ float s_inv(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(fmaf(-x, r, 1.0f), r, r);
+}
+
 // ---- Dual arithmetic
 #define PCEXP_DUAL_BINOP(OP, VEXPR, DEXPR)                                                      \
   template <typename T, int N>                                                                  \
@@ -82,7 +101,7 @@ PCEXP_DUAL_BINOP(*, a.v * b.v, a.d[i] * b.v + a.v * b.d[i])
 template <typename T, int N>
 __device__ __forceinline__ Dual<T, N> operator/(const Dual<T, N>& a, const Dual<T, N>& b) {
   Dual<T, N> r;
-  T ib = T(1) / b.v;
+  T ib = s_inv(b.v);
   r.v = a.v * ib;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) * ib;
@@ -131,7 +150,7 @@ __device__ __forceinline__ Dual<T, N> operator*(T b, const Dual<T, N>& a) { retu
 template <typename T, int N>
 __device__ __forceinline__ Dual<T, N> operator/(const Dual<T, N>& a, T b) {
   Dual<T, N> r;
-  T ib = T(1) / b;
+  T ib = s_inv(b);
   r.v = a.v * ib;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * ib;
@@ -140,7 +159,7 @@ __device__ __forceinline__ Dual<T, N> operator/(const Dual<T, N>& a, T b) {
 template <typename T, int N>
 __device__ __forceinline__ Dual<T, N> operator/(T a, const Dual<T, N>& b) {
   Dual<T, N> r;
-  T ib = T(1) / b.v;
+  T ib = s_inv(b.v);
   r.v = a * ib;
   T f = -r.v * ib;
 #pragma unroll
@@ -166,7 +185,7 @@ PCEXP_DUAL_PLAIN(-)
 #define PCEXP_DUAL_PLAIN_D(x, b) ((x) * (b))
 PCEXP_DUAL_PLAIN(*)
 #undef PCEXP_DUAL_PLAIN_D
-#define PCEXP_DUAL_PLAIN_D(x, b) ((x) * (1.0 / (b)))
+#define PCEXP_DUAL_PLAIN_D(x, b) ((x) * s_inv((double)(b)))
 PCEXP_DUAL_PLAIN(/)
 #undef PCEXP_DUAL_PLAIN_D
 #undef PCEXP_DUAL_PLAIN
@@ -190,7 +209,7 @@ template <typename T, int N, typename U,
           typename std::enable_if<IsPlain<U>::value && !std::is_same<U, T>::value, int>::type = 0>
 __device__ __forceinline__ Dual<T, N> operator/(U a, const Dual<T, N>& b) {
   Dual<T, N> r;
-  T ib = T(1) / b.v;
+  T ib = s_inv(b.v);
   r.v = a * ib;
   T f = -r.v * ib;
 #pragma unroll
@@ -234,7 +253,16 @@ template <typename T, int N>
 __device__ __forceinline__ Dual<T, N> s_sqrt(const Dual<T, N>& a) {
   Dual<T, N> r;
   r.v = s_sqrt(a.v);
-  T f = T(0.5) / r.v;
+  T f = T(0.5) * s_inv(r.v);
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = f * a.d[i];
+  return r;
+}
+template <typename T, int N>
+__device__ __forceinline__ Dual<T, N> s_inv(const Dual<T, N>& a) {
+  Dual<T, N> r;
+  r.v = s_inv(a.v);
+  T f = -r.v * r.v;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.d[i] = f * a.d[i];
   return r;
@@ -267,7 +295,7 @@ __device__ __forceinline__ Dual<T, N> s_pow(const Dual<T, N>& a, E e) {
 //   F.a = (m.a, m (m.a)/rho + p a, (rho E + p)(m.a)/rho).
 template <int D, typename S, typename T>
 __device__ __forceinline__ void normal_flux(const S* U, const T* a, T gm1, S* F, S* p_out = nullptr) {
-  S rinv = T(1) / U[0];
+  S rinv = s_inv(U[0]);
   S ma = U[1] * a[0];
   S m2 = U[1] * U[1];
 #pragma unroll
@@ -292,9 +320,10 @@ __device__ __forceinline__ void flux_lf(const S* UL, const S* UR, const T* n, T 
   S FL[D + 2], FR[D + 2], pL, pR;
   normal_flux<D>(UL, n, gm1, FL, &pL);
   normal_flux<D>(UR, n, gm1, FR, &pR);
-  S vnL = FL[0] / UL[0], vnR = FR[0] / UR[0];
-  S aL = s_abs(vnL) + s_sqrt(gamma * pL / UL[0]);
-  S aR = s_abs(vnR) + s_sqrt(gamma * pR / UR[0]);
+  const S riL = s_inv(UL[0]), riR = s_inv(UR[0]);
+  S vnL = FL[0] * riL, vnR = FR[0] * riR;
+  S aL = s_abs(vnL) + s_sqrt(gamma * pL * riL);
+  S aR = s_abs(vnR) + s_sqrt(gamma * pR * riR);
   S al = s_max(aL, aR);
 #pragma unroll
   for (int k = 0; k < D + 2; ++k) F[k] = T(0.5) * (FL[k] + FR[k]) - T(0.5) * al * (UR[k] - UL[k]);
@@ -305,12 +334,19 @@ __device__ __forceinline__ void flux_lf(const S* UL, const S* UR, const T* n, T 
 template <int D, typename S, typename T>
 __device__ __forceinline__ void flux_roe(const S* UL, const S* UR, const T* n, T gamma, S* F) {
   const T gm1 = gamma - T(1);
-  S FL[D + 2], FR[D + 2], pL, pR;
-  normal_flux<D>(UL, n, gm1, FL, &pL);
-  normal_flux<D>(UR, n, gm1, FR, &pR);
-  S rLi = T(1) / UL[0], rRi = T(1) / UR[0];
+  S pL, pR;
+  {
+    // the central part 1/2 (F_L + F_R).n first, so that the two physical
+    // fluxes are not held while the dissipation is formed
+    S FR[D + 2];
+    normal_flux<D>(UL, n, gm1, F, &pL);
+    normal_flux<D>(UR, n, gm1, FR, &pR);
+#pragma unroll
+    for (int k = 0; k < D + 2; ++k) F[k] = T(0.5) * (F[k] + FR[k]);
+  }
+  S rLi = s_inv(UL[0]), rRi = s_inv(UR[0]);
   S sL = s_sqrt(UL[0]), sR = s_sqrt(UR[0]);
-  S den = T(1) / (sL + sR);
+  S den = s_inv(sL + sR);
   S HL = (UL[D + 1] + pL) * rLi, HR = (UR[D + 1] + pR) * rRi;
   S ut[D], dv[D];
   S q2 = mkzero<S>(), vn = mkzero<S>(), dvn = mkzero<S>(), udv = mkzero<S>();
@@ -330,21 +366,21 @@ __device__ __forceinline__ void flux_roe(const S* UL, const S* UR, const T* n, T
   S rt = sL * sR;
   S dr = UR[0] - UL[0];
   S dp = pR - pL;
-  S ic2 = T(1) / c2;
+  S ic2 = s_inv(c2);
   S a1 = (dp - rt * ct * dvn) * (T(0.5) * ic2);
   S a3 = (dp + rt * ct * dvn) * (T(0.5) * ic2);
   S a2 = dr - dp * ic2;
   S l1 = s_abs(vn - ct), l2 = s_abs(vn), l3 = s_abs(vn + ct);
   S w1 = l1 * a1, w2 = l2 * a2, w3 = l3 * a3, ws = l2 * rt;
   S Dk = w1 + w2 + w3;
-  F[0] = T(0.5) * (FL[0] + FR[0]) - T(0.5) * Dk;
+  F[0] = F[0] - T(0.5) * Dk;
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     S Dc = w1 * (ut[c] - ct * n[c]) + w2 * ut[c] + ws * (dv[c] - dvn * n[c]) + w3 * (ut[c] + ct * n[c]);
-    F[1 + c] = T(0.5) * (FL[1 + c] + FR[1 + c]) - T(0.5) * Dc;
+    F[1 + c] = F[1 + c] - T(0.5) * Dc;
   }
   S DE = w1 * (Ht - ct * vn) + w2 * (T(0.5) * q2) + ws * (udv - vn * dvn) + w3 * (Ht + ct * vn);
-  F[D + 1] = T(0.5) * (FL[D + 1] + FR[D + 1]) - T(0.5) * DE;
+  F[D + 1] = F[D + 1] - T(0.5) * DE;
 }
 
 // Slip wall: mirror state (rho, m - 2 (m.n) n, rho E).
@@ -367,7 +403,7 @@ __device__ __forceinline__ void ghost_slip(const S* UL, const T* n, S* G) {
 template <int D, typename S, typename T>
 __device__ __forceinline__ void ghost_farfield(const S* UL, const T* n, const T* prim, T gamma, S* G) {
   const T gm1 = gamma - T(1);
-  S rinv = T(1) / UL[0];
+  S rinv = s_inv(UL[0]);
   S vL[D], vnL = mkzero<S>(), q2 = mkzero<S>();
 #pragma unroll
   for (int c = 0; c < D; ++c) {
