@@ -159,9 +159,11 @@ pcexp_status pcexp_evaluate(pcexp_ctx* ctx, const double* u, double* U_qp, void*
 /* R(u) of eq. (euler3) with identity mass and omega = 0 (Sec. 4.2, 4.4). R != u. */
 pcexp_status pcexp_residual(pcexp_ctx* ctx, const double* u, double* R, void* stream);
 
-/* Jv = J(u) v, J = dR/du (Sec. 4.4).  v, Jv FP64 at the boundary; MIXED computes
- * in FP32.  FD is FP64 only.  Jv != v. */
-pcexp_status pcexp_jvp(pcexp_ctx* ctx, const double* u, const double* v, double* Jv,
+/* Jv = J(u) v, J = dR/du (Sec. 4.4).  u is FP64.  PCEXP_PREC_F64: v and Jv are
+ * double*.  PCEXP_PREC_MIXED: v and Jv are float* (FP32 arithmetic and
+ * accumulation inside the JVP, the precision of the Krylov basis in a mixed
+ * step).  FD is FP64 only.  Jv != v.  Uses the context's scratch. */
+pcexp_status pcexp_jvp(pcexp_ctx* ctx, const double* u, const void* v, void* Jv,
                        int32_t jvp, int32_t prec, void* stream);
 
 /* JTw = J(u)^T w, the transpose of the exact Jacobian of Sec. 4.4 (FP64).

@@ -259,9 +259,17 @@ class PCEXP:
         return R
 
     def jvp(self, u, v, kind="tangent", prec="f64", out=None):
+        """J(u) v; v and the result are float64 for prec="f64" and float32 for
+        prec="mixed" (the library's FP32 boundary)."""
         u = self._vec(u, self.shape)
-        v = self._vec(v, self.shape)
-        Jv = self.empty() if out is None else out
+        if prec == "mixed":
+            v = self.torch.as_tensor(v, device=self.device).to(self.torch.float32).contiguous().reshape(self.shape)
+            Jv = self.torch.empty(self.shape, dtype=self.torch.float32, device=self.device) if out is None else out
+            if Jv.dtype != self.torch.float32:
+                raise ValueError("mixed-precision jvp writes a float32 output")
+        else:
+            v = self._vec(v, self.shape)
+            Jv = self.empty() if out is None else out
         self._check(self.lib.pcexp_jvp(self.ctx, _ptr(u), _ptr(v), _ptr(Jv), JVP[kind], PREC[prec],
                                        self._stream()), "jvp")
         return Jv

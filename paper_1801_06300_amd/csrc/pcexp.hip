@@ -740,9 +740,9 @@ pcexp_status pcexp_residual(pcexp_ctx* c, const double* u, double* R, void* stre
   return hip_check(c, "residual");
 }
 
-pcexp_status pcexp_jvp(pcexp_ctx* c, const double* u, const double* v, double* Jv, int32_t jvp, int32_t prec,
+pcexp_status pcexp_jvp(pcexp_ctx* c, const double* u, const void* v_, void* Jv_, int32_t jvp, int32_t prec,
                        void* stream) {
-  if (!c || !u || !v || !Jv || v == Jv) return c ? fail(c, PCEXP_E_ARG, "bad pointers") : PCEXP_E_ARG;
+  if (!c || !u || !v_ || !Jv_ || v_ == Jv_) return c ? fail(c, PCEXP_E_ARG, "bad pointers") : PCEXP_E_ARG;
   if (jvp != PCEXP_JVP_TANGENT && jvp != PCEXP_JVP_FD && jvp != PCEXP_JVP_ZERO)
     return fail(c, PCEXP_E_ARG, "bad jvp kind");
   if (prec != PCEXP_PREC_F64 && prec != PCEXP_PREC_MIXED) return fail(c, PCEXP_E_ARG, "bad precision");
@@ -750,18 +750,25 @@ pcexp_status pcexp_jvp(pcexp_ctx* c, const double* u, const double* v, double* J
   hipStream_t st = (hipStream_t)stream;
   const size_t n = c->Kint;
   to_int(c, u, c->io[0], st);
-  to_int(c, v, c->io[1], st);
   bool ok;
   if (prec == PCEXP_PREC_MIXED) {
+    // FP32 v and Jv at the boundary; the change of basis runs in FP64 on
+    // widened copies (an orthogonal map per element), the JVP in FP32
+    k_cast<float, double>((const float*)v_, c->io[4], c->K, st);
+    to_int(c, c->io[4], c->io[1], st);
     k_cast<double, float>(c->io[0], c->io32[0], n, st);
     k_cast<double, float>(c->io[1], c->io32[1], n, st);
     // the FP32 result is written as float into io[2]'s storage
     ok = jvp_int(c, jvp, prec, nullptr, c->io32[0], c->io32[1], (void*)c->io[2], nullptr, nullptr, nullptr,
                  nullptr, st);
     k_cast<float, double>((const float*)c->io[2], c->io[3], n, st);
-    to_abi(c, c->io[3], Jv, st);
+    to_abi(c, c->io[3], c->io[4], st);
+    k_cast<double, float>(c->io[4], (float*)Jv_, c->K, st);
     return ok ? hip_check(c, "jvp") : fail(c, PCEXP_E_UNSUPPORTED, "no kernel");
   }
+  const double* v = (const double*)v_;
+  double* Jv = (double*)Jv_;
+  to_int(c, v, c->io[1], st);
   const double* Rb = nullptr;
   double* eps = nullptr;
   if (jvp == PCEXP_JVP_FD) {
