@@ -71,16 +71,22 @@ def _n(t):
 
 class _Progress(ExactJacobian):
     """The oracle's exact-Jacobian operator, printing a line every ten JVPs so
-    that the long oracle step shows it is running."""
+    that the long oracle step shows it is running.  With `capsys` the lines
+    bypass pytest's output capture (a long step must not look silent)."""
 
-    def __init__(self, dg):
+    def __init__(self, dg, capsys=None):
         super().__init__(dg)
         self.calls = 0
+        self.capsys = capsys
 
     def jvp(self, u_lin, v, R_lin=None):
         self.calls += 1
         if self.calls % 10 == 0:
-            print(f"[oracle] {self.calls} JVPs", flush=True)
+            if self.capsys is not None:
+                with self.capsys.disabled():
+                    print(f"[oracle] {self.calls} JVPs", flush=True)
+            else:
+                print(f"[oracle] {self.calls} JVPs", flush=True)
             sys.stdout.flush()
         return super().jvp(u_lin, v, R_lin)
 
@@ -321,7 +327,7 @@ def test_3d_16cube_parity():
     from oracle import krylov
     mesh = W.periodic_cube(16, 10.0)
     print(f"\n[case] mesh=cube16 p=2 flux=lf nE={mesh.n_elem}", flush=True)
-    g = DG(mesh, 2, "lf")
+    g = DG(mesh, 2, "lf", cache_limit=1e8)     # tables cached: 3 s per oracle JVP
     ctx = PCEXP(mesh, 2, "lf")
     u = vortex_state(g, mesh, 1e-3)
     ud = _t(u)
@@ -340,3 +346,32 @@ def test_3d_16cube_parity():
     want = krylov.arnoldi_phi(lambda x: jvp_cs(g, u, x.reshape(u.shape)), Ro, dt, 1, 5)
     print(f"[full] cube16 Arnoldi phi_1 (m = 5) {rel(out, want):.2e}", flush=True)
     assert rel(out, want) < 1e-11
+
+
+@pytest.mark.timeout(1200)
+def test_3d_16cube_mixed_pcexp_step(capsys):
+    """One mixed-precision PCEXP step (m = 30, CFL 10) of the 3D vortex column
+    on 16^3 cubes x 6 tetrahedra (24 576, P2 LF, K = 1 228 800) against the
+    FP64 oracle's step (61 complex-step JVPs on the host) over the whole
+    vector: the state at 1e-6 relative and the increment u_{n+1} - u_n at
+    the stated 1e-5 relative."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1801_06300_amd import PCEXP
+    from tests.helpers import vortex_state
+    mesh = W.periodic_cube(16, 10.0)
+    print(f"\n[case] mesh=cube16 p=2 flux=lf nE={mesh.n_elem}: mixed PCEXP step, m=30", flush=True)
+    g = DG(mesh, 2, "lf", cache_limit=1e8)     # tables cached: 3 s per oracle JVP
+    ctx = PCEXP(mesh, 2, "lf")
+    u = vortex_state(g, mesh, 1e-6)
+    dt = stable_dt(g, u, 10.0)
+    ud = _t(u)
+    info = ctx.step(ud, dt=dt, m=30, prec="mixed", info=True)
+    got = _n(ud)
+    want = pcexp_step(_Progress(g, capsys), u, dt, 30)
+    e_state, e_inc = rel(got, want), rel(got - u, want - u)
+    print(f"[full] cube16 mixed PCEXP step: state rel {e_state:.3e} (bar 1e-6), increment rel {e_inc:.3e} "
+          f"(bar 1e-5), m_eff {info['k1']['m_eff']}/{info['k2']['m_eff']}", flush=True)
+    assert info["flags"] == 0
+    assert e_state < 1e-6
+    assert e_inc < 1e-5
