@@ -105,6 +105,13 @@ struct Tile {
   // unchanged, and the 2D P2 kernels (six basis functions pad to 16 rows)
   // lose 4 %, so 2D keeps the VALU contraction.
   static constexpr bool VMFMA = D == 3 && P >= 2 && Sh::NB <= 16;
+  // basis-to-quadrature interpolation U_q = B u on the matrix cores, in the
+  // same element class (3D P2: 27 points x 10 basis functions per (set,
+  // variable, element) column).  Measured: the 3D P2 FP32 tangent JVP
+  // 1.13 -> 1.10 ms, the FP64 residual 1.52 -> 1.43 ms; in 2D P2 (9 points x
+  // 6 basis functions pad to 16 x 8) the JVPs got 1-6 % slower, so 2D keeps
+  // the VALU interpolation.
+  static constexpr bool VMFMA_IN = VMFMA;
   // per element: coefficients (and direction), flux scratch, geometry (det,
   // A^-1, neighbours, face codes) and the face orientation codes
   static constexpr int per_elem = (int)sizeof(T) * (Sh::NVB * (DUAL ? 2 : 1) + NW + 1 + D * D) + 8 * Sh::NF + Sh::NF;
@@ -438,7 +445,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
       for (int k = 0; k < NV; ++k) sw[vix(q, k, r, e)] = wgt * Part<S>::get(F[k]);
     }
   };
-  if constexpr (Tl::VMFMA) {
+  if constexpr (Tl::VMFMA_IN) {
     // U at the quadrature points on the matrix cores: C = B X with rows the
     // points q < NQ (tiles of 16), the contraction over the basis functions
     // i < NB in steps of 4, and columns c = (s, k, e): coefficient set s (the
