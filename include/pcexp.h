@@ -20,7 +20,11 @@
  *    geometry, tables and a fixed scratch area allocated at creation; no
  *    other entry point allocates device memory.  Host descriptor arrays are
  *    copied by pcexp_create and not retained.
- *  * One host thread at a time per context.
+ *  * One host thread and one stream at a time per context: the single-shot
+ *    calls (residual, JVP, VJP, functional, dt, totals, projection) work in
+ *    the context's scratch, so calls on two streams would race on it; use one
+ *    context per stream.  The stepping calls work in the caller's workspace
+ *    and share only the context's flag word.
  *  * Errors: argument/mesh/workspace validation returns before any work is
  *    enqueued; HIP failures return PCEXP_E_HIP.  pcexp_last_error() returns a
  *    message for the last failing call on the context.  Kernels record

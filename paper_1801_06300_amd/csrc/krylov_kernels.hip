@@ -1223,6 +1223,66 @@ void k_rv_combine(const RvComb& a, double* out, size_t n, hipStream_t st) {
   launch(rv_combine_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a, out, n);
 }
 
+// Two combinations of one basis from the same loads:
+//   out1 = ax x + sum_{i < n1} c1_i sigma_i V_i,  out2 = sum_{i < n2} c2_i sigma_i V_i
+// (x may be null; both sums start at V_0).
+__global__ __launch_bounds__(256) void rv_combine2_kernel(const double* x, double ax, const double* V, size_t ld,
+                                                          const double* sigma, const double* c1, int n1,
+                                                          const double* c2, int n2, double* out1, double* out2,
+                                                          size_t n) {
+  __shared__ double f1[KMAX + 2], f2[KMAX + 2];
+  const int nv = n1 > n2 ? n1 : n2;
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    const double s = sigma ? sigma[i] : 1.0;
+    f1[i] = i < n1 ? c1[i] * s : 0.0;
+    f2[i] = i < n2 ? c2[i] * s : 0.0;
+  }
+  __syncthreads();
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
+    double r1 = x ? ax * x[idx] : 0.0, r2 = 0.0;
+    const double* Vp = V + idx;
+    int i = 0;
+    for (; i + 4 <= nv; i += 4) {
+      const double v0 = Vp[(size_t)i * ld], v1 = Vp[(size_t)(i + 1) * ld];
+      const double v2 = Vp[(size_t)(i + 2) * ld], v3 = Vp[(size_t)(i + 3) * ld];
+      r1 += f1[i] * v0 + f1[i + 1] * v1 + f1[i + 2] * v2 + f1[i + 3] * v3;
+      r2 += f2[i] * v0 + f2[i + 1] * v1 + f2[i + 2] * v2 + f2[i + 3] * v3;
+    }
+    for (; i < nv; ++i) {
+      const double v = Vp[(size_t)i * ld];
+      r1 += f1[i] * v;
+      r2 += f2[i] * v;
+    }
+    out1[idx] = r1;
+    out2[idx] = r2;
+  }
+}
+
+void k_rv_combine2(const double* x, double ax, const double* V, size_t ld, const double* sigma, const double* c1,
+                   int n1, const double* c2, int n2, double* out1, double* out2, size_t n, hipStream_t st) {
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  launch(rv_combine2_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, ax, V, ld, sigma, c1, n1, c2, n2, out1,
+         out2, n);
+}
+
+// o1 += y1 and o2 += (*s2) y2 in one pass.
+__global__ __launch_bounds__(256) void rv_acc2_kernel(double* o1, const double* y1, double* o2, const double* y2,
+                                                      const double* s2, size_t n) {
+  const double s = *s2;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
+    o1[idx] = o1[idx] + y1[idx];
+    o2[idx] = o2[idx] + s * y2[idx];
+  }
+}
+
+void k_rv_acc2(double* o1, const double* y1, double* o2, const double* y2, const double* s2, size_t n,
+               hipStream_t st) {
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  launch(rv_acc2_kernel, dim3((unsigned)blocks), dim3(256), 0, st, o1, y1, o2, y2, s2, n);
+}
+
 // Vb_i (=|+=) a[i] r + b[i] w for i < nvec (r or w may be null).
 __global__ __launch_bounds__(256) void rv_rank_kernel(double* Vb, size_t ld, int nvec, const double* r,
                                                       const double* w, const double* ca, const double* cb, int set,

@@ -118,6 +118,12 @@ struct RvComb {
 void k_rv_dots(const double* V, size_t ld, const double* sigma, int i0, int nvec, const double* x, size_t n,
                double* part, double* out, hipStream_t st);
 void k_rv_combine(const RvComb& a, double* out, size_t n, hipStream_t st);
+// out1 = ax x + sum_{i<n1} c1_i sigma_i V_i and out2 = sum_{i<n2} c2_i sigma_i V_i from one read of V
+void k_rv_combine2(const double* x, double ax, const double* V, size_t ld, const double* sigma, const double* c1,
+                   int n1, const double* c2, int n2, double* out1, double* out2, size_t n, hipStream_t st);
+// o1 += y1, o2 += (*s2) y2
+void k_rv_acc2(double* o1, const double* y1, double* o2, const double* y2, const double* s2, size_t n,
+               hipStream_t st);
 void k_rv_rank(double* Vb, size_t ld, int nvec, const double* r, const double* w, const double* a, const double* b,
                bool set, size_t n, hipStream_t st);
 void k_rv_init(const KState* ks, RState* rs, double fac, const double* dtp, hipStream_t st);

@@ -455,32 +455,21 @@ void arnoldi_reverse(pcexp_ctx* c, const double* u_lin, const KState* ks, int M,
     } else {
       k_rv_coef_w(ks, rs, j, nullptr, st);
     }
-    {  // w_bar = r_bar + sum_{i <= j} h_bar_i v_i
+    if (j < M - 1) {
+      // w_bar = r_bar + sum_{i <= j} h_bar_i v_i and J v_j = sum_{i <= j+1} c_i v_i (the Arnoldi
+      // relation) from one read of the basis
+      k_rv_combine2(rptr, 1.0, V, ld, sig, rs->b, j + 1, rs->c, j + 2, B.wb, B.wj, n, st);
+    } else {
       RvComb a{};
       a.x = rptr; a.axc = 1.0; a.V = V; a.ld = ld; a.sigma = sig; a.coef = rs->b; a.i0 = 0; a.nvec = j + 1;
       k_rv_combine(a, B.wb, n, st);
-    }
-    if (j < M - 1) {  // J v_j from the Arnoldi relation
-      RvComb a{};
-      a.V = V; a.ld = ld; a.sigma = sig; a.coef = rs->c; a.i0 = 0; a.nvec = j + 2;
-      k_rv_combine(a, B.wj, n, st);
-    } else {
       jvp_int(c, PCEXP_JVP_TANGENT, PCEXP_PREC_F64, u_lin, nullptr, V + (size_t)j * ld, B.wj, &sig[j], nullptr,
               nullptr, nullptr, st);
     }
     k_rv_rank(B.Vb, ld, j + 1, rptr, B.wj, rs->a, rs->b, false, n, st);
     vjp_int(c, u_lin, V + (size_t)j * ld, B.wb, B.t1, B.t2, false, st);
-    double* vbj = B.Vb + (size_t)j * ld;
-    {
-      RvComb a{};
-      a.x = vbj; a.axc = 1.0; a.y = B.t1; a.ayc = 1.0;
-      k_rv_combine(a, vbj, n, st);
-    }
-    {
-      RvComb a{};
-      a.x = ubar; a.axc = 1.0; a.y = B.t2; a.ayp = &sig[j];
-      k_rv_combine(a, ubar, n, st);
-    }
+    // v_j_bar += J^T w_bar, u_bar += sigma_j (d_u[J v_j])^T w_bar
+    k_rv_acc2(B.Vb + (size_t)j * ld, B.t1, ubar, B.t2, &sig[j], n, st);
   }
   k_rv_dots(V, ld, sig, 0, 1, B.Vb, n, B.part, &rs->t[0], st);
   k_rv_coef_b(ks, rs, &rs->t[0], st);
