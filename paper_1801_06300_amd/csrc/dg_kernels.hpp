@@ -268,16 +268,34 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   __shared__ __attribute__((aligned(16))) T sw[Tl::NW * TE];
   __shared__ unsigned char sori[NF * TE];
   __shared__ T stab[Tl::STAGE_TAB ? Tl::NTAB : 1];
-  // Per-element geometry.  Neighbours and face codes are staged in LDS.
-  // When the volume and face phases are single rounds, thread tid works on
-  // element e0 + tid % TE in both and keeps its det and A^-1 in registers;
-  // otherwise they are staged in LDS too.
-  constexpr bool PF = NQ * TE <= NT && NF * NFQ * TE <= NT;
-  constexpr int GTE = PF ? 1 : TE;
+  // Faces whose two elements both lie in the tile are evaluated once, by
+  // the side of smaller index (see the face phase), in the FP32 kernels.
+  // Measured: the mixed-precision JVP gains 9 % on the 3D P2 vortex and 2 %
+  // on the 2D one; the FP64 kernels, with fewer resident waves and bound by
+  // latency, lose 2-10 % to the indirection through the face list, so they
+  // keep one item per face point of every element.
+  constexpr bool DEDUP = sizeof(T) == 4;
+  // Per-element geometry, neighbours and face codes, staged in LDS.  When
+  // the pointwise phases that use the geometry are single rounds, thread tid
+  // works on element e0 + tid % TE in them and keeps its det and A^-1 in
+  // registers (with DEDUP the face phase reads them from LDS).
+  constexpr bool PF = NQ * TE <= NT && (DEDUP || NF * NFQ * TE <= NT);
+  constexpr int GTE = (PF && !DEDUP) ? 1 : TE;
   __shared__ T sg_det[GTE];
   __shared__ T sg_ainv[D * D * GTE];
   __shared__ int sg_nbr[NF * TE];
   __shared__ int sg_info[NF * TE];
+  // With DEDUP, the face incidences (e, f) of the tile, entry f * TE + e, in
+  // three classes: 0, the neighbour lies in the tile and has the larger
+  // index (this side evaluates the flux for both); 1, the neighbour lies in
+  // another tile; 2, a boundary face; 3, none (the neighbour in the tile
+  // evaluates it, or a padding element).  flist holds classes 0, 1, 2 in
+  // that order, each in entry order; fcnt the per-wave class counts.
+  static_assert(!DEDUP || NF * TE <= NT, "one face incidence per thread");
+  constexpr int NFL_ = DEDUP ? NF * TE : 1;
+  __shared__ unsigned short flist[NFL_];
+  __shared__ unsigned char fcls[NFL_];
+  __shared__ int fcnt[NT / 64][3];
   // sw holds, in turn, the weighted volume fluxes (k, r, q, e) and the face
   // values (c, f, r, e), with the pointwise index (q or face point) next to
   // e: the threads of a pointwise phase, t = q * TE + e, then touch
@@ -333,6 +351,7 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     else rv[s] = T(0);
   }
   constexpr int NGT = PF ? 0 : (1 + D * D) * TE, NGI = 2 * NF * TE;
+  static_assert(!PF || TE <= NT, "the register copy of the geometry covers the tile");
   constexpr int NGTL = (NGT + NT - 1) / NT, NGIL = (NGI + NT - 1) / NT;
   T gt[NGTL > 0 ? NGTL : 1];
   int gi[NGIL > 0 ? NGIL : 1];
@@ -368,6 +387,8 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     if constexpr (PF) return pg_ainv[c];
     else return sg_ainv[c * TE + e];
   };
+  auto l_det = [&](int e) -> T { return sg_det[e]; };
+  auto l_ainv = [&](int e, int c) -> T { return sg_ainv[c * TE + e]; };
   auto g_nbr = [&](int e, int f) -> int { return sg_nbr[f * TE + e]; };
   auto g_info = [&](int e, int f) -> int { return sg_info[f * TE + e]; };
 
@@ -387,6 +408,13 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
       const int c = t / TE, e = t % TE;
       if (c == 0) sg_det[e] = gt[s];
       else sg_ainv[(c - 1) * TE + e] = gt[s];
+    }
+  }
+  if constexpr (PF && DEDUP) {
+    if (tid < TE) {
+      sg_det[tid] = pg_det;
+#pragma unroll
+      for (int c = 0; c < D * D; ++c) sg_ainv[c * TE + tid] = pg_ainv[c];
     }
   }
 #pragma unroll
@@ -412,6 +440,31 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     }
   }
   __syncthreads();
+
+  // ---- face incidences: class of thread tid's incidence, per-wave counts
+  if constexpr (DEDUP) {
+    const int f = tid / TE, e = tid % TE, ge = e0 + e;
+    int cls = 3;
+    if (tid < NF * TE && ge < nE) {
+      const int nb = g_nbr(e, f);
+      if (nb < 0) cls = 2;
+      else if (nb >= e0 && nb < e0 + TE && nb != ge) cls = ge < nb ? 0 : 3;
+      else cls = 1;
+    }
+    if (tid < NF * TE) fcls[tid] = (unsigned char)cls;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const unsigned long long m = __ballot(cls == c);
+      if ((tid & 63) == 0) fcnt[tid >> 6][c] = __popcll(m);
+    }
+  }
+  // class totals (after the barrier that follows the counts)
+  auto ftot = [&](int c) -> int {
+    int n = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) n += fcnt[w][c];
+    return n;
+  };
 
   T acc[NOUT][NI];
 #pragma unroll
@@ -549,6 +602,22 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
     }
   }
   __syncthreads();
+  // ---- compact list of the face incidences (see flist)
+  if constexpr (DEDUP) {
+    const int lane = tid & 63, w = tid >> 6;
+    const int cls = tid < NF * TE ? fcls[tid] : 3;
+    int pos = 0, base = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      int before = 0;
+#pragma unroll
+      for (int q = 0; q < NT / 64; ++q) before += q < w ? fcnt[q][c] : 0;
+      const unsigned long long m = __ballot(cls == c);
+      if (cls == c) pos = base + before + __popcll(m & ((1ull << lane) - 1ull));
+      base += ftot(c);
+    }
+    if (cls < 3) flist[pos] = (unsigned short)tid;
+  }
   if constexpr (Tl::VMFMA) {
     // R_k = Dg^T F_k for every variable k: rows i < NB, columns c = k TE + e,
     // contraction over kappa = r NQ + q (F_k(kappa, e) = sw[vix(q, k, r, e)]),
@@ -620,105 +689,179 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   }
   __syncthreads();
 
-  // ---- neighbour traces: item (k, f, e) gathers the neighbour's
-  // coefficients of variable k across face f once and evaluates them at the
-  // face points (the face threads below then read them from LDS)
-  for (int t = tid; t < NV * NF * TE; t += NT) {
-    const int kf = t / TE, e = t % TE, k = kf / NF, f = kf % NF, ge = e0 + e;
-    if (ge >= nE) continue;
-    const int nb = g_nbr(e, f);
-    if (nb < 0) continue;
-    const int info = g_info(e, f);
-    const int fN = info & 3, oN = (info >> 2) & 7;
-    const T rsn = s_inv(prm.sdet[nb]);
-    T cu[NB], cv[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      T uu = io.u[(size_t)(k * NB + i) * Epad + nb];
-      T vv = T(0);
-      if constexpr (MODE != MODE_RES) vv = io.v[(size_t)(k * NB + i) * Epad + nb] * scale;
-      if (MODE == MODE_FD) uu = uu + eps * vv;
-      cu[i] = uu;
-      cv[i] = vv;
-    }
-#pragma unroll
-    for (int r = 0; r < NFQ; ++r) {
-      const T* br = tBf + ((fN * NORI + oN) * NFQ + r) * NB;
-      T a = T(0), b = T(0);
-#pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        a += cu[i] * br[i];
-        if (DUAL) b += cv[i] * br[i];
+  // ---- neighbour traces: item (k, f, e) takes the coefficients of variable
+  // k of the neighbour across face f of element e -- from LDS when it lies
+  // in the tile, else from global memory -- and evaluates them at the face
+  // points (the face items below read them from LDS).  With DEDUP the items
+  // are (k, j) for the list entries j < nA + nB (classes 0 and 1).
+  {
+    const int nA = DEDUP ? ftot(0) : 0, nAB = DEDUP ? nA + ftot(1) : NF * TE;
+    // rounds bounded at compile time (a loop with a run-time bound costs the
+    // face phase below 30-60 registers)
+    constexpr int NIT = (NV * NF * TE + NT - 1) / NT;
+#pragma unroll 1
+    for (int it = 0; it < NIT; ++it) {
+      const int t = tid + it * NT;
+      if (t >= NV * nAB) break;
+      int k = 0, j = t, f, e;
+      if constexpr (DEDUP) {
+        while (j >= nAB) {
+          j -= nAB;
+          ++k;
+        }
+        const int ent = flist[j];
+        f = ent / TE;
+        e = ent % TE;
+      } else {
+        const int kf = t / TE;
+        e = t % TE;
+        k = kf / NF;
+        f = kf % NF;
+        if (e0 + e >= nE) continue;
       }
-      sw[fix(k, f * NFQ + r, e)] = a * rsn;
-      if (DUAL) sw[fix(NV + k, f * NFQ + r, e)] = b * rsn;
+      const int nb = g_nbr(e, f);
+      if (!DEDUP && nb < 0) continue;
+      const int info = g_info(e, f);
+      const int fN = info & 3, oN = (info >> 2) & 7;
+      T cu[NB], cv[NB], rsn;
+      if (DEDUP && j < nA) {
+        const int en = nb - e0;
+        rsn = s_inv(l_det(en));
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          cu[i] = su[(k * NB + i) * TE + en];
+          cv[i] = DUAL ? sv[(k * NB + i) * TE + en] : T(0);
+        }
+      } else {
+        rsn = s_inv(prm.sdet[nb]);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          T uu = io.u[(size_t)(k * NB + i) * Epad + nb];
+          T vv = T(0);
+          if constexpr (MODE != MODE_RES) vv = io.v[(size_t)(k * NB + i) * Epad + nb] * scale;
+          if (MODE == MODE_FD) uu = uu + eps * vv;
+          cu[i] = uu;
+          cv[i] = vv;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < NFQ; ++r) {
+        const T* br = tBf + ((fN * NORI + oN) * NFQ + r) * NB;
+        T a = T(0), b = T(0);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          a += cu[i] * br[i];
+          if (DUAL) b += cv[i] * br[i];
+        }
+        sw[fix(k, f * NFQ + r, e)] = a * rsn;
+        if (DUAL) sw[fix(NV + k, f * NFQ + r, e)] = b * rsn;
+      }
     }
   }
   __syncthreads();
 
-  // ---- faces: traces, numerical flux (each face computed by both sides)
-  for (int t = tid; t < NF * NFQ * TE; t += NT) {
-    const int fr = t / TE, e = t % TE, f = fr / NFQ, r = fr % NFQ, ge = e0 + e;
-    if (ge >= nE) continue;
-    const int info = g_info(e, f);
-    const int nb = g_nbr(e, f);
-    const int oE = (info >> 5) & 7;
-    if (r == 0) sori[f * TE + e] = (unsigned char)oE;
-    const T sd = g_det(e);
-    const T rs = s_inv(sd);
-    const T* bl = tBf + ((f * NORI + oE) * NFQ + r) * NB;
-    S UL[NV], UR[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      T a = T(0), b = T(0);
-#pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        a += su[(k * NB + i) * TE + e] * bl[i];
-        if (DUAL) b += sv[(k * NB + i) * TE + e] * bl[i];
-      }
-      if constexpr (DUAL) {
-        UL[k].v = a * rs;
-        UL[k].d[0] = b * rs;
+  // ---- faces: traces and the numerical flux, item (r, j) for point r of
+  // list entry j.  A face whose two elements lie in the tile is evaluated
+  // once, by the side of smaller index, which also writes the neighbour's
+  // term: both sides parametrise the face by the same points, the normals
+  // are opposite, and the Roe and Lax-Friedrichs fluxes are antisymmetric,
+  // F(U_N, U_E, -n) = -F(U_E, U_N, n), so the neighbour's value at point r
+  // is -F weighted by its own face weight.
+  {
+    const int nA = DEDUP ? ftot(0) : 0, nT = DEDUP ? nA + ftot(1) + ftot(2) : NF * TE;
+    constexpr int NIT = (NF * NFQ * TE + NT - 1) / NT;
+#pragma unroll 1
+    for (int it = 0; it < NIT; ++it) {
+      const int t = tid + it * NT;
+      if (t >= NFQ * nT) break;
+      int r = 0, j = t, f, e;
+      if constexpr (DEDUP) {
+        while (j >= nT) {
+          j -= nT;
+          ++r;
+        }
+        const int ent = flist[j];
+        f = ent / TE;
+        e = ent % TE;
       } else {
-        UL[k] = a * rs;
+        const int fr_ = t / TE;
+        e = t % TE;
+        f = fr_ / NFQ;
+        r = fr_ % NFQ;
+        if (e0 + e >= nE) continue;
       }
-    }
-    // |f| n = det(A) A^{-T} nref_f
-    T nl[D];
-    T len2 = T(0);
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-      T s = T(0);
-#pragma unroll
-      for (int rr = 0; rr < D; ++rr) s += g_ainv(e, rr * D + c) * tnref[f * D + rr];
-      nl[c] = s * sd * sd;
-      len2 += nl[c] * nl[c];
-    }
-    const T len = s_sqrt(len2);
-    const T ilen = s_inv(len);
-    T n[D];
-#pragma unroll
-    for (int c = 0; c < D; ++c) n[c] = nl[c] * ilen;
-    if (nb >= 0) {
+      const int fr = f * NFQ + r;
+      const int info = g_info(e, f);
+      const int nb = g_nbr(e, f);
+      const int oE = (info >> 5) & 7;
+      const bool pair = DEDUP && j < nA;   // class 0: the neighbour's term too
+      const int en = pair ? nb - e0 : 0, fN = info & 3, oN = (info >> 2) & 7;
+      if (r == 0) {
+        sori[f * TE + e] = (unsigned char)oE;
+        if (pair) sori[fN * TE + en] = (unsigned char)oN;
+      }
+      const T sd = DEDUP ? l_det(e) : g_det(e);
+      const T rs = s_inv(sd);
+      const T* bl = tBf + ((f * NORI + oE) * NFQ + r) * NB;
+      S UL[NV], UR[NV];
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
+        T a = T(0), b = T(0);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          a += su[(k * NB + i) * TE + e] * bl[i];
+          if (DUAL) b += sv[(k * NB + i) * TE + e] * bl[i];
+        }
         if constexpr (DUAL) {
-          UR[k].v = sw[fix(k, fr, e)];
-          UR[k].d[0] = sw[fix(NV + k, fr, e)];
+          UL[k].v = a * rs;
+          UL[k].d[0] = b * rs;
         } else {
-          UR[k] = sw[fix(k, fr, e)];
+          UL[k] = a * rs;
         }
       }
-    } else if (((info >> 8) & 3) == 1) {
-      ghost_slip<D>(UL, n, UR);
-    } else {
-      ghost_farfield<D>(UL, n, prm.ff, prm.gamma, UR);
-    }
-    S F[NV];
-    num_flux<D, FLUX>(UL, UR, n, prm.gamma, F);
-    const T wgt = twf[r] * len * rs;
+      // |f| n = det(A) A^{-T} nref_f
+      T nl[D];
+      T len2 = T(0);
 #pragma unroll
-    for (int k = 0; k < NV; ++k) sw[fix(k, fr, e)] = wgt * Part<S>::get(F[k]);
+      for (int c = 0; c < D; ++c) {
+        T s_ = T(0);
+#pragma unroll
+        for (int rr = 0; rr < D; ++rr) s_ += (DEDUP ? l_ainv(e, rr * D + c) : g_ainv(e, rr * D + c)) * tnref[f * D + rr];
+        nl[c] = s_ * sd * sd;
+        len2 += nl[c] * nl[c];
+      }
+      const T len = s_sqrt(len2);
+      const T ilen = s_inv(len);
+      T n[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) n[c] = nl[c] * ilen;
+      if (nb >= 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+          if constexpr (DUAL) {
+            UR[k].v = sw[fix(k, fr, e)];
+            UR[k].d[0] = sw[fix(NV + k, fr, e)];
+          } else {
+            UR[k] = sw[fix(k, fr, e)];
+          }
+        }
+      } else if (((info >> 8) & 3) == 1) {
+        ghost_slip<D>(UL, n, UR);
+      } else {
+        ghost_farfield<D>(UL, n, prm.ff, prm.gamma, UR);
+      }
+      S F[NV];
+      num_flux<D, FLUX>(UL, UR, n, prm.gamma, F);
+      const T wl = twf[r] * len;
+      const T wgt = wl * rs;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) sw[fix(k, fr, e)] = wgt * Part<S>::get(F[k]);
+      if (pair) {
+        const T wgn = -(wl * s_inv(l_det(en)));
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sw[fix(k, fN * NFQ + r, en)] = wgn * Part<S>::get(F[k]);
+      }
+    }
   }
   __syncthreads();
 #pragma unroll
