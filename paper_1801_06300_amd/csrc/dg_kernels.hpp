@@ -978,10 +978,22 @@ struct VjpTile {
   // for first order; one column at a time for the nested second-order
   // scalars, whose NV-direction form does not fit the register file
   static constexpr int NC = std::is_same<ST, double>::value ? Sh::NV : 1;
-  static constexpr int TE = (64 * per_elem <= kLdsBudget) ? 64
-                            : (32 * per_elem <= kLdsBudget) ? 32
-                            : (16 * per_elem <= kLdsBudget) ? 16
-                            : (8 * per_elem <= kLdsBudget) ? 8 : 4;
+  // As for the forward tiles: the fewest rounds of the two pointwise phases
+  // (NQ TE and NF NFQ TE items over 256 threads) per element under the LDS
+  // budget, the smallest tile among equals (2D P2: 28 elements, one round
+  // each, instead of 32 with a second round of 32 items).
+  static constexpr int rounds(int te) {
+    return (Sh::NQ * te + 255) / 256 + (Sh::NF * Sh::NFQ * te + 255) / 256;
+  }
+  static constexpr int pick() {
+    int best = 1;
+    for (int te = 2; te <= 64; ++te) {
+      if (te * per_elem > kLdsBudget) break;
+      if (rounds(te) * best < rounds(best) * te) best = te;
+    }
+    return best;
+  }
+  static constexpr int TE = pick();
 };
 
 template <int D, int P, int FLUX, typename ST>

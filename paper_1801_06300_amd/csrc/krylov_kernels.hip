@@ -1223,47 +1223,57 @@ void k_rv_combine(const RvComb& a, double* out, size_t n, hipStream_t st) {
   launch(rv_combine_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a, out, n);
 }
 
-// Two combinations of one basis from the same loads:
-//   out1 = ax x + sum_{i < n1} c1_i sigma_i V_i,  out2 = sum_{i < n2} c2_i sigma_i V_i
-// (x may be null; both sums start at V_0).
-__global__ __launch_bounds__(256) void rv_combine2_kernel(const double* x, double ax, const double* V, size_t ld,
-                                                          const double* sigma, const double* c1, int n1,
-                                                          const double* c2, int n2, double* out1, double* out2,
-                                                          size_t n) {
+// Iteration j < M - 1: r, w_bar and J v_j (Arnoldi relation) from one read
+// of V_0 .. V_{j+1} (see krylov_kernels.hpp).
+__global__ __launch_bounds__(256) void rv_combine3_kernel(const double* __restrict__ vb1, const RState* rs,
+                                                          const double* __restrict__ V, size_t ld,
+                                                          const double* sigma, int j, double* r_out, double* wb_out,
+                                                          double* wj_out, size_t n) {
   __shared__ double f1[KMAX + 2], f2[KMAX + 2];
-  const int nv = n1 > n2 ? n1 : n2;
+  __shared__ double sa, sg, sc;
+  const int nv = j + 1;
   for (int i = threadIdx.x; i < nv; i += blockDim.x) {
     const double s = sigma ? sigma[i] : 1.0;
-    f1[i] = i < n1 ? c1[i] * s : 0.0;
-    f2[i] = i < n2 ? c2[i] * s : 0.0;
+    f1[i] = rs->b[i] * s;
+    f2[i] = rs->c[i] * s;
+  }
+  if (threadIdx.x == 0) {
+    const double s = sigma ? sigma[j + 1] : 1.0;
+    sa = rs->alpha;
+    sg = rs->gamma * s;
+    sc = rs->c[j + 1] * s;
   }
   __syncthreads();
+  const double al = sa, ga = sg, cj = sc;
+  const double* Vj1 = V + (size_t)(j + 1) * ld;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
-    double r1 = x ? ax * x[idx] : 0.0, r2 = 0.0;
+    const double v1 = Vj1[idx];
+    const double r = al * vb1[idx] + ga * v1;
+    double r1 = r, r2 = cj * v1;
     const double* Vp = V + idx;
     int i = 0;
     for (; i + 4 <= nv; i += 4) {
-      const double v0 = Vp[(size_t)i * ld], v1 = Vp[(size_t)(i + 1) * ld];
-      const double v2 = Vp[(size_t)(i + 2) * ld], v3 = Vp[(size_t)(i + 3) * ld];
-      r1 += f1[i] * v0 + f1[i + 1] * v1 + f1[i + 2] * v2 + f1[i + 3] * v3;
-      r2 += f2[i] * v0 + f2[i + 1] * v1 + f2[i + 2] * v2 + f2[i + 3] * v3;
+      const double v0 = Vp[(size_t)i * ld], va = Vp[(size_t)(i + 1) * ld];
+      const double vb = Vp[(size_t)(i + 2) * ld], vc = Vp[(size_t)(i + 3) * ld];
+      r1 += f1[i] * v0 + f1[i + 1] * va + f1[i + 2] * vb + f1[i + 3] * vc;
+      r2 += f2[i] * v0 + f2[i + 1] * va + f2[i + 2] * vb + f2[i + 3] * vc;
     }
     for (; i < nv; ++i) {
       const double v = Vp[(size_t)i * ld];
       r1 += f1[i] * v;
       r2 += f2[i] * v;
     }
-    out1[idx] = r1;
-    out2[idx] = r2;
+    r_out[idx] = r;
+    wb_out[idx] = r1;
+    wj_out[idx] = r2;
   }
 }
 
-void k_rv_combine2(const double* x, double ax, const double* V, size_t ld, const double* sigma, const double* c1,
-                   int n1, const double* c2, int n2, double* out1, double* out2, size_t n, hipStream_t st) {
+void k_rv_combine3(const double* vb1, const RState* rs, const double* V, size_t ld, const double* sigma, int j,
+                   double* r, double* wb, double* wj, size_t n, hipStream_t st) {
   size_t blocks = (n + 255) / 256;
   if (blocks > 2048) blocks = 2048;
-  launch(rv_combine2_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, ax, V, ld, sigma, c1, n1, c2, n2, out1,
-         out2, n);
+  launch(rv_combine3_kernel, dim3((unsigned)blocks), dim3(256), 0, st, vb1, rs, V, ld, sigma, j, r, wb, wj, n);
 }
 
 // o1 += y1 and o2 += (*s2) y2 in one pass.
@@ -1370,14 +1380,6 @@ __global__ __launch_bounds__(PHI_T) void rv_phi_adjoint_kernel(const KState* ks,
   }
 }
 
-// r_bar coefficients for iteration j < M - 1 from t = v_{j+1}_bar . v_{j+1}:
-//   r_bar = v_{j+1}_bar / h + (H_bar_{j+1,j} - t / h) v_{j+1},  h = h_{j+1,j}.
-__global__ void rv_coef_r_kernel(const KState* ks, RState* rs, int j, const double* tdot) {
-  const double h = ks->H[(size_t)j * KLD + j + 1];
-  rs->alpha = 1.0 / h;
-  rs->gamma = rs->Hbar[(size_t)j * KLD + j + 1] - *tdot / h;
-}
-
 // Iteration j: with c_i = v_i . r_bar (or 0), h_bar_i = H_bar_{i,j} - c_i;
 //   b[i] = h_bar_i, a[i] = -h_{i,j} (i <= j); c[i] = h_{i,j} (i <= j + 1).
 __global__ void rv_coef_w_kernel(const KState* ks, RState* rs, int j, const double* cdots) {
@@ -1385,6 +1387,28 @@ __global__ void rv_coef_w_kernel(const KState* ks, RState* rs, int j, const doub
     const bool in = i <= j;
     const double hij = (i <= j + 1 && i < KLD) ? ks->H[(size_t)j * KLD + i] : 0.0;
     rs->b[i] = in ? rs->Hbar[(size_t)j * KLD + i] - (cdots ? cdots[i] : 0.0) : 0.0;
+    rs->a[i] = in ? -hij : 0.0;
+    rs->c[i] = (i <= j + 1) ? hij : 0.0;
+  }
+}
+
+// Iteration j < M - 1 from d_i = v_i . v_{j+1}_bar (i <= j + 1):
+//   r_bar = alpha v_{j+1}_bar + gamma v_{j+1},  alpha = 1 / h,
+//   gamma = H_bar_{j+1,j} - d_{j+1} / h,  h = h_{j+1,j};
+//   c_i = v_i . r_bar = alpha d_i (i <= j: the basis is orthonormal, the
+//   reading under which the sweep differentiates the Arnoldi relations);
+//   b[i] = H_bar_{i,j} - c_i, a[i] = -h_{i,j} (i <= j); c[i] = h_{i,j} (i <= j + 1).
+__global__ void rv_coef_rw_kernel(const KState* ks, RState* rs, int j, const double* d) {
+  const double h = ks->H[(size_t)j * KLD + j + 1];
+  const double al = 1.0 / h;
+  if (threadIdx.x == 0) {
+    rs->alpha = al;
+    rs->gamma = rs->Hbar[(size_t)j * KLD + j + 1] - d[j + 1] / h;
+  }
+  for (int i = threadIdx.x; i < KMAX + 2; i += blockDim.x) {
+    const bool in = i <= j;
+    const double hij = (i <= j + 1 && i < KLD) ? ks->H[(size_t)j * KLD + i] : 0.0;
+    rs->b[i] = in ? rs->Hbar[(size_t)j * KLD + i] - al * d[i] : 0.0;
     rs->a[i] = in ? -hij : 0.0;
     rs->c[i] = (i <= j + 1) ? hij : 0.0;
   }
@@ -1404,11 +1428,11 @@ void k_rv_phi_adjoint(const KState* ks, RState* rs, const double* dots, double f
                       hipStream_t st) {
   launch(rv_phi_adjoint_kernel, dim3(1), dim3(PHI_T), 0, st, ks, rs, dots, fac, dtp, mem);
 }
-void k_rv_coef_r(const KState* ks, RState* rs, int j, const double* tdot, hipStream_t st) {
-  launch(rv_coef_r_kernel, dim3(1), dim3(1), 0, st, ks, rs, j, tdot);
-}
 void k_rv_coef_w(const KState* ks, RState* rs, int j, const double* cdots, hipStream_t st) {
   launch(rv_coef_w_kernel, dim3(1), dim3(64), 0, st, ks, rs, j, cdots);
+}
+void k_rv_coef_rw(const KState* ks, RState* rs, int j, const double* d, hipStream_t st) {
+  launch(rv_coef_rw_kernel, dim3(1), dim3(64), 0, st, ks, rs, j, d);
 }
 void k_rv_coef_b(const KState* ks, RState* rs, const double* tdot, hipStream_t st) {
   launch(rv_coef_b_kernel, dim3(1), dim3(1), 0, st, ks, rs, tdot);

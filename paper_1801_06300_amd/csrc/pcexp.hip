@@ -443,23 +443,16 @@ void arnoldi_reverse(pcexp_ctx* c, const double* u_lin, const KState* ks, int M,
   for (int j = M - 1; j >= 0; --j) {
     const double* rptr = nullptr;
     if (j < M - 1) {
+      // d_i = v_i . v_{j+1}_bar (i <= j + 1) in one pass, then r_bar, w_bar = r_bar + sum_{i <= j}
+      // h_bar_i v_i and J v_j = sum_{i <= j+1} c_i v_i (the Arnoldi relation) from one read of
+      // the basis
       double* vb1 = B.Vb + (size_t)(j + 1) * ld;
-      k_rv_dots(V, ld, sig, j + 1, 1, vb1, n, B.part, &rs->t[0], st);
-      k_rv_coef_r(ks, rs, j, &rs->t[0], st);
-      RvComb a{};
-      a.x = vb1; a.axp = &rs->alpha; a.V = V; a.ld = ld; a.sigma = sig; a.coef = &rs->gamma; a.i0 = j + 1; a.nvec = 1;
-      k_rv_combine(a, B.r, n, st);
-      k_rv_dots(V, ld, sig, 0, j + 1, B.r, n, B.part, rs->dots, st);
-      k_rv_coef_w(ks, rs, j, rs->dots, st);
+      k_rv_dots(V, ld, sig, 0, j + 2, vb1, n, B.part, rs->dots, st);
+      k_rv_coef_rw(ks, rs, j, rs->dots, st);
+      k_rv_combine3(vb1, rs, V, ld, sig, j, B.r, B.wb, B.wj, n, st);
       rptr = B.r;
     } else {
       k_rv_coef_w(ks, rs, j, nullptr, st);
-    }
-    if (j < M - 1) {
-      // w_bar = r_bar + sum_{i <= j} h_bar_i v_i and J v_j = sum_{i <= j+1} c_i v_i (the Arnoldi
-      // relation) from one read of the basis
-      k_rv_combine2(rptr, 1.0, V, ld, sig, rs->b, j + 1, rs->c, j + 2, B.wb, B.wj, n, st);
-    } else {
       RvComb a{};
       a.x = rptr; a.axc = 1.0; a.V = V; a.ld = ld; a.sigma = sig; a.coef = rs->b; a.i0 = 0; a.nvec = j + 1;
       k_rv_combine(a, B.wb, n, st);
