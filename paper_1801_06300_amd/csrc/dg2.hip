@@ -41,10 +41,10 @@ bool dg_run2_f(int p, int flux, int mode, const DGParams<float>& prm, const DGIO
 
 template <int P>
 static bool vjp_p(int flux, const DGParams<double>& prm, const double* u, const double* v, const double* w,
-                  double* out, double* out_d, hipStream_t st) {
+                  double* out, double* out_d, hipStream_t st, const double* acc_scale) {
   if (out_d) {
-    if (flux == FLUX_LF) launch_vjp2<2, P, FLUX_LF>(prm, u, v, w, out, out_d, st);
-    else launch_vjp2<2, P, FLUX_ROE>(prm, u, v, w, out, out_d, st);
+    if (flux == FLUX_LF) launch_vjp2<2, P, FLUX_LF>(prm, u, v, w, out, out_d, acc_scale, st);
+    else launch_vjp2<2, P, FLUX_ROE>(prm, u, v, w, out, out_d, acc_scale, st);
   } else {
     if (flux == FLUX_LF) launch_vjp<2, P, FLUX_LF>(prm, u, w, out, st);
     else launch_vjp<2, P, FLUX_ROE>(prm, u, w, out, st);
@@ -53,12 +53,12 @@ static bool vjp_p(int flux, const DGParams<double>& prm, const double* u, const 
 }
 
 bool dg_vjp2(int p, int flux, const DGParams<double>& prm, const double* u, const double* v, const double* w,
-             double* out, double* out_d, hipStream_t st) {
+             double* out, double* out_d, hipStream_t st, const double* acc_scale) {
   switch (p) {
-    case 0: return vjp_p<0>(flux, prm, u, v, w, out, out_d, st);
-    case 1: return vjp_p<1>(flux, prm, u, v, w, out, out_d, st);
-    case 2: return vjp_p<2>(flux, prm, u, v, w, out, out_d, st);
-    case 3: return vjp_p<3>(flux, prm, u, v, w, out, out_d, st);
+    case 0: return vjp_p<0>(flux, prm, u, v, w, out, out_d, st, acc_scale);
+    case 1: return vjp_p<1>(flux, prm, u, v, w, out, out_d, st, acc_scale);
+    case 2: return vjp_p<2>(flux, prm, u, v, w, out, out_d, st, acc_scale);
+    case 3: return vjp_p<3>(flux, prm, u, v, w, out, out_d, st, acc_scale);
   }
   return false;
 }

@@ -19,10 +19,12 @@ bool dg_run3_f(int p, int flux, int mode, const DGParams<float>& prm, const DGIO
 
 // Transpose J(u)^T w (FP64).
 // out = J(u)^T w; if out_d is not null also out_d = d/deps [J(u + eps v)^T w].
+// With acc_scale (device scalar s, only with out_d) both are accumulated
+// instead: out += J(u)^T w, out_d += s d/deps [J(u + eps v)^T w].
 bool dg_vjp2(int p, int flux, const DGParams<double>& prm, const double* u, const double* v, const double* w,
-             double* out, double* out_d, hipStream_t st);
+             double* out, double* out_d, hipStream_t st, const double* acc_scale = nullptr);
 bool dg_vjp3(int p, int flux, const DGParams<double>& prm, const double* u, const double* v, const double* w,
-             double* out, double* out_d, hipStream_t st);
+             double* out, double* out_d, hipStream_t st, const double* acc_scale = nullptr);
 
 // Element-level helpers (elem_kernels.hip); runtime sizes, not on the hot path.
 struct ElemArgs {

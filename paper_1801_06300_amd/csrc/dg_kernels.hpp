@@ -1000,7 +1000,7 @@ template <int D, int P, int FLUX, typename ST>
 __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const double* __restrict__ u,
                                                      const double* __restrict__ vdir,
                                                      const double* __restrict__ w, double* __restrict__ out,
-                                                     double* __restrict__ out_d) {
+                                                     double* __restrict__ out_d, const double* acc_scale) {
   using T = double;
   using SS = StateScalar<ST>;
   using Sh = Shape<D, P>;
@@ -1245,7 +1245,14 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
         }
         acc[o] = acc[o] + s;
       }
-      if (ge < Epad) {
+      if (acc_scale) {
+        // accumulate (second order only): out += value, out_d += s deriv
+        if (SS::SECOND && ge < nE) {
+          const size_t g = (size_t)ki * Epad + ge;
+          out[g] = out[g] + SS::value(acc[o]);
+          out_d[g] = out_d[g] + (*acc_scale) * SS::deriv(acc[o]);
+        }
+      } else if (ge < Epad) {
         out[(size_t)ki * Epad + ge] = ge < nE ? SS::value(acc[o]) : T(0);
         if (SS::SECOND) out_d[(size_t)ki * Epad + ge] = ge < nE ? SS::deriv(acc[o]) : T(0);
       }
@@ -1257,16 +1264,17 @@ template <int D, int P, int FLUX>
 void launch_vjp(const DGParams<double>& prm, const double* u, const double* w, double* out, hipStream_t st) {
   constexpr int TE = VjpTile<D, P, FLUX, double>::TE;
   launch((dg_vjp_kernel<D, P, FLUX, double>), dim3((prm.Epad + TE - 1) / TE), dim3(256), 0, st, prm, u,
-         (const double*)nullptr, w, out, (double*)nullptr);
+         (const double*)nullptr, w, out, (double*)nullptr, (const double*)nullptr);
 }
 
-// out = J(u)^T w and out_d = d/deps [J(u + eps v)^T w] in one pass.
+// out = J(u)^T w and out_d = d/deps [J(u + eps v)^T w] in one pass (with
+// acc_scale: out += J(u)^T w, out_d += (*acc_scale) d/deps [...]).
 template <int D, int P, int FLUX>
 void launch_vjp2(const DGParams<double>& prm, const double* u, const double* v, const double* w, double* out,
-                 double* out_d, hipStream_t st) {
+                 double* out_d, const double* acc_scale, hipStream_t st) {
   constexpr int TE = VjpTile<D, P, FLUX, Dual<double, 1>>::TE;
   launch((dg_vjp_kernel<D, P, FLUX, Dual<double, 1>>), dim3((prm.Epad + TE - 1) / TE), dim3(256), 0, st, prm, u,
-         v, w, out, out_d);
+         v, w, out, out_d, acc_scale);
 }
 
 // Host launchers (defined in the per-dimension translation units).

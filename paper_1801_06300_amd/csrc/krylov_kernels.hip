@@ -1129,28 +1129,35 @@ void k_gemv(const T* A, const T* v, T* out, int n, const double* vscale, const i
 // Kernels of the reverse sweep through one Arnoldi run (FP64 basis).  The
 // basis vectors are v_i = sigma_i V_i; adjoint vectors are plain.
 
-// Partial dot products of x with sigma_i V_i, i in [i0, i0 + nvec): blockIdx.y
-// selects a chunk of RV_NV vectors; column c of the partials is vector i0 + c.
-constexpr int RV_NV = 16;
+// Vectors per group of the read-modify-write passes over the adjoint basis.
+constexpr int RK = 8;
 
+// Partial dot products of x with sigma_i V_i, i in [i0, i0 + nvec): blockIdx.y
+// selects a chunk of NV vectors (NV the smallest bucket of 4, 8, .., 32 that
+// holds nvec, or 32 chunks beyond); column c of the partials is vector
+// i0 + c.  Slots past the last vector re-read it (a cache hit) and are
+// dropped, so that every load of a point is in flight together.
+constexpr int RV_CHUNK = 32;
+
+template <int NV>
 __global__ __launch_bounds__(RT) void rv_dots_kernel(const double* __restrict__ V, size_t ld, int i0, int nvec,
                                                      const double* __restrict__ x, size_t n, double* part) {
-  constexpr int NP = RV_NV;
-  const int c0 = blockIdx.y * RV_NV;
+  constexpr int NP = pow2_ceil(NV);
+  const int c0 = blockIdx.y * NV;
   double acc[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) acc[i] = 0.0;
   const size_t np = (n + 1) / 2;
   for (size_t p = (size_t)blockIdx.x * RT + threadIdx.x; p < np; p += (size_t)gridDim.x * RT) {
-    double x0, x1;
+    double x0, x1, v[NV][2];
     load_pair(x, p, n, x0, x1);
 #pragma unroll
-    for (int i = 0; i < RV_NV; ++i) {
+    for (int i = 0; i < NV; ++i) {
       const int c = c0 + i < nvec ? c0 + i : nvec - 1;
-      double v0, v1;
-      load_pair(V + (size_t)(i0 + c) * ld, p, n, v0, v1);
-      acc[i] += v0 * x0 + v1 * x1;
+      load_pair(V + (size_t)(i0 + c) * ld, p, n, v[i][0], v[i][1]);
     }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] += v[i][0] * x0 + v[i][1] * x1;
   }
   __shared__ double red[RW][NP];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1158,7 +1165,7 @@ __global__ __launch_bounds__(RT) void rv_dots_kernel(const double* __restrict__ 
   Bfly<NP / 2, 32>::run(acc, lane, col);
   if ((lane & (64 / NP - 1)) == 0) red[wid][col] = acc[0];
   __syncthreads();
-  for (int c = threadIdx.x; c < RV_NV; c += RT) {
+  for (int c = threadIdx.x; c < NV; c += RT) {
     if (c0 + c < nvec) {
       double t = 0.0;
 #pragma unroll
@@ -1177,13 +1184,28 @@ __global__ __launch_bounds__(RT) void rv_dots_finalize(const double* part, int n
   for (int c = threadIdx.x; c < nvec; c += RT) out[c] = (sigma ? sigma[i0 + c] : 1.0) * col[c];
 }
 
+// The partials of k_rv_dots; returns the blocks per chunk (partials per column).
+static int rv_dots_partials(const double* V, size_t ld, int i0, int nvec, const double* x, size_t n, double* part,
+                            hipStream_t st) {
+  const unsigned nc = (unsigned)((nvec + RV_CHUNK - 1) / RV_CHUNK);
+  int nb = (int)gs_blocks(n) / (int)nc;
+  if (nb < 1) nb = 1;
+  const dim3 g((unsigned)nb, nc), b(RT);
+  if (nvec <= 4) launch(rv_dots_kernel<4>, g, b, 0, st, V, ld, i0, nvec, x, n, part);
+  else if (nvec <= 8) launch(rv_dots_kernel<8>, g, b, 0, st, V, ld, i0, nvec, x, n, part);
+  else if (nvec <= 12) launch(rv_dots_kernel<12>, g, b, 0, st, V, ld, i0, nvec, x, n, part);
+  else if (nvec <= 16) launch(rv_dots_kernel<16>, g, b, 0, st, V, ld, i0, nvec, x, n, part);
+  else if (nvec <= 20) launch(rv_dots_kernel<20>, g, b, 0, st, V, ld, i0, nvec, x, n, part);
+  else if (nvec <= 24) launch(rv_dots_kernel<24>, g, b, 0, st, V, ld, i0, nvec, x, n, part);
+  else if (nvec <= 28) launch(rv_dots_kernel<28>, g, b, 0, st, V, ld, i0, nvec, x, n, part);
+  else launch(rv_dots_kernel<RV_CHUNK>, g, b, 0, st, V, ld, i0, nvec, x, n, part);
+  return nb;
+}
+
 void k_rv_dots(const double* V, size_t ld, const double* sigma, int i0, int nvec, const double* x, size_t n,
                double* part, double* out, hipStream_t st) {
   if (nvec <= 0) return;
-  const unsigned nc = (unsigned)((nvec + RV_NV - 1) / RV_NV);
-  int nb = (int)gs_blocks(n) / (int)nc;
-  if (nb < 1) nb = 1;
-  launch(rv_dots_kernel, dim3((unsigned)nb, nc), dim3(RT), 0, st, V, ld, i0, nvec, x, n, part);
+  const int nb = rv_dots_partials(V, ld, i0, nvec, x, n, part, st);
   launch(rv_dots_finalize, dim3(1), dim3(RT), 0, st, (const double*)part, nvec, nb, sigma, i0, out);
 }
 
@@ -1223,19 +1245,25 @@ void k_rv_combine(const RvComb& a, double* out, size_t n, hipStream_t st) {
   launch(rv_combine_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a, out, n);
 }
 
-// Iteration j < M - 1: r, w_bar and J v_j (Arnoldi relation) from one read
-// of V_0 .. V_{j+1} (see krylov_kernels.hpp).
-__global__ __launch_bounds__(256) void rv_combine3_kernel(const double* __restrict__ vb1, const RState* rs,
-                                                          const double* __restrict__ V, size_t ld,
-                                                          const double* sigma, int j, double* r_out, double* wb_out,
-                                                          double* wj_out, size_t n) {
-  __shared__ double f1[KMAX + 2], f2[KMAX + 2];
+// Iteration j < M - 1 in one pass over V_0 .. V_{j+1}, v_{j+1}_bar and the
+// adjoint basis Vb_0 .. Vb_j (coefficients from k_rv_dots_coef):
+//   r = alpha v_{j+1}_bar + gamma v_{j+1},  wb = r + sum_{i<=j} b_i v_i,
+//   wj = sum_{i<=j+1} c_i v_i  (J v_j by the Arnoldi relation; v_i = sigma_i V_i),
+//   Vb_i += a_i r + b_i wj  (i <= j);
+// r and wj stay in registers, only wb is written.
+__global__ __launch_bounds__(256) void rv_iter_kernel(const double* __restrict__ vb1, const RState* rs,
+                                                      const double* __restrict__ V, size_t ld, const double* sigma,
+                                                      int j, double* __restrict__ Vb, double* __restrict__ wb_out,
+                                                      size_t n) {
+  __shared__ double f1[KMAX + 2], f2[KMAX + 2], ra[KMAX + 2], rb[KMAX + 2];
   __shared__ double sa, sg, sc;
   const int nv = j + 1;
   for (int i = threadIdx.x; i < nv; i += blockDim.x) {
     const double s = sigma ? sigma[i] : 1.0;
     f1[i] = rs->b[i] * s;
     f2[i] = rs->c[i] * s;
+    ra[i] = rs->a[i];
+    rb[i] = rs->b[i];
   }
   if (threadIdx.x == 0) {
     const double s = sigma ? sigma[j + 1] : 1.0;
@@ -1263,17 +1291,25 @@ __global__ __launch_bounds__(256) void rv_combine3_kernel(const double* __restri
       r1 += f1[i] * v;
       r2 += f2[i] * v;
     }
-    r_out[idx] = r;
     wb_out[idx] = r1;
-    wj_out[idx] = r2;
+    // the rank update, reads of a group of RK before its writes
+    for (int g0 = 0; g0 < nv; g0 += RK) {
+      double* p = Vb + (size_t)g0 * ld + idx;
+      double old[RK];
+#pragma unroll
+      for (int k = 0; k < RK; ++k) old[k] = g0 + k < nv ? p[(size_t)k * ld] : 0.0;
+#pragma unroll
+      for (int k = 0; k < RK; ++k)
+        if (g0 + k < nv) p[(size_t)k * ld] = old[k] + (ra[g0 + k] * r + rb[g0 + k] * r2);
+    }
   }
 }
 
-void k_rv_combine3(const double* vb1, const RState* rs, const double* V, size_t ld, const double* sigma, int j,
-                   double* r, double* wb, double* wj, size_t n, hipStream_t st) {
+void k_rv_iter(const double* vb1, const RState* rs, const double* V, size_t ld, const double* sigma, int j,
+               double* Vb, double* wb, size_t n, hipStream_t st) {
   size_t blocks = (n + 255) / 256;
   if (blocks > 2048) blocks = 2048;
-  launch(rv_combine3_kernel, dim3((unsigned)blocks), dim3(256), 0, st, vb1, rs, V, ld, sigma, j, r, wb, wj, n);
+  launch(rv_iter_kernel, dim3((unsigned)blocks), dim3(256), 0, st, vb1, rs, V, ld, sigma, j, Vb, wb, n);
 }
 
 // o1 += y1 and o2 += (*s2) y2 in one pass.
@@ -1293,10 +1329,13 @@ void k_rv_acc2(double* o1, const double* y1, double* o2, const double* y2, const
   launch(rv_acc2_kernel, dim3((unsigned)blocks), dim3(256), 0, st, o1, y1, o2, y2, s2, n);
 }
 
-// Vb_i (=|+=) a[i] r + b[i] w for i < nvec (r or w may be null).
-__global__ __launch_bounds__(256) void rv_rank_kernel(double* Vb, size_t ld, int nvec, const double* r,
-                                                      const double* w, const double* ca, const double* cb, int set,
-                                                      size_t n) {
+// Vb_i (=|+=) a[i] r + b[i] w for i < nvec (r or w may be null).  The
+// vectors go in groups of RK: the reads of a group are issued before its
+// writes (the compiler cannot reorder them through the run-time stride), so
+// each lane has RK loads in flight at a small register cost.
+__global__ __launch_bounds__(256) void rv_rank_kernel(double* __restrict__ Vb, size_t ld, int nvec,
+                                                      const double* __restrict__ r, const double* __restrict__ w,
+                                                      const double* ca, const double* cb, int set, size_t n) {
   __shared__ double sa[KMAX + 2], sb[KMAX + 2];
   for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
     sa[i] = ca ? ca[i] : 0.0;
@@ -1305,10 +1344,14 @@ __global__ __launch_bounds__(256) void rv_rank_kernel(double* Vb, size_t ld, int
   __syncthreads();
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
     const double rr = r ? r[idx] : 0.0, ww = w ? w[idx] : 0.0;
-    for (int i = 0; i < nvec; ++i) {
-      double* p = Vb + (size_t)i * ld + idx;
-      const double add = sa[i] * rr + sb[i] * ww;
-      *p = set ? add : *p + add;
+    for (int g0 = 0; g0 < nvec; g0 += RK) {
+      double* p = Vb + (size_t)g0 * ld + idx;
+      double old[RK];
+#pragma unroll
+      for (int i = 0; i < RK; ++i) old[i] = (!set && g0 + i < nvec) ? p[(size_t)i * ld] : 0.0;
+#pragma unroll
+      for (int i = 0; i < RK; ++i)
+        if (g0 + i < nvec) p[(size_t)i * ld] = old[i] + (sa[g0 + i] * rr + sb[g0 + i] * ww);
     }
   }
 }
@@ -1392,23 +1435,30 @@ __global__ void rv_coef_w_kernel(const KState* ks, RState* rs, int j, const doub
   }
 }
 
-// Iteration j < M - 1 from d_i = v_i . v_{j+1}_bar (i <= j + 1):
+// Iteration j < M - 1, from the partials of d_i = v_i . v_{j+1}_bar
+// (i <= j + 1; column sums in a fixed order, as rv_dots_finalize):
 //   r_bar = alpha v_{j+1}_bar + gamma v_{j+1},  alpha = 1 / h,
 //   gamma = H_bar_{j+1,j} - d_{j+1} / h,  h = h_{j+1,j};
 //   c_i = v_i . r_bar = alpha d_i (i <= j: the basis is orthonormal, the
 //   reading under which the sweep differentiates the Arnoldi relations);
 //   b[i] = H_bar_{i,j} - c_i, a[i] = -h_{i,j} (i <= j); c[i] = h_{i,j} (i <= j + 1).
-__global__ void rv_coef_rw_kernel(const KState* ks, RState* rs, int j, const double* d) {
+__global__ __launch_bounds__(RT) void rv_coef_rw_kernel(const double* part, int nblk, const double* sigma,
+                                                        const KState* ks, RState* rs, int j) {
+  __shared__ double col[KMAX + 2];
+  block_col_sums(part, j + 2, nblk, col);
+  __syncthreads();
   const double h = ks->H[(size_t)j * KLD + j + 1];
   const double al = 1.0 / h;
   if (threadIdx.x == 0) {
+    const double dj1 = (sigma ? sigma[j + 1] : 1.0) * col[j + 1];
     rs->alpha = al;
-    rs->gamma = rs->Hbar[(size_t)j * KLD + j + 1] - d[j + 1] / h;
+    rs->gamma = rs->Hbar[(size_t)j * KLD + j + 1] - dj1 / h;
   }
-  for (int i = threadIdx.x; i < KMAX + 2; i += blockDim.x) {
+  for (int i = threadIdx.x; i < KMAX + 2; i += RT) {
     const bool in = i <= j;
     const double hij = (i <= j + 1 && i < KLD) ? ks->H[(size_t)j * KLD + i] : 0.0;
-    rs->b[i] = in ? rs->Hbar[(size_t)j * KLD + i] - al * d[i] : 0.0;
+    const double di = in ? (sigma ? sigma[i] : 1.0) * col[i] : 0.0;
+    rs->b[i] = in ? rs->Hbar[(size_t)j * KLD + i] - al * di : 0.0;
     rs->a[i] = in ? -hij : 0.0;
     rs->c[i] = (i <= j + 1) ? hij : 0.0;
   }
@@ -1431,8 +1481,10 @@ void k_rv_phi_adjoint(const KState* ks, RState* rs, const double* dots, double f
 void k_rv_coef_w(const KState* ks, RState* rs, int j, const double* cdots, hipStream_t st) {
   launch(rv_coef_w_kernel, dim3(1), dim3(64), 0, st, ks, rs, j, cdots);
 }
-void k_rv_coef_rw(const KState* ks, RState* rs, int j, const double* d, hipStream_t st) {
-  launch(rv_coef_rw_kernel, dim3(1), dim3(64), 0, st, ks, rs, j, d);
+void k_rv_dots_coef(const double* V, size_t ld, const double* sigma, int j, const double* vb1, size_t n, double* part,
+                    const KState* ks, RState* rs, hipStream_t st) {
+  const int nb = rv_dots_partials(V, ld, 0, j + 2, vb1, n, part, st);
+  launch(rv_coef_rw_kernel, dim3(1), dim3(RT), 0, st, (const double*)part, nb, sigma, ks, rs, j);
 }
 void k_rv_coef_b(const KState* ks, RState* rs, const double* tdot, hipStream_t st) {
   launch(rv_coef_b_kernel, dim3(1), dim3(1), 0, st, ks, rs, tdot);

@@ -118,12 +118,12 @@ struct RvComb {
 void k_rv_dots(const double* V, size_t ld, const double* sigma, int i0, int nvec, const double* x, size_t n,
                double* part, double* out, hipStream_t st);
 void k_rv_combine(const RvComb& a, double* out, size_t n, hipStream_t st);
-// Iteration j < M - 1 of the reverse sweep, from one read of V_0 .. V_{j+1}
-// and v_{j+1}_bar (coefficients from k_rv_coef_rw):
+// Iteration j < M - 1 of the reverse sweep in one pass (coefficients from
+// k_rv_dots_coef; v_i = sigma_i V_i):
 //   r = alpha v_{j+1}_bar + gamma v_{j+1},  wb = r + sum_{i<=j} b_i v_i,
-//   wj = sum_{i<=j+1} c_i v_i  (v_i = sigma_i V_i)
-void k_rv_combine3(const double* vb1, const RState* rs, const double* V, size_t ld, const double* sigma, int j,
-                   double* r, double* wb, double* wj, size_t n, hipStream_t st);
+//   wj = sum_{i<=j+1} c_i v_i,  Vb_i += a_i r + b_i wj (i <= j); writes wb.
+void k_rv_iter(const double* vb1, const RState* rs, const double* V, size_t ld, const double* sigma, int j,
+               double* Vb, double* wb, size_t n, hipStream_t st);
 // o1 += y1, o2 += (*s2) y2
 void k_rv_acc2(double* o1, const double* y1, double* o2, const double* y2, const double* s2, size_t n,
                hipStream_t st);
@@ -133,9 +133,10 @@ void k_rv_init(const KState* ks, RState* rs, double fac, const double* dtp, hipS
 void k_rv_phi_adjoint(const KState* ks, RState* rs, const double* dots, double fac, const double* dtp, double* mem,
                       hipStream_t st);
 void k_rv_coef_w(const KState* ks, RState* rs, int j, const double* cdots, hipStream_t st);
-// alpha, gamma and the coefficients a, b, c of iteration j < M - 1 from
-// d_i = v_i . v_{j+1}_bar, i <= j + 1
-void k_rv_coef_rw(const KState* ks, RState* rs, int j, const double* d, hipStream_t st);
+// Iteration j < M - 1: d_i = v_i . v_{j+1}_bar (i <= j + 1) in one pass, then
+// alpha, gamma and the coefficients a, b, c into rs
+void k_rv_dots_coef(const double* V, size_t ld, const double* sigma, int j, const double* vb1, size_t n, double* part,
+                    const KState* ks, RState* rs, hipStream_t st);
 void k_rv_coef_b(const KState* ks, RState* rs, const double* tdot, hipStream_t st);
 void k_gemv_t(const double* A, const double* v, double* out, int n, hipStream_t st);
 

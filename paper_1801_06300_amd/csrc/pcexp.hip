@@ -441,28 +441,32 @@ void arnoldi_reverse(pcexp_ctx* c, const double* u_lin, const KState* ks, int M,
   k_rv_dots(V, ld, sig, 0, M, xbar, n, B.part, rs->dots, st);
   k_rv_phi_adjoint(ks, rs, rs->dots, fac, dtp, B.mem, st);
   for (int j = M - 1; j >= 0; --j) {
-    const double* rptr = nullptr;
     if (j < M - 1) {
       // d_i = v_i . v_{j+1}_bar (i <= j + 1) in one pass, then r_bar, w_bar = r_bar + sum_{i <= j}
-      // h_bar_i v_i and J v_j = sum_{i <= j+1} c_i v_i (the Arnoldi relation) from one read of
-      // the basis
+      // h_bar_i v_i, J v_j = sum_{i <= j+1} c_i v_i (the Arnoldi relation) and the updates of
+      // v_i_bar (i <= j) from one read of the basis
       double* vb1 = B.Vb + (size_t)(j + 1) * ld;
-      k_rv_dots(V, ld, sig, 0, j + 2, vb1, n, B.part, rs->dots, st);
-      k_rv_coef_rw(ks, rs, j, rs->dots, st);
-      k_rv_combine3(vb1, rs, V, ld, sig, j, B.r, B.wb, B.wj, n, st);
-      rptr = B.r;
+      k_rv_dots_coef(V, ld, sig, j, vb1, n, B.part, ks, rs, st);
+      k_rv_iter(vb1, rs, V, ld, sig, j, B.Vb, B.wb, n, st);
     } else {
       k_rv_coef_w(ks, rs, j, nullptr, st);
       RvComb a{};
-      a.x = rptr; a.axc = 1.0; a.V = V; a.ld = ld; a.sigma = sig; a.coef = rs->b; a.i0 = 0; a.nvec = j + 1;
+      a.x = nullptr; a.axc = 1.0; a.V = V; a.ld = ld; a.sigma = sig; a.coef = rs->b; a.i0 = 0; a.nvec = j + 1;
       k_rv_combine(a, B.wb, n, st);
       jvp_int(c, PCEXP_JVP_TANGENT, PCEXP_PREC_F64, u_lin, nullptr, V + (size_t)j * ld, B.wj, &sig[j], nullptr,
               nullptr, nullptr, st);
+      k_rv_rank(B.Vb, ld, j + 1, nullptr, B.wj, rs->a, rs->b, false, n, st);
     }
-    k_rv_rank(B.Vb, ld, j + 1, rptr, B.wj, rs->a, rs->b, false, n, st);
-    vjp_int(c, u_lin, V + (size_t)j * ld, B.wb, B.t1, B.t2, false, st);
-    // v_j_bar += J^T w_bar, u_bar += sigma_j (d_u[J v_j])^T w_bar
-    k_rv_acc2(B.Vb + (size_t)j * ld, B.t1, ubar, B.t2, &sig[j], n, st);
+    // v_j_bar += J^T w_bar, u_bar += sigma_j (d_u[J v_j])^T w_bar (accumulated by the DG
+    // kernel itself; the dense test operators have no second-order term)
+    if (c->dense) {
+      vjp_int(c, u_lin, V + (size_t)j * ld, B.wb, B.t1, B.t2, false, st);
+      k_rv_acc2(B.Vb + (size_t)j * ld, B.t1, ubar, B.t2, &sig[j], n, st);
+    } else if (c->dim == 2) {
+      dg_vjp2(c->p, c->flux, params_d(c), u_lin, V + (size_t)j * ld, B.wb, B.Vb + (size_t)j * ld, ubar, st, &sig[j]);
+    } else {
+      dg_vjp3(c->p, c->flux, params_d(c), u_lin, V + (size_t)j * ld, B.wb, B.Vb + (size_t)j * ld, ubar, st, &sig[j]);
+    }
   }
   k_rv_dots(V, ld, sig, 0, 1, B.Vb, n, B.part, &rs->t[0], st);
   k_rv_coef_b(ks, rs, &rs->t[0], st);
