@@ -723,14 +723,11 @@ __device__ void mat_mul_mfma(const double* A, const double* B, const double* D, 
     mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
     const double* a = A + (size_t)lk * ld + ti * 16 + li;
     const double* b = B + (size_t)(tj * 16 + li) * ld + lk;
-    if (np == 32) {
-      mfma_chain<8>(a, b, ld, acc);
-    } else if (np == 16) {
-      mfma_chain<4>(a, b, ld, acc);
-    } else {
-      for (int k0 = 0; k0 < np; k0 += 4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[(size_t)k0 * ld], b[k0], acc, 0, 0, 0);
-    }
+    // chunks of 32 along k (np is a multiple of 16): the loads of a chunk
+    // are in flight together, the products keep the order of k
+    int k0 = 0;
+    for (; k0 + 32 <= np; k0 += 32) mfma_chain<8>(a + (size_t)k0 * ld, b + k0, ld, acc);
+    if (k0 < np) mfma_chain<4>(a + (size_t)k0 * ld, b + k0, ld, acc);
     const int col = tj * 16 + li;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
