@@ -89,9 +89,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--workload", default="vortex2d", choices=["vortex2d", "channel", "vortex3d", "stiffvortex"],
+    ap.add_argument("--workload", default="vortex2d",
+                    choices=["vortex2d", "channel", "vortex3d", "stiffvortex", "reverse"],
                     help="vortex2d: the headline PCEXP step benchmark; channel: steady bump channel to "
-                         "||R(rho)|| <= 1e-10 with the CFL ramp; vortex3d: 3D P2 vortex, mixed precision")
+                         "||R(rho)|| <= 1e-10 with the CFL ramp; vortex3d: 3D P2 vortex, mixed precision; "
+                         "reverse: the discrete adjoint of one step of the headline workload alone")
     ap.add_argument("--channel-iters", type=int, default=12000,
                     help="iteration cap of the steady channel runs (a short cap serves profiling)")
     ap.add_argument("--sections", default="all",
@@ -356,6 +358,43 @@ def bench_vortex3d(args, dev):
     print(json.dumps(line))
 
 
+def bench_reverse(args, ctx, u0, dt0, m, K):
+    """The discrete adjoint of one PCEXP step of the headline workload
+    (dt frozen from u_0, m = 30, FP64): step_vjp recomputes the forward step
+    with both Krylov bases, then runs the reverse sweep.  Reports its time
+    per call against a forward step with the same dt."""
+    import torch
+    import workloads as W
+
+    ub = torch.as_tensor(W.random_unit_vector(tuple(u0.shape), 501), device=u0.device)
+    log(f"reverse: {args.warmup} warm-up and {args.steps} timed reverse steps")
+    for _ in range(max(args.warmup, 1)):
+        ctx.step_vjp(u0, ub, dt0, m=m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g = ctx.step_vjp(u0, ub, dt0, m=m)
+    torch.cuda.synchronize()
+    rev = (time.perf_counter() - t0) / args.steps
+    u = u0.clone()
+    ctx.step(u, dt=dt0, m=m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        u = u0.clone()
+        ctx.step(u, dt=dt0, m=m)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / args.steps
+    out = dict(metric="reverse (discrete adjoint) PCEXP step time", value=round(1e3 * rev, 4), unit="ms",
+               n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=round(1e3 * rev, 4),
+               higher_is_better=False, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+               config=dict(workload="discrete adjoint of one PCEXP step, 2D isentropic vortex 128x128x2 jittered, "
+                                    "DG P2, Roe, m=30, dt frozen from u_0 (CFL 20), FP64", K=K, m=m),
+               forward_ms_per_step=round(1e3 * fwd, 4), ratio_to_forward=round(rev / fwd, 4),
+               gradient_norm=float(torch.linalg.norm(g)))
+    print(json.dumps(out), flush=True)
+
+
 def section_adjoint(dev, ctx, u0, dt_fixed):
     """Gradient of J(u_0) = sum_{n=1}^{40} dt int (p_h(t_n) - 1)^2 dx through 40
     PCEXP steps (dt frozen from u_0, m = 30, checkpoints every 8) on the
@@ -471,6 +510,8 @@ def main():
     dt0 = ctx.stable_dt(u0, cfl)
     m = cfg["m"]
     steps, warm = args.steps, args.warmup
+    if args.workload == "reverse":
+        return bench_reverse(args, ctx, u0, dt0, m, K)
 
     def run(prec, jvp, nsteps, profile=False):
         # the steps of a timed region run through one pcexp_advance call: the
