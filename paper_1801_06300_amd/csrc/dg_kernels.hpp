@@ -760,13 +760,14 @@ __global__ __launch_bounds__(NT) void dg_apply(DGParams<T> prm, DGIO<T> io) {
   }
   __syncthreads();
 
-  // ---- faces: traces and the numerical flux, item (r, j) for point r of
-  // list entry j.  A face whose two elements lie in the tile is evaluated
-  // once, by the side of smaller index, which also writes the neighbour's
-  // term: both sides parametrise the face by the same points, the normals
-  // are opposite, and the Roe and Lax-Friedrichs fluxes are antisymmetric,
-  // F(U_N, U_E, -n) = -F(U_E, U_N, n), so the neighbour's value at point r
-  // is -F weighted by its own face weight.
+  // ---- faces: traces and the numerical flux, item (f, r, e) for point r of
+  // face f of element e (each face computed by both sides), or with DEDUP
+  // item (r, j) for point r of list entry j: a face whose two elements lie
+  // in the tile is then evaluated once, by the side of smaller index, which
+  // also writes the neighbour's term: both sides parametrise the face by the
+  // same points, the normals are opposite, and the Roe and Lax-Friedrichs
+  // fluxes are antisymmetric, F(U_N, U_E, -n) = -F(U_E, U_N, n), so the
+  // neighbour's value at point r is -F weighted by its own face weight.
   {
     const int nA = DEDUP ? ftot(0) : 0, nT = DEDUP ? nA + ftot(1) + ftot(2) : NF * TE;
     constexpr int NIT = (NF * NFQ * TE + NT - 1) / NT;
