@@ -975,9 +975,11 @@ struct VjpTile {
   using Sh = Shape<D, P>;
   static constexpr int NX = (Sh::NQ > Sh::NF * Sh::NFQ ? Sh::NQ : Sh::NF * Sh::NFQ) * Sh::NV;
   static constexpr int per_elem = (int)sizeof(ST) * (Sh::NVB + NX) + 8 * Sh::NVB + Sh::NF;
-  // derivative directions per flux evaluation: the whole Jacobian at once
-  // for first order; one column at a time for the nested second-order
-  // scalars, whose NV-direction form does not fit the register file
+  // derivative directions per face-flux evaluation: the whole Jacobian at
+  // once for first order; one column at a time for the nested second-order
+  // scalars, whose NV-direction form of the numerical flux does not fit the
+  // register file (the lighter physical flux of the volume term takes all
+  // NV directions in one pass in both cases)
   static constexpr int NC = std::is_same<ST, double>::value ? Sh::NV : 1;
   // As for the forward tiles: the fewest rounds of the two pointwise phases
   // (NQ TE and NF NFQ TE items over 256 threads) per element under the LDS
@@ -1013,8 +1015,9 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
   constexpr int NOUT = (NVB * TE + NT - 1) / NT;
   constexpr int NC = VjpTile<D, P, FLUX, ST>::NC;
   using SD = Dual<ST, NC>;
-  // The passes over the derivative directions are kept apart (not unrolled)
-  // so that only one pass's duals are live; Ub is indexed through selects.
+  // The face terms' passes over the derivative directions are kept apart
+  // (not unrolled) so that only one pass's duals are live; Ub is indexed
+  // through selects.
   auto add_dir = [](ST* Ub, int j, ST x) {
 #pragma unroll
     for (int jj = 0; jj < NV; ++jj)
@@ -1077,23 +1080,30 @@ __global__ __launch_bounds__(256) void dg_vjp_kernel(DGParams<double> prm, const
     ST Ub[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) Ub[j] = ST(0);
-#pragma unroll 1
-    for (int j0 = 0; j0 < NV; j0 += NC) {
-      SD U[NV];
-      seed(Uv, j0, U);
+    {
+      // every state component seeded at once: the physical flux is light
+      // enough for NV directions of the nested scalars
+      using SDV = Dual<ST, NV>;
+      SDV U[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        U[k].v = Uv[k];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) U[k].d[c] = ST(k == c ? 1.0 : 0.0);
+      }
 #pragma unroll
       for (int r = 0; r < D; ++r) {
         T a[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) a[c] = prm.ainv[(size_t)(r * D + c) * Epad + ge];
-        SD F[NV];
+        SDV F[NV];
         normal_flux<D>(U, a, gm1, F);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
+        for (int c = 0; c < NV; ++c) {
           ST x = ST(0);
 #pragma unroll
           for (int k = 0; k < NV; ++k) x = x + F[k].d[c] * gb[r][k];
-          add_dir(Ub, j0 + c, x);
+          Ub[c] = Ub[c] + x;
         }
       }
     }
