@@ -80,13 +80,15 @@ def test_vjp2_parity(name, p, flux, full):
         assert abs(float(np.sum(z * k6)) - want) < 1e-7 * max(abs(want), np.linalg.norm(k6) * 1e-3)
 
 
-@pytest.mark.parametrize("m", [6, 20])
+@pytest.mark.parametrize("n,m", [(20, 6), (20, 20), (80, 40), (80, 64)])
 @pytest.mark.parametrize("scheme", ["pcexp", "exp1"])
-def test_step_vjp_dense(m, scheme):
-    """Linear split operator: <ubar, D d> with D d exact by complex step."""
+def test_step_vjp_dense(n, m, scheme):
+    """Linear split operator: <ubar, D d> with D d exact by complex step.
+    With n = 80 the Arnoldi runs reach m = 40 and 64 without breakdown, so
+    the reverse sweep's dot passes take more than 32 basis vectors (chunks)
+    and its coefficient sums more than 32 columns."""
     PCEXP = _dev()
     rng = np.random.default_rng(7)
-    n = 20
     A = rng.standard_normal((n, n)) / 2 - 2 * np.eye(n)
     B = rng.standard_normal((n, n)) / 2 - 1.5 * np.eye(n)
     ctx = PCEXP.dense(A, B)
