@@ -20,6 +20,8 @@ def mesh_case(name):
         return W.periodic_square(8, 10.0, 0.15, 23), 45.0
     if name == "cube3":
         return W.periodic_cube(3, 10.0), 45.0
+    if name == "box3":
+        return W.box_cube(3, 10.0, 0.1, 7), 0.0
     if name == "chan":
         return W.channel_bump(12, 4, height=0.1, seed=5), 0.0
     if name == "chan_flat":

@@ -48,7 +48,8 @@ def _n(t):
 
 
 CASES = [("sq3", 1, "lf"), ("sq4j", 2, "roe"), ("sq4j", 3, "lf"), ("sq3", 0, "roe"),
-         ("cube3", 1, "lf"), ("cube3", 2, "roe"), ("chan", 2, "roe"), ("chan", 1, "lf")]
+         ("cube3", 1, "lf"), ("cube3", 2, "roe"), ("chan", 2, "roe"), ("chan", 1, "lf"),
+         ("box3", 1, "roe"), ("box3", 2, "lf")]
 
 
 @pytest.mark.parametrize("name,p,flux", CASES)
@@ -98,7 +99,8 @@ def test_fd_jvp_parity(name, p, flux):
     assert rel(fd, jvp_cs(g, u, v)) < 1e-5
 
 
-@pytest.mark.parametrize("name,p,flux", [("sq4j", 2, "roe"), ("cube3", 2, "lf"), ("chan", 2, "roe")])
+@pytest.mark.parametrize("name,p,flux", [("sq4j", 2, "roe"), ("cube3", 2, "lf"), ("chan", 2, "roe"),
+                                         ("box3", 2, "roe")])
 def test_mixed_jvp_bound(name, p, flux):
     """FP32 tangent JVP against the FP64 oracle: stated bound 1e-5 relative."""
     g, ctx, u = _pair(name, p, flux, amp=1e-3)
@@ -108,7 +110,7 @@ def test_mixed_jvp_bound(name, p, flux):
 
 
 @pytest.mark.parametrize("name,p,flux", [("sq3", 1, "roe"), ("sq3", 2, "lf"), ("cube3", 1, "roe"),
-                                         ("chan", 1, "roe")])
+                                         ("chan", 1, "roe"), ("box3", 1, "lf")])
 def test_vjp_parity(name, p, flux):
     g, ctx, u = _pair(name, p, flux, amp=1e-3)
     w = W.random_unit_vector(u.shape, 10)

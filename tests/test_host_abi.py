@@ -90,7 +90,7 @@ def test_host_gauss_jacobi_matches_scipy(n, a, b):
     assert np.max(np.abs(x - xs)) < 1e-14 and np.max(np.abs(w - ws)) < 1e-14 * ws.max()
 
 
-@pytest.mark.parametrize("name,p", [("sq4j", 2), ("cube3", 2), ("chan", 1), ("sq3", 3)])
+@pytest.mark.parametrize("name,p", [("sq4j", 2), ("cube3", 2), ("chan", 1), ("sq3", 3), ("box3", 2)])
 def test_host_setup_against_oracle(name, p):
     from tests.helpers import mesh_case
     m, _ = mesh_case(name)
@@ -108,6 +108,7 @@ def test_host_setup_against_oracle(name, p):
     nbr = S["nbr"].reshape(nf, Ep)[:, :nE].T
     assert np.array_equal(nbr, np.where(g.mesh.nbr >= 0, g.mesh.nbr, -1))
     finfo = S["finfo"].reshape(nf, Ep)[:, :nE].T
+    assert np.array_equal((finfo >> 8) & 3, np.where(g.mesh.nbr >= 0, 0, g.mesh.bc))
     fpts = S["fpts"].reshape(nf, nori, nfq, d)
     X = g.mesh.X
     A = X[:, 1:, :] - X[:, :1, :]

@@ -57,6 +57,7 @@ def _meshes():
         ("sq4j", W.periodic_square(4, 10.0, 0.15, 11), 45.0),
         ("cube3", W.periodic_cube(3, 10.0), 45.0),
         ("chan", W.channel_bump(8, 4, height=0.1, seed=5), 0.0),
+        ("box3", W.box_cube(3, 10.0, 0.1, 7), 0.0),
     ]
 
 
@@ -164,14 +165,18 @@ def test_roe_supersonic_upwinding():
     assert np.allclose(euler.roe(UL, UR, n, GAMMA), euler.normal_flux(UR, n, GAMMA), atol=1e-12)
 
 
-def test_ghost_states():
-    UL, n = _states(30, 2, 8)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_ghost_states(dim):
+    UL, n = _states(30, dim, 8)
     G = euler.slip_wall_ghost(UL, n, GAMMA)
     # mirror: same density, energy, tangential momentum; reversed normal momentum
     assert np.allclose(G[:, 0], UL[:, 0]) and np.allclose(G[:, -1], UL[:, -1])
-    assert np.allclose(np.sum(G[:, 1:3] * n, 1), -np.sum(UL[:, 1:3] * n, 1))
+    mG, mL = G[:, 1:1 + dim], UL[:, 1:1 + dim]
+    gn, ln = np.sum(mG * n, 1), np.sum(mL * n, 1)
+    assert np.allclose(gn, -ln)
+    assert np.allclose(mG - gn[:, None] * n, mL - ln[:, None] * n, atol=1e-13)
     # far field: the free stream is its own ghost
-    prim = W.freestream_prim(2, angle_deg=0.0)
+    prim = W.freestream_prim(dim, angle_deg=0.0)
     Uinf = np.tile(W.prim_to_cons(prim), (30, 1))
     assert np.allclose(euler.farfield_ghost(Uinf, n, prim, GAMMA), Uinf, atol=1e-13)
 
@@ -209,7 +214,8 @@ def _prims(U):
     return rho, v, p
 
 
-def test_farfield_characteristics():
+@pytest.mark.parametrize("dim", [2, 3])
+def test_farfield_characteristics(dim):
     """Riemann-invariant far field, checked on the ghost state it returns:
     for subsonic normal flow the ghost carries the interior's outgoing
     invariant v.n + 2c/(g-1) and the free stream's incoming one
@@ -217,17 +223,19 @@ def test_farfield_characteristics():
     upwind side (interior if the ghost's v.n >= 0); supersonic outflow returns
     the interior state, supersonic inflow the free stream."""
     rng = np.random.default_rng(21)
-    N, dim = 60, 2
+    N = 60
     n = rng.standard_normal((N, dim))
     n /= np.linalg.norm(n, axis=1, keepdims=True)
     rho = rng.uniform(0.7, 1.4, N)
     p = rng.uniform(0.7, 1.4, N)
     c = np.sqrt(GAMMA * p / rho)
-    t = np.stack([-n[:, 1], n[:, 0]], 1)
+    t = rng.standard_normal((N, dim))
+    t -= np.sum(t * n, 1)[:, None] * n
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
     vn = rng.uniform(-0.8, 0.8, N) * c
     v = vn[:, None] * n + rng.uniform(-0.5, 0.5, (N, 1)) * t
     UL = W.prim_to_cons(np.concatenate([rho[:, None], v, p[:, None]], 1))
-    prim = W.freestream_prim(2, mach=0.5, angle_deg=30.0)
+    prim = W.freestream_prim(dim, mach=0.5, angle_deg=30.0)
     G = euler.farfield_ghost(UL, n, prim, GAMMA)
     rb, vb, pb = _prims(G)
     cb = np.sqrt(GAMMA * pb / rb)

@@ -8,7 +8,7 @@ code), so that both the FP64 CPU oracle and the HIP path can consume the
 same inputs without sharing any part of the method.
 """
 
-from .meshes import (MeshArrays, periodic_square, channel_bump, periodic_cube,
+from .meshes import (MeshArrays, periodic_square, channel_bump, periodic_cube, box_cube,
                      stretched_square, BC_SLIP, BC_FARFIELD)
 from .fields import (GAMMA, freestream_prim, prim_to_cons, isentropic_vortex,
                      uniform_state, perturbation, random_directions,
@@ -16,7 +16,7 @@ from .fields import (GAMMA, freestream_prim, prim_to_cons, isentropic_vortex,
 from .configs import CONFIGS, get_config, build_mesh
 
 __all__ = [
-    "MeshArrays", "periodic_square", "channel_bump", "periodic_cube",
+    "MeshArrays", "periodic_square", "channel_bump", "periodic_cube", "box_cube",
     "stretched_square", "BC_SLIP", "BC_FARFIELD", "GAMMA", "freestream_prim",
     "prim_to_cons", "isentropic_vortex", "uniform_state", "perturbation",
     "random_directions", "random_unit_vector", "paper_vortex", "CONFIGS", "get_config", "build_mesh",

@@ -172,6 +172,39 @@ def channel_bump(nx, ny, height=0.1, jitter=0.15, seed=None, x0=-3.0, x1=3.0,
                       meta=dict(nx=nx, ny=ny, height=height, jitter=jitter, seed=seed, top_bc=top_bc))
 
 
+def box_cube(n, length, jitter=0.0, seed=None, name=""):
+    """[0, L]^3 with n^3 cubes, each split into 6 tetrahedra as in
+    :func:`periodic_cube`, without periodic identification.  The faces on
+    x = 0 and x = L are far-field boundaries, those on the other four sides
+    slip walls.  ``jitter`` displaces interior vertices by U(-jitter,
+    jitter) of h in each coordinate."""
+    h = length / n
+    nv1 = n + 1
+    kk, jj, ii = np.meshgrid(np.arange(nv1), np.arange(nv1), np.arange(nv1), indexing="ij")
+    vert = np.stack([ii * h, jj * h, kk * h], axis=-1).reshape(-1, 3).astype(np.float64)
+    if jitter > 0.0:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        interior = ((ii > 0) & (ii < n) & (jj > 0) & (jj < n) & (kk > 0) & (kk < n)).reshape(-1)
+        disp = rng.uniform(-jitter * h, jitter * h, size=vert.shape)
+        vert = np.where(interior[:, None], vert + disp, vert)
+    ref = periodic_cube(n, length)
+    elem = _orient(vert, np.asarray(ref.elem, np.int32)).astype(np.int32)
+    # boundary faces: the element faces whose three vertices lie on one side of the box
+    faces = np.concatenate([elem[:, [1, 2, 3]], elem[:, [0, 2, 3]], elem[:, [0, 1, 3]], elem[:, [0, 1, 2]]])
+    ijk = np.stack([ii, jj, kk], axis=-1).reshape(-1, 3)
+    fi = ijk[faces]                                              # (nF, 3 vertices, 3 axes)
+    bf, tags = [], []
+    for ax in range(3):
+        for side in (0, n):
+            on = np.all(fi[:, :, ax] == side, axis=1)
+            bf.append(faces[on])
+            tags.append(np.full(int(on.sum()), BC_FARFIELD if ax == 0 else BC_SLIP))
+    return MeshArrays(dim=3, vert=vert, elem=elem, vert_canon=None,
+                      bface=np.concatenate(bf).astype(np.int32), bface_tag=np.concatenate(tags).astype(np.int32),
+                      period=np.zeros(3, np.float64),
+                      name=name or f"box_cube_{n}", meta=dict(n=n, length=length, h=h, jitter=jitter, seed=seed))
+
+
 def periodic_cube(n, length, name=""):
     """Periodic [0, L]^3 with n^3 cubes, each split into 6 tetrahedra.
 
