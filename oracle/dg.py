@@ -47,8 +47,7 @@ class DG:
         self.exps = basis.exponents(d, p)
         self.N = len(self.exps)
         self.nE = self.mesh.X.shape[0]
-        self.ref_pts, self.ref_w = quadrature.simplex_rule(d, p + 1)
-        self.mu, self.wf = quadrature.face_rule(d, p + 1)
+        self.ref_pts, self.ref_w, self.mu, self.wf = quadrature.dg_rules(d, p)
         self.Nq = len(self.ref_w)
         self.Nfq = len(self.wf)
         self.chunk = chunk

@@ -3,6 +3,9 @@
 Reading: conical-product (Stroud) Gauss-Jacobi rules with q = p+1 points
 per collapsed direction.  Volume rules are exact to degree 2q-1 = 2p+1
 (>= 2p, so the MGS inner products of Alg. 1 are exact); face rules likewise.
+For p = 2 in 3D the operator uses fully symmetric rules of the same degree
+5 with fewer points instead (:func:`dg_rules`): 14 points on the
+tetrahedron (27 conical) and Radon's 7 points on each triangular face (9).
 
 Reference simplex: vertices 0, e_1, ..., e_d.  In 2D the collapse is
   eta = (1+b)/2,  xi = (1+a)/2 (1-eta),
@@ -56,3 +59,67 @@ def face_rule(dim, q):
     pts, w = simplex_rule(dim - 1, q)
     mu = np.concatenate([1.0 - pts.sum(axis=1, keepdims=True), pts], axis=1)
     return mu, w / w.sum()
+
+
+def radon7():
+    """Radon's 7-point rule on the triangle, exact to degree 5, in barycentric
+    form: the centroid, weight 9/40, and the orbits of (a, a, 1 - 2a) for
+    a = (6 - sqrt 15)/21 and (6 + sqrt 15)/21, weights (155 - sqrt 15)/1200
+    and (155 + sqrt 15)/1200 (fractions of the area).  Order: centroid, then
+    each orbit with 1 - 2a at barycentric index 0, 1, 2."""
+    s = np.sqrt(15.0)
+    bary = [[1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0]]
+    w = [9.0 / 40.0]
+    for a, wa in (((6.0 - s) / 21.0, (155.0 - s) / 1200.0), ((6.0 + s) / 21.0, (155.0 + s) / 1200.0)):
+        for k in range(3):
+            b = [a, a, a]
+            b[k] = 1.0 - 2.0 * a
+            bary.append(b)
+            w.append(wa)
+    return np.array(bary), np.array(w)
+
+
+# 14-point fully symmetric rule on the reference tetrahedron, exact to
+# degree 5 with positive weights: orbit parameters a1, a2 of (a, a, a, 1 - 3a)
+# (4 points each) and b of (b, b, 1/2 - b, 1/2 - b) (6 points), and the
+# weight of one point of each orbit (the weights sum to 1/6).  They solve the
+# moment equations of degree <= 5 (checked on every monomial by the tests).
+TET14_A = (0.0927352503108912, 0.3108859192633006)
+TET14_B = 0.0455037041256496
+TET14_W = (0.01224884051939366, 0.01878132095300264, 0.007091003462846911)
+
+
+def tet14():
+    """The 14-point degree-5 rule in barycentric form (14, 4) and weights
+    summing to 1/6.  Order: the two 4-point orbits, each with 1 - 3a at
+    barycentric index 0..3, then the 6-point orbit with b at the index pairs
+    (i, j), i < j, in lexicographic order."""
+    bary, w = [], []
+    for a, wa in zip(TET14_A, TET14_W[:2]):
+        for k in range(4):
+            b = [a] * 4
+            b[k] = 1.0 - 3.0 * a
+            bary.append(b)
+            w.append(wa)
+    for i in range(4):
+        for j in range(i + 1, 4):
+            b = [0.5 - TET14_B] * 4
+            b[i] = TET14_B
+            b[j] = TET14_B
+            bary.append(b)
+            w.append(TET14_W[2])
+    return np.array(bary), np.array(w)
+
+
+def dg_rules(dim, p):
+    """Volume rule (points on the reference simplex, weights summing to
+    1/dim!) and face rule (barycentric, weights summing to 1) of the DG
+    operator of degree p: the symmetric degree-5 rules for dim = 3, p = 2,
+    else the conical-product rules with p + 1 points per direction."""
+    if dim == 3 and p == 2:
+        bary, w = tet14()
+        mu, wf = radon7()
+        return bary[:, 1:].copy(), w, mu, wf
+    pts, w = simplex_rule(dim, p + 1)
+    mu, wf = face_rule(dim, p + 1)
+    return pts, w, mu, wf

@@ -32,9 +32,13 @@ template <int D, int P>
 struct Shape {
   static constexpr int NV = D + 2;
   static constexpr int NB = D == 2 ? (P + 1) * (P + 2) / 2 : (P + 1) * (P + 2) * (P + 3) / 6;
+  // quadrature points, volume and per face: conical-product rules with P + 1
+  // points per collapsed direction, except 3D P2, which takes symmetric rules
+  // of the same degree 5 (14 points on the tetrahedron, 7 on each face)
   static constexpr int Q1 = P + 1;
-  static constexpr int NQ = D == 2 ? Q1 * Q1 : Q1 * Q1 * Q1;
-  static constexpr int NFQ = D == 2 ? Q1 : Q1 * Q1;
+  static constexpr bool SYM = D == 3 && P == 2;
+  static constexpr int NQ = SYM ? 14 : D == 2 ? Q1 * Q1 : Q1 * Q1 * Q1;
+  static constexpr int NFQ = SYM ? 7 : D == 2 ? Q1 : Q1 * Q1;
   static constexpr int NF = D + 1;
   static constexpr int NORI = D == 2 ? 2 : 6;
   static constexpr int NVB = NV * NB;

@@ -576,6 +576,26 @@ bool dg_run_f(int dim, int p, int flux, int mode, const DGParams<float>& prm, co
 }
 }  // namespace pcexp
 
+// Quadrature sizes (volume, per face) the DG kernels of (dim, p) are built
+// for; the host set-up must generate rules of the same sizes.
+template <int D, int P>
+static void rule_sizes(int* nq, int* nfq) {
+  *nq = Shape<D, P>::NQ;
+  *nfq = Shape<D, P>::NFQ;
+}
+static bool kernel_rule_sizes(int dim, int p, int* nq, int* nfq) {
+  switch (dim * 10 + p) {
+    case 20: rule_sizes<2, 0>(nq, nfq); return true;
+    case 21: rule_sizes<2, 1>(nq, nfq); return true;
+    case 22: rule_sizes<2, 2>(nq, nfq); return true;
+    case 23: rule_sizes<2, 3>(nq, nfq); return true;
+    case 30: rule_sizes<3, 0>(nq, nfq); return true;
+    case 31: rule_sizes<3, 1>(nq, nfq); return true;
+    case 32: rule_sizes<3, 2>(nq, nfq); return true;
+    default: return false;
+  }
+}
+
 extern "C" {
 
 pcexp_status pcexp_create(const pcexp_mesh_desc* mesh, const pcexp_disc_desc* disc, void* stream,
@@ -601,8 +621,12 @@ pcexp_status pcexp_create(const pcexp_mesh_desc* mesh, const pcexp_disc_desc* di
     return s;
   }
   if (S.nb > 20 || S.nv > 5) { delete c; return PCEXP_E_UNSUPPORTED; }
-  for (int64_t e = 0; e < S.nE * S.nf; ++e) {
-    (void)e;
+  {
+    int kq = 0, kfq = 0;
+    if (!kernel_rule_sizes(S.dim, S.p, &kq, &kfq) || kq != S.nq || kfq != S.nfq) {
+      delete c;
+      return PCEXP_E_UNSUPPORTED;
+    }
   }
   bool has_far = false;
   for (int64_t b = 0; b < mesh->n_bface; ++b) has_far |= (mesh->bface_tag[b] == PCEXP_BC_FARFIELD);

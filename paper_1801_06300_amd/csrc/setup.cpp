@@ -156,6 +156,61 @@ void face_rule(int dim, int q, std::vector<double>& mu, std::vector<double>& w) 
   }
 }
 
+// Radon's 7-point triangle rule, exact to degree 5: the centroid (weight
+// 9/40 of the area) and the orbits of the barycentric point (a, a, 1 - 2a)
+// for a = (6 -+ sqrt 15)/21 (weights (155 -+ sqrt 15)/1200).  bary [7][3],
+// weights summing to 1; each orbit lists 1 - 2a at index 0, 1, 2 in turn.
+static void radon7(std::vector<double>& bary, std::vector<double>& w) {
+  const double r15 = std::sqrt(15.0);
+  bary = {1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0};
+  w = {9.0 / 40.0};
+  const double av[2] = {(6.0 - r15) / 21.0, (6.0 + r15) / 21.0};
+  const double wv[2] = {(155.0 - r15) / 1200.0, (155.0 + r15) / 1200.0};
+  for (int o = 0; o < 2; ++o)
+    for (int k = 0; k < 3; ++k) {
+      for (int j = 0; j < 3; ++j) bary.push_back(j == k ? 1.0 - 2.0 * av[o] : av[o]);
+      w.push_back(wv[o]);
+    }
+}
+
+// The 14-point fully symmetric tetrahedron rule, exact to degree 5, with
+// positive weights: two orbits of (a, a, a, 1 - 3a) (4 points each, 1 - 3a at
+// index 0..3) and the orbit of (b, b, 1/2 - b, 1/2 - b) (6 points, b at the
+// index pairs i < j in lexicographic order); the parameters solve the moment
+// equations of degree <= 5.  bary [14][4], weights summing to 1/6.
+static void tet14(std::vector<double>& bary, std::vector<double>& w) {
+  const double av[2] = {0.0927352503108912, 0.3108859192633006};
+  const double wv[3] = {0.01224884051939366, 0.01878132095300264, 0.007091003462846911};
+  const double b = 0.0455037041256496;
+  bary.clear();
+  w.clear();
+  for (int o = 0; o < 2; ++o)
+    for (int k = 0; k < 4; ++k) {
+      for (int j = 0; j < 4; ++j) bary.push_back(j == k ? 1.0 - 3.0 * av[o] : av[o]);
+      w.push_back(wv[o]);
+    }
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j) {
+      for (int k = 0; k < 4; ++k) bary.push_back(k == i || k == j ? b : 0.5 - b);
+      w.push_back(wv[2]);
+    }
+}
+
+void dg_rules(int dim, int p, std::vector<double>& pts, std::vector<double>& w, std::vector<double>& mu,
+              std::vector<double>& wf) {
+  if (dim == 3 && p == 2) {
+    std::vector<double> bary;
+    tet14(bary, w);
+    pts.clear();
+    for (size_t q = 0; q < w.size(); ++q)
+      for (int a = 1; a < 4; ++a) pts.push_back(bary[q * 4 + a]);
+    radon7(mu, wf);
+    return;
+  }
+  simplex_rule(dim, p + 1, pts, w);
+  face_rule(dim, p + 1, mu, wf);
+}
+
 // ---------------------------------------------------------------- bases
 static void monomials(int dim, const std::vector<int>& ex, const double* z, double* val,
                       double* grad /* [N][dim] or null */) {
@@ -408,15 +463,12 @@ std::string build_setup(const MeshIn& m, int p, int tile, Setup& S) {
     }
 
   // ---- reference quadrature and tables
-  const int q = p + 1;
-  std::vector<double> pts, w;
-  simplex_rule(d, q, pts, w);
+  std::vector<double> pts, w, mu, wf;
+  dg_rules(d, p, pts, w, mu, wf);
   S.nq = (int)w.size();
   S.ref_pts = pts;
   S.wq = w;
   ref_basis_eval(d, p, pts, &S.B, &S.Dg);
-  std::vector<double> mu, wf;
-  face_rule(d, q, mu, wf);
   S.nfq = (int)wf.size();
   S.wf = wf;
   S.nref.assign(nf * d, 0.0);

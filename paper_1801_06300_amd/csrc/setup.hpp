@@ -29,6 +29,13 @@ void simplex_rule(int dim, int q, std::vector<double>& pts, std::vector<double>&
 // vertices, weights summing to 1.
 void face_rule(int dim, int q, std::vector<double>& mu, std::vector<double>& w);
 
+// The rules of the DG operator of degree p: the conical-product rules with
+// q = p + 1, except dim = 3, p = 2, which takes the symmetric rules of the
+// same degree 5 with fewer points (14 on the tetrahedron, Radon's 7 on each
+// triangular face).  Volume rule as simplex_rule, face rule as face_rule.
+void dg_rules(int dim, int p, std::vector<double>& pts, std::vector<double>& w, std::vector<double>& mu,
+              std::vector<double>& wf);
+
 struct MeshIn {
   int dim = 0;
   int64_t n_vert = 0, n_elem = 0, n_bface = 0;

@@ -50,6 +50,60 @@ def test_face_rule_exactness(dim, q):
             assert abs(got - want) < 1e-15
 
 
+def _moment_errors(pts, w, deg):
+    """Largest error of the rule over the monomials of each degree <= deg on
+    the reference simplex (closed-form integrals)."""
+    dim = pts.shape[1]
+    errs = []
+    for tot in range(deg + 1):
+        e_tot = 0.0
+        for e in basis.exponents(dim, tot):
+            if sum(e) != tot:
+                continue
+            got = np.sum(w * np.prod(pts ** np.asarray(e)[None, :], axis=1))
+            e_tot = max(e_tot, abs(got - _exact_simplex_monomial(e)))
+        errs.append(e_tot)
+    return errs
+
+
+def test_symmetric_degree5_rules():
+    """Radon's 7-point triangle rule and the 14-point tetrahedron rule: exact
+    on every monomial of degree <= 5 and not on degree 6, positive weights,
+    points strictly inside, and each orbit invariant under the vertex
+    permutations."""
+    bary, w = quadrature.radon7()
+    assert bary.shape == (7, 3) and np.all(w > 0) and np.all(bary > 0)
+    assert np.allclose(bary.sum(axis=1), 1.0, atol=1e-15)
+    errs = _moment_errors(bary[:, 1:], w / 2.0, 6)
+    assert max(errs[:6]) < 1e-16 and errs[6] > 1e-6
+    bary, w = quadrature.tet14()
+    assert bary.shape == (14, 4) and np.all(w > 0) and np.all(bary > 0)
+    assert np.allclose(bary.sum(axis=1), 1.0, atol=1e-15)
+    errs = _moment_errors(bary[:, 1:], w, 6)
+    assert max(errs[:6]) < 2e-16 and errs[6] > 1e-7
+    for perm in ([1, 0, 2, 3], [1, 2, 3, 0]):
+        pb = bary[:, perm]
+        for a in range(14):
+            j = int(np.argmin(np.abs(bary - pb[a]).sum(axis=1)))
+            assert np.abs(bary[j] - pb[a]).max() < 1e-15 and w[j] == w[a]
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (3, 1), (3, 2)])
+def test_dg_rules_degree(dim, p):
+    """The operator's rules integrate degree 2p + 1 exactly (degree 5 for
+    p = 2; the 3D P2 volume rule has 14 points, its face rule 7)."""
+    pts, w, mu, wf = quadrature.dg_rules(dim, p)
+    assert max(_moment_errors(pts, w, 2 * p + 1)) < 1e-15
+    assert abs(wf.sum() - 1.0) < 1e-15 and np.allclose(mu.sum(axis=1), 1.0, atol=1e-15)
+    if dim == 3:
+        ferr = max(_moment_errors(mu[:, 1:], wf / 2.0, 2 * p + 1))
+    else:
+        ferr = max(abs(np.sum(wf * mu[:, 1] ** k) - 1.0 / (k + 1)) for k in range(2 * p + 2))
+    assert ferr < 1e-15
+    if (dim, p) == (3, 2):
+        assert len(w) == 14 and len(wf) == 7
+
+
 # ------------------------------------------------------------------ basis
 def _meshes():
     return [
