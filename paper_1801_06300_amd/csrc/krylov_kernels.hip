@@ -29,21 +29,37 @@ size_t gs_blocks(size_t n) {
 }
 
 // Two consecutive entries per lane: one 16-byte (FP64) or 8-byte (FP32) load.
+// With NTL the load carries the non-temporal hint, which raises the rate of
+// a pass streaming many vectors far larger than the Infinity Cache (3D P2
+// vortex, 133 MB per FP32 vector: reduction and update passes -10 % and
+// -4 %); where the cache serves part of a pass the hint costs more than it
+// gains, so the caller chooses it per pass by the bytes streamed.
 template <typename T> struct Pair;
-template <> struct Pair<double> { using type = double2; };
-template <> struct Pair<float> { using type = float2; };
-template <typename T>
+template <> struct Pair<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct Pair<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <typename T, bool NTL>
+__device__ __forceinline__ typename Pair<T>::type ld_pair(const T* base, size_t p) {
+  const typename Pair<T>::type* q = reinterpret_cast<const typename Pair<T>::type*>(base) + p;
+  if constexpr (NTL) return __builtin_nontemporal_load(q);
+  else return *q;
+}
+template <typename T, bool NTL>
+__device__ __forceinline__ T ld_one(const T* base, size_t p) {
+  if constexpr (NTL) return __builtin_nontemporal_load(base + p);
+  else return base[p];
+}
+template <typename T, bool NTL = false>
 __device__ __forceinline__ void load_pair(const T* base, size_t p, size_t n, double& a, double& b) {
-  const typename Pair<T>::type v = reinterpret_cast<const typename Pair<T>::type*>(base)[p];
-  a = (double)v.x;
-  b = (2 * p + 1 < n) ? (double)v.y : 0.0;   // the slot stride is even, so the load stays in the slot
+  const typename Pair<T>::type v = ld_pair<T, NTL>(base, p);
+  a = (double)v[0];
+  b = (2 * p + 1 < n) ? (double)v[1] : 0.0;   // the slot stride is even, so the load stays in the slot
 }
 template <typename T>
 __device__ __forceinline__ void store_pair(T* base, size_t p, size_t n, double a, double b) {
   if (2 * p + 1 < n) {
     typename Pair<T>::type v;
-    v.x = (T)a;
-    v.y = (T)b;
+    v[0] = (T)a;
+    v[1] = (T)b;
     reinterpret_cast<typename Pair<T>::type*>(base)[p] = v;
   } else {
     base[2 * p] = (T)a;
@@ -231,26 +247,26 @@ constexpr int pow2_ceil(int x) { return x <= 4 ? 4 : 2 * pow2_ceil((x + 1) / 2);
 // vectors are split over blockIdx.y (each chunk re-reads U and W).
 constexpr int CHUNK = 32;
 
-template <typename TV, int PW>
+template <typename TV, int PW, bool NTL = false>
 __device__ __forceinline__ void load_pw(const TV* base, size_t p, size_t n, double* x) {
-  if (PW == 2) load_pair(base, p, n, x[0], x[1]);
-  else x[0] = (double)base[p];
+  if (PW == 2) load_pair<TV, NTL>(base, p, n, x[0], x[1]);
+  else x[0] = (double)ld_one<TV, NTL>(base, p);
 }
 // Unmasked variant for passes that write back what they read: past the end
 // of the vector the second entry holds whatever the slot's padding holds,
 // and store_pair never writes it.
-template <typename TV, int PW>
+template <typename TV, int PW, bool NTL = false>
 __device__ __forceinline__ void load_pw_raw(const TV* base, size_t p, double* x) {
   if (PW == 2) {
-    const typename Pair<TV>::type v = reinterpret_cast<const typename Pair<TV>::type*>(base)[p];
-    x[0] = (double)v.x;
-    x[1] = (double)v.y;
+    const typename Pair<TV>::type v = ld_pair<TV, NTL>(base, p);
+    x[0] = (double)v[0];
+    x[1] = (double)v[1];
   } else {
-    x[0] = (double)base[p];
+    x[0] = (double)ld_one<TV, NTL>(base, p);
   }
 }
 
-template <typename TV, int NV, int PW, bool CLOSE>
+template <typename TV, int NV, int PW, bool CLOSE, bool NTL>
 __global__ __launch_bounds__(RT) void dcgs_reduce(const TV* __restrict__ V, size_t ld, int j, size_t n,
                                                   const KState* ks, double* part) {
   if (ks->done) return;
@@ -270,10 +286,10 @@ __global__ __launch_bounds__(RT) void dcgs_reduce(const TV* __restrict__ V, size
   const size_t np = PW == 2 ? (n + 1) / 2 : n;
   for (size_t p = (size_t)blockIdx.x * RT + threadIdx.x; p < np; p += (size_t)gridDim.x * RT) {
     double u[PW], w[PW], v[NV][PW];
-    load_pw<TV, PW>(U, p, n, u);
-    if (!CLOSE) load_pw<TV, PW>(W, p, n, w);
+    load_pw<TV, PW, NTL>(U, p, n, u);
+    if (!CLOSE) load_pw<TV, PW, NTL>(W, p, n, w);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) load_pw<TV, PW>(V + (size_t)clampv(i0 + i, nq) * ld, p, n, v[i]);
+    for (int i = 0; i < NV; ++i) load_pw<TV, PW, NTL>(V + (size_t)clampv(i0 + i, nq) * ld, p, n, v[i]);
 #pragma unroll
     for (int k = 0; k < PW; ++k) {
 #pragma unroll
@@ -331,7 +347,7 @@ __global__ __launch_bounds__(RT) void dcgs_reduce(const TV* __restrict__ V, size
 // Every block computes the same algebra (same inputs, same order); block 0
 // publishes H, the scales and the stop flags, into locations no block of this
 // launch reads.
-template <typename TV, int NV, int PW, int CV, int NR>
+template <typename TV, int NV, int PW, int CV, int NR, bool NTL>
 __global__ __launch_bounds__(RT) void dcgs_fin_update(TV* __restrict__ V, size_t ld, int j, size_t n, KState* ks,
                                                       const double* part, int nblk) {
   if (ks->done_at < j) return;
@@ -380,10 +396,10 @@ __global__ __launch_bounds__(RT) void dcgs_fin_update(TV* __restrict__ V, size_t
   const size_t pc = p0 < np ? p0 : np - 1;
   double pv[PREFETCH ? NV : 1][PW], pu[PW], pw[PW];
   if (PREFETCH) {
-    load_pw_raw<TV, PW>(U, pc, pu);
-    load_pw_raw<TV, PW>(W, pc, pw);
+    load_pw_raw<TV, PW, NTL>(U, pc, pu);
+    load_pw_raw<TV, PW, NTL>(W, pc, pw);
 #pragma unroll
-    for (int i = 0; i < (PREFETCH ? NV : 1); ++i) load_pw_raw<TV, PW>(V + (size_t)clampv(i, nq) * ld, pc, pv[i]);
+    for (int i = 0; i < (PREFETCH ? NV : 1); ++i) load_pw_raw<TV, PW, NTL>(V + (size_t)clampv(i, nq) * ld, pc, pv[i]);
   }
   __builtin_amdgcn_sched_barrier(0);   // keep both groups of loads ahead of the first use
 
@@ -540,8 +556,8 @@ __global__ __launch_bounds__(RT) void dcgs_fin_update(TV* __restrict__ V, size_t
   }
   for (size_t p = p0 + (PREFETCH ? stride : 0); p < np; p += stride) {
     double u[PW], w[PW], un[PW], wn[PW];
-    load_pw_raw<TV, PW>(U, p, u);
-    load_pw_raw<TV, PW>(W, p, w);
+    load_pw_raw<TV, PW, NTL>(U, p, u);
+    load_pw_raw<TV, PW, NTL>(W, p, w);
 #pragma unroll
     for (int k = 0; k < PW; ++k) {
       un[k] = u[k];
@@ -552,7 +568,7 @@ __global__ __launch_bounds__(RT) void dcgs_fin_update(TV* __restrict__ V, size_t
       if (CV < NV && c0 >= nq) break;
       double v[CV][PW];
 #pragma unroll
-      for (int i = 0; i < CV; ++i) load_pw_raw<TV, PW>(V + (size_t)clampv(c0 + i, nq) * ld, p, v[i]);
+      for (int i = 0; i < CV; ++i) load_pw_raw<TV, PW, NTL>(V + (size_t)clampv(c0 + i, nq) * ld, p, v[i]);
 #pragma unroll
       for (int i = 0; i < CV; ++i) {
         const double ei = e[c0 + i], bi = b[c0 + i];
@@ -601,26 +617,26 @@ static int red_blocks(size_t n, int nq) {
 
 // Smallest vector-count bucket that holds nq (>= 1) vectors; two entries per
 // lane while the registers allow it.
-template <typename TV, bool CLOSE>
+template <typename TV, bool CLOSE, bool NTL>
 static void launch_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, double* part, hipStream_t st) {
   const int nq = j > 0 ? j : 1;
   const dim3 b(RT);
   const unsigned nb = (unsigned)red_blocks(n, nq);
-  if (nq <= 4) launch((dcgs_reduce<TV, 4, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
-  else if (nq <= 8) launch((dcgs_reduce<TV, 8, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
-  else if (nq <= 12) launch((dcgs_reduce<TV, 12, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
-  else if (nq <= 16) launch((dcgs_reduce<TV, 16, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
-  else if (nq <= 20) launch((dcgs_reduce<TV, 20, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
-  else if (nq <= 24) launch((dcgs_reduce<TV, 24, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
-  else if (nq <= 28) launch((dcgs_reduce<TV, 28, 2, CLOSE>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  if (nq <= 4) launch((dcgs_reduce<TV, 4, 2, CLOSE, NTL>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 8) launch((dcgs_reduce<TV, 8, 2, CLOSE, NTL>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 12) launch((dcgs_reduce<TV, 12, 2, CLOSE, NTL>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 16) launch((dcgs_reduce<TV, 16, 2, CLOSE, NTL>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 20) launch((dcgs_reduce<TV, 20, 2, CLOSE, NTL>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 24) launch((dcgs_reduce<TV, 24, 2, CLOSE, NTL>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
+  else if (nq <= 28) launch((dcgs_reduce<TV, 28, 2, CLOSE, NTL>), dim3(nb), b, 0, st, V, ld, j, n, ks, part);
   else {
     // the closing pass forms V.U only, so its registers hold two entries per lane
     const unsigned nc = (unsigned)((nq + CHUNK - 1) / CHUNK);
-    launch((dcgs_reduce<TV, CHUNK, CLOSE ? 2 : 1, CLOSE>), dim3(nb, nc), b, 0, st, V, ld, j, n, ks, part);
+    launch((dcgs_reduce<TV, CHUNK, CLOSE ? 2 : 1, CLOSE, NTL>), dim3(nb, nc), b, 0, st, V, ld, j, n, ks, part);
   }
 }
 
-template <typename TV, int NR>
+template <typename TV, int NR, bool NTL>
 static void launch_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, int nb,
                           hipStream_t st) {
   const int nq = j > 0 ? j : 1;
@@ -630,34 +646,44 @@ static void launch_update(TV* V, size_t ld, int j, size_t n, KState* ks, const d
   // 4 vectors gain nothing more).
   const unsigned mult = (NR == 1 && nq <= 12) ? 2u : 1u;
   const dim3 g(mult * (unsigned)gs_blocks(n)), b(RT);
-  if (nq <= 4) launch((dcgs_fin_update<TV, 4, 2, 4, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
-  else if (nq <= 8) launch((dcgs_fin_update<TV, 8, 2, 8, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
-  else if (nq <= 12) launch((dcgs_fin_update<TV, 12, 2, 12, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
-  else if (nq <= 16) launch((dcgs_fin_update<TV, 16, 2, 16, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
-  else if (nq <= 20) launch((dcgs_fin_update<TV, 20, 2, 20, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
-  else if (nq <= 24) launch((dcgs_fin_update<TV, 24, 2, 24, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  if (nq <= 4) launch((dcgs_fin_update<TV, 4, 2, 4, NR, NTL>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 8) launch((dcgs_fin_update<TV, 8, 2, 8, NR, NTL>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 12) launch((dcgs_fin_update<TV, 12, 2, 12, NR, NTL>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 16) launch((dcgs_fin_update<TV, 16, 2, 16, NR, NTL>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 20) launch((dcgs_fin_update<TV, 20, 2, 20, NR, NTL>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 24) launch((dcgs_fin_update<TV, 24, 2, 24, NR, NTL>), g, b, 0, st, V, ld, j, n, ks, part, nb);
   else if (nq <= 28) {
     constexpr int PW = sizeof(TV) == 8 ? 2 : 1;   // FP32 pairs would spill here
-    launch((dcgs_fin_update<TV, 28, PW, 28, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+    launch((dcgs_fin_update<TV, 28, PW, 28, NR, NTL>), g, b, 0, st, V, ld, j, n, ks, part, nb);
   }
-  else if (nq <= 32) launch((dcgs_fin_update<TV, 32, 1, 32, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
-  else launch((dcgs_fin_update<TV, KMAX, 1, 16, NR>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else if (nq <= 32) launch((dcgs_fin_update<TV, 32, 1, 32, NR, NTL>), g, b, 0, st, V, ld, j, n, ks, part, nb);
+  else launch((dcgs_fin_update<TV, KMAX, 1, 16, NR, NTL>), g, b, 0, st, V, ld, j, n, ks, part, nb);
 }
 
 template <typename TV>
-void k_gs_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, double* part, bool close, hipStream_t st) {
-  if (close) launch_reduce<TV, true>(V, ld, j, n, ks, part, st);
-  else launch_reduce<TV, false>(V, ld, j, n, ks, part, st);
+void k_gs_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, double* part, bool close, hipStream_t st,
+                 bool nt) {
+  if (nt) {
+    if (close) launch_reduce<TV, true, true>(V, ld, j, n, ks, part, st);
+    else launch_reduce<TV, false, true>(V, ld, j, n, ks, part, st);
+  } else {
+    if (close) launch_reduce<TV, true, false>(V, ld, j, n, ks, part, st);
+    else launch_reduce<TV, false, false>(V, ld, j, n, ks, part, st);
+  }
 }
 
 template <typename TV>
-void k_gs_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st) {
-  launch_update<TV, CS_PER>(V, ld, j, n, ks, part, red_blocks(n, j > 0 ? j : 1), st);
+void k_gs_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st, bool nt) {
+  const int nb = red_blocks(n, j > 0 ? j : 1);
+  if (nt) launch_update<TV, CS_PER, true>(V, ld, j, n, ks, part, nb, st);
+  else launch_update<TV, CS_PER, false>(V, ld, j, n, ks, part, nb, st);
 }
 
 template <typename TV>
-void k_gs_update_one(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st) {
-  launch_update<TV, 1>(V, ld, j, n, ks, part, 1, st);
+void k_gs_update_one(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st,
+                     bool nt) {
+  if (nt) launch_update<TV, 1, true>(V, ld, j, n, ks, part, 1, st);
+  else launch_update<TV, 1, false>(V, ld, j, n, ks, part, 1, st);
 }
 
 // Column c < ncol of fp (nblk partials at stride pld) summed in a fixed order
@@ -1501,12 +1527,12 @@ void k_gemv_t(const double* A, const double* v, double* out, int n, hipStream_t 
 
 template void k_start<double>(const double*, double*, size_t, KState*, double*, hipStream_t);
 template void k_start<float>(const double*, float*, size_t, KState*, double*, hipStream_t);
-template void k_gs_reduce<double>(const double*, size_t, int, size_t, KState*, double*, bool, hipStream_t);
-template void k_gs_reduce<float>(const float*, size_t, int, size_t, KState*, double*, bool, hipStream_t);
-template void k_gs_update<double>(double*, size_t, int, size_t, KState*, const double*, hipStream_t);
-template void k_gs_update<float>(float*, size_t, int, size_t, KState*, const double*, hipStream_t);
-template void k_gs_update_one<double>(double*, size_t, int, size_t, KState*, const double*, hipStream_t);
-template void k_gs_update_one<float>(float*, size_t, int, size_t, KState*, const double*, hipStream_t);
+template void k_gs_reduce<double>(const double*, size_t, int, size_t, KState*, double*, bool, hipStream_t, bool);
+template void k_gs_reduce<float>(const float*, size_t, int, size_t, KState*, double*, bool, hipStream_t, bool);
+template void k_gs_update<double>(double*, size_t, int, size_t, KState*, const double*, hipStream_t, bool);
+template void k_gs_update<float>(float*, size_t, int, size_t, KState*, const double*, hipStream_t, bool);
+template void k_gs_update_one<double>(double*, size_t, int, size_t, KState*, const double*, hipStream_t, bool);
+template void k_gs_update_one<float>(float*, size_t, int, size_t, KState*, const double*, hipStream_t, bool);
 template void k_combine<double, double>(const double*, size_t, const KState*, const double*, double*, double*,
                                         double, const double*, size_t, hipStream_t);
 template void k_combine<float, float>(const float*, size_t, const KState*, const double*, double*, float*,

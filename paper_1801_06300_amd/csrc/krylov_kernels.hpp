@@ -76,13 +76,18 @@ void k_start(const double* b, TV* V0, size_t n, KState* ks, double* part, hipStr
 // iteration (every block recomputes the small algebra from the partials,
 // block 0 publishes it) and rewrites V_j and V_{j+1}.  After the last
 // iteration, reduce with close = true and k_gs_close complete column m-1 of H.
+// nt: read the basis with non-temporal loads (for a basis larger than the
+// Infinity Cache).
 template <typename TV>
-void k_gs_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, double* part, bool close, hipStream_t st);
+void k_gs_reduce(const TV* V, size_t ld, int j, size_t n, KState* ks, double* part, bool close, hipStream_t st,
+                 bool nt = false);
 template <typename TV>
-void k_gs_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st);
+void k_gs_update(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st,
+                 bool nt = false);
 // The same pass when the reduction left one partial per column (part[c * 512]).
 template <typename TV>
-void k_gs_update_one(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st);
+void k_gs_update_one(TV* V, size_t ld, int j, size_t n, KState* ks, const double* part, hipStream_t st,
+                     bool nt = false);
 // Fixed-order sums of columns [0, ncol) of fp (nblk partials each, stride pld)
 // into part[c * 512]; a no-op once ks->done is set.
 void k_gs_colsum(const double* fp, int pld, int nblk, int ncol, const KState* ks, double* part, hipStream_t st);

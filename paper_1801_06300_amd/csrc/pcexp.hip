@@ -265,6 +265,17 @@ bool fuse_gs(const pcexp_ctx* c, int jvp, int prec) {
   return !c->dense && jvp != PCEXP_JVP_ZERO && c->Kint < ((size_t)1 << 31) &&
          jvp_tiles(c, jvp, prec) <= kFuseMaxTiles;
 }
+// A Gram-Schmidt pass over nvec basis vectors reads them with non-temporal
+// loads when they exceed twice the 256 MB Infinity Cache, which then keeps
+// nothing of them for the next pass.  Measured: the 3D P2 vortex (133 MB
+// per FP32 vector) step -4 %; with the hint on every pass, the 384 x 128
+// channel (9.4 MB per FP32 vector, 31 vectors) lost 9 % per mixed-precision
+// iteration and the 128 x 128 vortex (6.3 MB per FP64 vector) 11 % per
+// step, whose passes the cache serves in part.
+constexpr size_t kMallBytes = (size_t)256 << 20;
+bool basis_streams(const pcexp_ctx* c, int nvec, size_t word) {
+  return (size_t)nvec * c->Kld * word > 2 * kMallBytes;
+}
 // Partials region: the Gram-Schmidt passes' columns (3 * 512 * (KMAX + 2)
 // doubles), then room for the fused reduction's 2m + 3 columns of one partial
 // per tile (at most kFuseMaxTiles).
@@ -359,19 +370,20 @@ void arnoldi_run(pcexp_ctx* c, int jvp, int prec, const double* u_lin, const flo
   double* fpart = part + kPartStd;
   for (int j = 0; j < m; ++j) {
     const double vb = (double)c->K * sizeof(TV);
+    const bool nt = basis_streams(c, j + 2, sizeof(TV));
     if (fuse) {
       // JVP + reduction in one launch (it reads V_0..V_{j-1} besides its operands),
       // then the column sums of its per-tile partials
       jvp_int(c, jvp, prec, u_lin, u32, V + (size_t)j * ld, V + (size_t)(j + 1) * ld, &ks->sig_t[j], &ks->done,
               Rlin, &ks->fd_eps, st, V, j, fpart, fpld);
       { Prof pr(c, st, PC_GSR, (2.0 * j + 3.0) * fpld * 8.0); k_gs_colsum(fpart, fpld, fpld, 2 * j + 3, ks, part, st); }
-      { Prof pr(c, st, PC_GSU, (j + 4.0) * vb); k_gs_update_one<TV>(V, ld, j, n, ks, part, st); }
+      { Prof pr(c, st, PC_GSU, (j + 4.0) * vb); k_gs_update_one<TV>(V, ld, j, n, ks, part, st, nt); }
     } else {
       jvp_int(c, jvp, prec, u_lin, u32, V + (size_t)j * ld, V + (size_t)(j + 1) * ld, &ks->sig_t[j], &ks->done,
               Rlin, &ks->fd_eps, st);
       // the reduction pass reads j + 2 vectors; the finalise-and-update pass reads j + 2 and writes 2
-      { Prof pr(c, st, PC_GSR, (j + 2.0) * vb); k_gs_reduce<TV>(V, ld, j, n, ks, part, false, st); }
-      { Prof pr(c, st, PC_GSU, (j + 4.0) * vb); k_gs_update<TV>(V, ld, j, n, ks, part, st); }
+      { Prof pr(c, st, PC_GSR, (j + 2.0) * vb); k_gs_reduce<TV>(V, ld, j, n, ks, part, false, st, nt); }
+      { Prof pr(c, st, PC_GSU, (j + 4.0) * vb); k_gs_update<TV>(V, ld, j, n, ks, part, st, nt); }
     }
     // adaptive dimension: H_j is final now; stop at m_eff = j if its estimate meets tol
     if (tol > 0.0 && check_every > 0 && k == 1 && j >= 1 && j % check_every == 0) {
@@ -381,7 +393,7 @@ void arnoldi_run(pcexp_ctx* c, int jvp, int prec, const double* u_lin, const flo
   }
   {
     Prof pr(c, st, PC_GSR, (m + 1.0) * (double)c->K * sizeof(TV));
-    k_gs_reduce<TV>(V, ld, m, n, ks, part, true, st);
+    k_gs_reduce<TV>(V, ld, m, n, ks, part, true, st, basis_streams(c, m + 1, sizeof(TV)));
   }
   { Prof pr(c, st, PC_GSF, 0.0); k_gs_close(ks, part, m, n, st); }
   {
