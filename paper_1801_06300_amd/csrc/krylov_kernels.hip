@@ -54,16 +54,27 @@ __device__ __forceinline__ void load_pair(const T* base, size_t p, size_t n, dou
   a = (double)v[0];
   b = (2 * p + 1 < n) ? (double)v[1] : 0.0;   // the slot stride is even, so the load stays in the slot
 }
-template <typename T>
+
+// Stores of the update pass, with the non-temporal hint under NTL (3D P2
+// vortex: update passes a further -2 %).
+template <typename T, bool NTL>
 __device__ __forceinline__ void store_pair(T* base, size_t p, size_t n, double a, double b) {
   if (2 * p + 1 < n) {
     typename Pair<T>::type v;
     v[0] = (T)a;
     v[1] = (T)b;
-    reinterpret_cast<typename Pair<T>::type*>(base)[p] = v;
+    typename Pair<T>::type* q = reinterpret_cast<typename Pair<T>::type*>(base) + p;
+    if constexpr (NTL) __builtin_nontemporal_store(v, q);
+    else *q = v;
   } else {
-    base[2 * p] = (T)a;
+    if constexpr (NTL) __builtin_nontemporal_store((T)a, base + 2 * p);
+    else base[2 * p] = (T)a;
   }
+}
+template <typename T, bool NTL>
+__device__ __forceinline__ void store_one(T* base, size_t p, double a) {
+  if constexpr (NTL) __builtin_nontemporal_store((T)a, base + p);
+  else base[p] = (T)a;
 }
 
 __device__ __forceinline__ double wave_sum(double a) {
@@ -547,11 +558,11 @@ __global__ __launch_bounds__(RT) void dcgs_fin_update(TV* __restrict__ V, size_t
       }
     }
     if (PW == 2) {
-      store_pair(U, p0, n, un[0], un[1]);
-      store_pair(W, p0, n, wn[0], wn[1]);
+      store_pair<TV, NTL>(U, p0, n, un[0], un[1]);
+      store_pair<TV, NTL>(W, p0, n, wn[0], wn[1]);
     } else {
-      U[p0] = (TV)un[0];
-      W[p0] = (TV)wn[0];
+      store_one<TV, NTL>(U, p0, un[0]);
+      store_one<TV, NTL>(W, p0, wn[0]);
     }
   }
   for (size_t p = p0 + (PREFETCH ? stride : 0); p < np; p += stride) {
@@ -580,11 +591,11 @@ __global__ __launch_bounds__(RT) void dcgs_fin_update(TV* __restrict__ V, size_t
       }
     }
     if (PW == 2) {
-      store_pair(U, p, n, un[0], un[1]);
-      store_pair(W, p, n, wn[0], wn[1]);
+      store_pair<TV, NTL>(U, p, n, un[0], un[1]);
+      store_pair<TV, NTL>(W, p, n, wn[0], wn[1]);
     } else {
-      U[p] = (TV)un[0];
-      W[p] = (TV)wn[0];
+      store_one<TV, NTL>(U, p, un[0]);
+      store_one<TV, NTL>(W, p, wn[0]);
     }
   }
 }
