@@ -123,6 +123,23 @@ def test_vjp_parity(name, p, flux):
     assert abs(lhs - rhs) < 1e-12 * max(np.linalg.norm(w) * np.linalg.norm(Jv), 1.0)
 
 
+@pytest.mark.parametrize("name,p,flux", [("cube3", 2, "lf"), ("box3", 2, "roe")])
+def test_vjp_parity_sampled_3d_p2(name, p, flux):
+    """J^T w on the 3D P2 meshes (8100 unknowns, where a dense oracle Jacobian
+    takes minutes) against the oracle through the adjoint identity on six
+    seeded directions: <J^T w, v_k> = <w, J v_k>, with J v_k the oracle's
+    complex-step JVP (exact to rounding), at 1e-11 of |J^T w| |v_k|."""
+    g, ctx, u = _pair(name, p, flux, amp=1e-3)
+    w = W.random_unit_vector(u.shape, 10)
+    JTw = _n(ctx.vjp(_t(u), _t(w)))
+    scale = np.linalg.norm(JTw)
+    for seed in range(30, 36):
+        v = W.random_unit_vector(u.shape, seed)
+        want = float(np.sum(w * jvp_cs(g, u, v)))
+        got = float(np.sum(JTw * v))
+        assert abs(got - want) < 1e-11 * scale * np.linalg.norm(v), (seed, got, want)
+
+
 @pytest.mark.parametrize("k", [0, 1, 2])
 @pytest.mark.parametrize("jvp", ["tangent", "fd"])
 def test_arnoldi_phi_parity(k, jvp):
