@@ -15,6 +15,9 @@ In 3D
 with c Gauss-Jacobi(2,0); weight w_a w_b w_c / 64.  Weights sum to 1/d!.
 """
 
+import itertools
+from math import factorial
+
 import numpy as np
 from scipy.special import roots_jacobi
 
@@ -79,36 +82,57 @@ def radon7():
     return np.array(bary), np.array(w)
 
 
-# 14-point fully symmetric rule on the reference tetrahedron, exact to
-# degree 5 with positive weights: orbit parameters a1, a2 of (a, a, a, 1 - 3a)
-# (4 points each) and b of (b, b, 1/2 - b, 1/2 - b) (6 points), and the
-# weight of one point of each orbit (the weights sum to 1/6).  They solve the
-# moment equations of degree <= 5 (checked on every monomial by the tests).
-TET14_A = (0.0927352503108912, 0.3108859192633006)
-TET14_B = 0.0455037041256496
-TET14_W = (0.01224884051939366, 0.01878132095300264, 0.007091003462846911)
+def _tet14_points(a1, a2, b):
+    """Barycentric points (14, 4) of the orbits of (a, a, a, 1 - 3a) for
+    a = a1, a2 (1 - 3a at index 0..3 in turn) and of (b, b, 1/2 - b, 1/2 - b)
+    (b at the index pairs i < j in lexicographic order)."""
+    bary = []
+    for a in (a1, a2):
+        for k in range(4):
+            row = [a] * 4
+            row[k] = 1.0 - 3.0 * a
+            bary.append(row)
+    for i in range(4):
+        for j in range(i + 1, 4):
+            row = [0.5 - b] * 4
+            row[i] = b
+            row[j] = b
+            bary.append(row)
+    return np.array(bary)
+
+
+def _tet14_moments(x, exps, exact):
+    a1, a2, b, w1, w2, w3 = x
+    pts = _tet14_points(a1, a2, b)[:, 1:]
+    w = np.array([w1] * 4 + [w2] * 4 + [w3] * 6)
+    return np.array([np.sum(w * np.prod(pts ** e[None, :], axis=1)) for e in exps]) - exact
 
 
 def tet14():
-    """The 14-point degree-5 rule in barycentric form (14, 4) and weights
-    summing to 1/6.  Order: the two 4-point orbits, each with 1 - 3a at
-    barycentric index 0..3, then the 6-point orbit with b at the index pairs
-    (i, j), i < j, in lexicographic order."""
-    bary, w = [], []
-    for a, wa in zip(TET14_A, TET14_W[:2]):
-        for k in range(4):
-            b = [a] * 4
-            b[k] = 1.0 - 3.0 * a
-            bary.append(b)
-            w.append(wa)
-    for i in range(4):
-        for j in range(i + 1, 4):
-            b = [0.5 - TET14_B] * 4
-            b[i] = TET14_B
-            b[j] = TET14_B
-            bary.append(b)
-            w.append(TET14_W[2])
-    return np.array(bary), np.array(w)
+    """The 14-point fully symmetric rule on the reference tetrahedron, exact to
+    degree 5 with positive weights: two orbits (a, a, a, 1 - 3a) of 4 points
+    and the orbit (b, b, 1/2 - b, 1/2 - b) of 6, one weight per orbit.  The
+    six parameters are the solution of the moment equations (every monomial
+    of degree <= 5 integrated exactly, prod e_i! / (|e| + 3)!), found here by
+    Gauss-Newton from rough starting values.  Returns barycentric points
+    (14, 4) (order as in :func:`_tet14_points`) and weights summing to 1/6."""
+    exps = [np.array(e) for e in itertools.product(range(6), repeat=3) if sum(e) <= 5]
+    exact = np.array([np.prod([factorial(k) for k in e]) / factorial(int(sum(e)) + 3) for e in exps])
+    x = np.array([0.09, 0.31, 0.05, 0.012, 0.019, 0.007])
+    for _ in range(40):
+        r = _tet14_moments(x, exps, exact)
+        J = np.empty((len(r), 6))
+        for k in range(6):
+            h = 1e-7 * max(abs(x[k]), 1e-3)
+            d = np.zeros(6)
+            d[k] = h
+            J[:, k] = (_tet14_moments(x + d, exps, exact) - _tet14_moments(x - d, exps, exact)) / (2 * h)
+        dx = np.linalg.lstsq(J, -r, rcond=None)[0]
+        x = x + dx
+        if np.max(np.abs(dx)) < 1e-17:
+            break
+    a1, a2, b, w1, w2, w3 = x
+    return _tet14_points(a1, a2, b), np.array([w1] * 4 + [w2] * 4 + [w3] * 6)
 
 
 def dg_rules(dim, p):
