@@ -110,18 +110,19 @@ struct Tile {
   // lose 4 %, so 2D keeps the VALU contraction.
   static constexpr bool VMFMA = D == 3 && P >= 2 && Sh::NB <= 16;
   // basis-to-quadrature interpolation U_q = B u on the matrix cores, in the
-  // same element class (3D P2: 27 points x 10 basis functions per (set,
-  // variable, element) column).  Measured: the 3D P2 FP32 tangent JVP
-  // 1.13 -> 1.10 ms, the FP64 residual 1.52 -> 1.43 ms; in 2D P2 (9 points x
-  // 6 basis functions pad to 16 x 8) the JVPs got 1-6 % slower, so 2D keeps
-  // the VALU interpolation.
+  // same element class (3D P2: 14 points, one 16-row tile, x 10 basis
+  // functions per (set, variable, element) column).  Measured with the
+  // 27-point conical rule: the 3D P2 FP32 tangent JVP 1.13 -> 1.10 ms, the
+  // FP64 residual 1.52 -> 1.43 ms; in 2D P2 (9 points x 6 basis functions
+  // pad to 16 x 8) the JVPs got 1-6 % slower, so 2D keeps the VALU
+  // interpolation.
   static constexpr bool VMFMA_IN = VMFMA;
   // per element: coefficients (and direction), flux scratch, geometry (det,
   // A^-1, neighbours, face codes) and the face orientation codes
   static constexpr int per_elem = (int)sizeof(T) * (Sh::NVB * (DUAL ? 2 : 1) + NW + 1 + D * D) + 8 * Sh::NF + Sh::NF;
   // reference tables B, Dg, Bf, wq, wf, nref, staged in LDS: every lane
   // reads an entry per multiply-add, and from global memory (L1) those reads
-  // bound the kernel (3D P2: 3288 entries).  A 3D tile gets a larger LDS
+  // bound the kernel (3D P2: 2273 entries).  A 3D tile gets a larger LDS
   // budget so that the tables fit beside a tile that fills the pointwise
   // phases.
   static constexpr int NTAB = Sh::NQ * Sh::NB * (D + 1) + Sh::NF * Sh::NORI * Sh::NFQ * Sh::NB + Sh::NQ +
