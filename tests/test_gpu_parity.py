@@ -49,7 +49,7 @@ def _n(t):
 
 CASES = [("sq3", 1, "lf"), ("sq4j", 2, "roe"), ("sq4j", 3, "lf"), ("sq3", 0, "roe"),
          ("cube3", 1, "lf"), ("cube3", 2, "roe"), ("chan", 2, "roe"), ("chan", 1, "lf"),
-         ("box3", 1, "roe"), ("box3", 2, "lf")]
+         ("box3", 1, "roe"), ("box3", 2, "lf"), ("cube3", 0, "lf"), ("box3", 0, "roe")]
 
 
 @pytest.mark.parametrize("name,p,flux", CASES)
@@ -110,7 +110,8 @@ def test_mixed_jvp_bound(name, p, flux):
 
 
 @pytest.mark.parametrize("name,p,flux", [("sq3", 1, "roe"), ("sq3", 2, "lf"), ("cube3", 1, "roe"),
-                                         ("chan", 1, "roe"), ("box3", 1, "lf")])
+                                         ("chan", 1, "roe"), ("box3", 1, "lf"), ("sq3", 0, "lf"),
+                                         ("sq3", 3, "roe"), ("cube3", 0, "roe")])
 def test_vjp_parity(name, p, flux):
     g, ctx, u = _pair(name, p, flux, amp=1e-3)
     w = W.random_unit_vector(u.shape, 10)
