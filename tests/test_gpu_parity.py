@@ -87,7 +87,8 @@ def test_tangent_jvp_parity(name, p, flux):
     assert rel(Jv, jvp_cs(g, u, v)) < 1e-11
 
 
-@pytest.mark.parametrize("name,p,flux", [("sq4j", 2, "roe"), ("cube3", 1, "lf"), ("chan", 2, "roe")])
+@pytest.mark.parametrize("name,p,flux", [("sq4j", 2, "roe"), ("cube3", 1, "lf"), ("chan", 2, "roe"),
+                                         ("cube3", 2, "lf"), ("box3", 2, "roe")])
 def test_fd_jvp_parity(name, p, flux):
     """FD JVP against the oracle's FD JVP (same eps formula).  The two residual
     evaluations differ by a few ulps of R, amplified by 1/eps:
@@ -409,9 +410,24 @@ def test_step_conservation_and_determinism():
     assert np.max(np.abs(q1 - q0) / np.abs(q0).max()) < 1e-13
 
 
-def test_stable_dt_parity():
-    g, ctx, u = _pair("sq4j", 2, "roe")
+@pytest.mark.parametrize("name,p,flux", [("sq4j", 2, "roe"), ("cube3", 2, "lf"), ("box3", 1, "roe")])
+def test_stable_dt_parity(name, p, flux):
+    g, ctx, u = _pair(name, p, flux)
     assert abs(ctx.stable_dt(_t(u), 3.0) - stable_dt(g, u, 3.0)) < 1e-14 * stable_dt(g, u, 3.0)
+
+
+@pytest.mark.parametrize("name,p,flux", [("cube3", 2, "lf"), ("box3", 2, "roe"), ("box3", 1, "lf")])
+def test_step_parity_3d(name, p, flux):
+    """One FP64 PCEXP step (m = 10, CFL 5) on the 3^3 x 6 tetrahedral meshes,
+    periodic and bounded, against the oracle's step at 1e-11."""
+    g, ctx, u0 = _pair(name, p, flux, amp=1e-3)
+    dt = stable_dt(g, u0, 5.0)
+    want = pcexp_step(ExactJacobian(g), u0, dt, 10)
+    u = _t(u0)
+    ctx.step(u, dt=dt, m=10)
+    print(f"[3d step] state rel {rel(_n(u), want):.2e}, increment rel {rel(_n(u) - u0, want - u0):.2e}", flush=True)
+    assert rel(_n(u), want) < 1e-11
+    assert rel(_n(u) - u0, want - u0) < 1e-10
 
 
 def test_unphysical_flag():
