@@ -104,7 +104,7 @@ def test_step_vjp_dense(n, m, scheme):
 
 
 @pytest.mark.parametrize("name,p,flux,m", [("sq4j", 1, "roe", 8), ("sq3", 2, "lf", 10), ("chan", 1, "roe", 8),
-                                           ("cube3", 1, "roe", 6), ("cube3", 1, "lf", 6)])
+                                           ("cube3", 1, "roe", 6), ("cube3", 1, "lf", 6), ("cube3", 2, "lf", 6)])
 def test_step_vjp_dg(name, p, flux, m):
     """<ubar, D d> against Richardson differences of the oracle's step (the
     3D cases run the second-order kernel's accumulating form on tetrahedra;
