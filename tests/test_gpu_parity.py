@@ -416,15 +416,17 @@ def test_stable_dt_parity(name, p, flux):
     assert abs(ctx.stable_dt(_t(u), 3.0) - stable_dt(g, u, 3.0)) < 1e-14 * stable_dt(g, u, 3.0)
 
 
-@pytest.mark.parametrize("name,p,flux", [("cube3", 2, "lf"), ("box3", 2, "roe"), ("box3", 1, "lf")])
-def test_step_parity_3d(name, p, flux):
-    """One FP64 PCEXP step (m = 10, CFL 5) on the 3^3 x 6 tetrahedral meshes,
-    periodic and bounded, against the oracle's step at 1e-11."""
+@pytest.mark.parametrize("name,p,flux,scheme", [("cube3", 2, "lf", "pcexp"), ("box3", 2, "roe", "pcexp"),
+                                                ("box3", 1, "lf", "pcexp"), ("cube3", 2, "roe", "exp1")])
+def test_step_parity_3d(name, p, flux, scheme):
+    """One FP64 PCEXP (or EXP1) step (m = 10, CFL 5) on the 3^3 x 6
+    tetrahedral meshes, periodic and bounded, against the oracle's step at
+    1e-11."""
     g, ctx, u0 = _pair(name, p, flux, amp=1e-3)
     dt = stable_dt(g, u0, 5.0)
-    want = pcexp_step(ExactJacobian(g), u0, dt, 10)
+    want = pcexp_step(ExactJacobian(g), u0, dt, 10, scheme=scheme)
     u = _t(u0)
-    ctx.step(u, dt=dt, m=10)
+    ctx.step(u, dt=dt, m=10, scheme=scheme)
     print(f"[3d step] state rel {rel(_n(u), want):.2e}, increment rel {rel(_n(u) - u0, want - u0):.2e}", flush=True)
     assert rel(_n(u), want) < 1e-11
     assert rel(_n(u) - u0, want - u0) < 1e-10
