@@ -127,7 +127,12 @@ typedef struct {
 
 /* Create a context for a mesh and discretisation (Sec. 4.2-4.3): builds faces,
  * periodic pairing, geometry, quadrature and basis tables on the host and
- * uploads them.  Synchronises `stream`.  *out is NULL on failure. */
+ * uploads them.  Synchronises `stream`.  *out is NULL on failure.
+ * Quadrature (Sec. 4.3 asks for Gaussian rules): conical-product Gauss-Jacobi
+ * rules with p + 1 points per collapsed direction, (p+1)^dim in the volume and
+ * (p+1)^(dim-1) per face, except dim = 3, p = 2, which takes fully symmetric
+ * rules of the same degree 5 (14 points on the tetrahedron, 7 per face);
+ * pcexp_sizes reports both counts. */
 pcexp_status pcexp_create(const pcexp_mesh_desc* mesh, const pcexp_disc_desc* disc,
                           void* stream, pcexp_ctx** out);
 
