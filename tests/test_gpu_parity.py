@@ -570,10 +570,12 @@ def test_step_etd2_parity_dense():
     assert rel(_n(up), wup) < 1e-13 and rel(_n(rp), wrp) < 1e-12
 
 
-def test_step_etd2_parity_dg():
-    """Three ETD2 steps with the tangent JVP on the jittered 4x4 P2 Roe vortex."""
+@pytest.mark.parametrize("name,p,flux", [("sq4j", 2, "roe"), ("cube3", 2, "lf")])
+def test_step_etd2_parity_dg(name, p, flux):
+    """Three ETD2 steps with the tangent JVP on the jittered 4x4 P2 Roe vortex
+    and on the 3^3 x 6 tetrahedral P2 LF vortex."""
     from oracle.integrators import stable_dt
-    g, ctx, u = _pair("sq4j", 2, "roe", amp=1e-3)
+    g, ctx, u = _pair(name, p, flux, amp=1e-3)
     dt = stable_dt(g, u, 5.0)
     ud, up, rp = _t(u), _t(np.zeros_like(u)), _t(np.zeros_like(u))
     for i in range(3):
