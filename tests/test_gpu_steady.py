@@ -13,13 +13,13 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _setup(p):
+def _setup(p, name="chan"):
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     from paper_1801_06300_amd import PCEXP
-    m, _ = mesh_case("chan")
-    prim = W.freestream_prim(2, angle_deg=0.0)
-    print(f"\n[case] steady chan p={p}", flush=True)
+    m, _ = mesh_case(name)
+    prim = W.freestream_prim(m.dim, angle_deg=0.0)
+    print(f"\n[case] steady {name} p={p}", flush=True)
     g = DG(m, p, "roe", farfield_prim=prim)
     ctx = PCEXP(m, p, "roe", farfield_prim=prim)
     u = vortex_state(g, m, 1e-3)
@@ -37,6 +37,18 @@ def test_steady_iterations_parity(scheme):
     ud = _t(u)
     info = ctx.steady(ud, cfl_max=1000.0, tol=0.0, max_iter=5, check_every=1, m=30, scheme=scheme)
     want, hist = steady_iterations(g, ExactJacobian(g), u, 5, 1000.0, 30, scheme)
+    assert info["iterations"] == 5
+    assert abs(info["res_rho_norm0"] - hist[0]) < 1e-12 * hist[0]
+    assert rel(ud.cpu().numpy(), want) < 1e-10
+
+
+def test_steady_iterations_parity_3d():
+    """Five ramped iterations on the bounded 3^3 x 6 tetrahedral box (slip
+    walls, far field at both ends), P1 Roe, m = 10, equal the oracle's."""
+    g, ctx, u = _setup(1, "box3")
+    ud = _t(u)
+    info = ctx.steady(ud, cfl_max=1000.0, tol=0.0, max_iter=5, check_every=1, m=10)
+    want, hist = steady_iterations(g, ExactJacobian(g), u, 5, 1000.0, 10)
     assert info["iterations"] == 5
     assert abs(info["res_rho_norm0"] - hist[0]) < 1e-12 * hist[0]
     assert rel(ud.cpu().numpy(), want) < 1e-10
